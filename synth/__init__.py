@@ -1,0 +1,207 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle.
+
+The paper benchmarks its neighbourhood-graph step on the PCA embeddings of
+public 10x / CELLxGENE datasets (Performance and reproducibility; Methods,
+Benchmarking).  Those datasets are not available here, so every workload is
+a seeded Gaussian mixture with the shape of such an embedding: ``d`` PCA
+components whose variances fall off as ``1/i`` (a PCA spectrum), cells
+grouped around cluster centres.
+
+This module only draws random numbers.  It holds none of the arithmetic of
+the method (no distances, no selection, no smoothing), so that both the HIP
+path and the CPU oracle can take their inputs from it without sharing code.
+
+Recipe (fixed here so that every consumer draws the same data):
+
+* ``numpy.random.Generator(PCG64(seed))``;
+* draw order: centres ``C x d`` from ``N(0, 25 I)`` (standard deviation 5),
+  then the cluster label of every cell, then the within-cluster noise
+  ``N(0, diag(lambda))`` with ``lambda_i = 1/i`` for ``i = 1..d``;
+* cluster weights are either uniform or the finite rank-Zipf law
+  ``p_m ~ m^-s`` for ``m = 1..C``;
+* ``X = centres[label] + noise`` is formed in float64 and rounded once to
+  float32 (round to nearest even).
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+__all__ = [
+    "MixtureSpec",
+    "cluster_weights",
+    "draw_centres",
+    "mixture",
+    "mixture_from_centres",
+    "batched_sizes",
+    "batched_samples",
+    "WORKLOADS",
+    "workload",
+    "sample_rows",
+    "lattice_1d",
+    "random_knn_lists",
+]
+
+_CHUNK = 1 << 18  # rows drawn per call; the PCG64 stream is identical to one big draw
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def cluster_weights(n_clusters: int, law: str = "uniform", zipf_s: float = 1.1) -> np.ndarray:
+    """Mixture weights: ``uniform`` or rank-Zipf ``p_m ~ m**-zipf_s``."""
+    if n_clusters < 1:
+        raise ValueError("n_clusters must be >= 1")
+    if law == "uniform":
+        p = np.full(n_clusters, 1.0 / n_clusters)
+    elif law == "zipf":
+        p = np.arange(1, n_clusters + 1, dtype=np.float64) ** (-zipf_s)
+        p /= p.sum()
+    else:
+        raise ValueError(f"unknown cluster law {law!r}")
+    return p
+
+
+def draw_centres(rng: np.random.Generator, n_clusters: int, d: int, centre_sd: float = 5.0) -> np.ndarray:
+    return rng.standard_normal((n_clusters, d)) * centre_sd
+
+
+def _noise_scale(d: int) -> np.ndarray:
+    lam = 1.0 / np.arange(1, d + 1, dtype=np.float64)
+    return np.sqrt(lam)
+
+
+def mixture_from_centres(rng: np.random.Generator, centres: np.ndarray, n: int,
+                         weights: np.ndarray, return_labels: bool = False):
+    """Draw ``n`` cells around given ``centres`` (labels first, then noise)."""
+    c, d = centres.shape
+    labels = rng.choice(c, size=n, p=weights)
+    scale = _noise_scale(d)
+    out = np.empty((n, d), dtype=np.float32)
+    for s in range(0, n, _CHUNK):
+        e = min(n, s + _CHUNK)
+        noise = rng.standard_normal((e - s, d)) * scale
+        out[s:e] = (centres[labels[s:e]] + noise).astype(np.float32)
+    if return_labels:
+        return out, labels
+    return out
+
+
+@dataclass(frozen=True)
+class MixtureSpec:
+    n: int
+    d: int = 50
+    n_clusters: int = 20
+    law: str = "uniform"
+    seed: int = 0
+
+
+def mixture(n: int, d: int = 50, n_clusters: int = 20, law: str = "uniform", seed: int = 0,
+            return_labels: bool = False):
+    """One seeded Gaussian-mixture embedding, ``n x d`` float32, C-contiguous."""
+    rng = _rng(seed)
+    centres = draw_centres(rng, n_clusters, d)
+    return mixture_from_centres(rng, centres, n, cluster_weights(n_clusters, law), return_labels)
+
+
+def batched_sizes(n_samples: int = 64, lo: int = 2000, hi: int = 200000, seed: int = 4) -> np.ndarray:
+    """Sample sizes log-uniform in ``[lo, hi]`` (rounded to integers)."""
+    rng = _rng(seed)
+    u = rng.uniform(math.log(lo), math.log(hi), size=n_samples)
+    return np.rint(np.exp(u)).astype(np.int64)
+
+
+def batched_samples(n_samples: int = 64, lo: int = 2000, hi: int = 200000, d: int = 50, seed: int = 4):
+    """Concatenated independent samples plus their ``int64`` offsets (``S+1``).
+
+    Sample ``s`` has its own seed ``1000 + s`` and ``C_s ~ U{10..40}`` uniform
+    clusters, drawn from that sample's generator before its centres.
+    """
+    sizes = batched_sizes(n_samples, lo, hi, seed)
+    offsets = np.zeros(n_samples + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum(sizes)
+    X = np.empty((int(offsets[-1]), d), dtype=np.float32)
+    for s in range(n_samples):
+        rng = _rng(1000 + s)
+        c = int(rng.integers(10, 41))
+        centres = draw_centres(rng, c, d)
+        X[offsets[s]:offsets[s + 1]] = mixture_from_centres(rng, centres, int(sizes[s]), cluster_weights(c))
+    return X, offsets
+
+
+# The paper's benchmark scales, as synthetic stand-ins (d = 50 PCA components, k = 15).
+WORKLOADS = {
+    "plain_10k": MixtureSpec(n=10_000, n_clusters=20, law="uniform", seed=0),
+    "plain_1m": MixtureSpec(n=1_000_000, n_clusters=100, law="zipf", seed=1),
+    "precision_2m": MixtureSpec(n=2_000_000, n_clusters=100, law="zipf", seed=2),
+}
+
+
+def workload(name: str, n: int | None = None) -> np.ndarray:
+    """Embedding of a named workload; ``n`` overrides the size (same recipe)."""
+    spec = WORKLOADS[name]
+    return mixture(n if n is not None else spec.n, spec.d, spec.n_clusters, spec.law, spec.seed)
+
+
+def sample_rows(n: int, count: int, seed: int) -> np.ndarray:
+    """A sorted seeded sample of distinct row ids (for sampled parity checks)."""
+    rng = _rng(seed)
+    count = min(count, n)
+    return np.sort(rng.choice(n, size=count, replace=False)).astype(np.int64)
+
+
+def lattice_1d(n: int, d: int = 1, spacing: float = 1.0) -> np.ndarray:
+    """Points ``i * spacing`` on the first axis (other axes zero): exact ties."""
+    X = np.zeros((n, d), dtype=np.float32)
+    X[:, 0] = np.arange(n, dtype=np.float32) * np.float32(spacing)
+    return X
+
+
+def random_knn_lists(n: int, k: int, seed: int, hub_fraction: float = 0.01):
+    """Synthetic kNN-shaped lists (``idx`` int32, ``dist`` float32, self at slot 0).
+
+    Neighbours are distinct, never the row itself; a small set of hub rows is
+    over-represented so that some rows receive many reverse edges.  Distances
+    are positive and non-decreasing along each row.  Used to exercise the
+    graph stage at sizes where a brute-force kNN on the CPU would be too slow.
+    """
+    if k < 1 or n < k:
+        raise ValueError("need 1 <= k <= n")
+    rng = _rng(seed)
+    idx = np.empty((n, k), dtype=np.int64)
+    idx[:, 0] = np.arange(n)
+    if k > 1:
+        m = 3 * k + 8
+        n_hub = max(1, int(n * hub_fraction))
+        hubs = rng.choice(n, size=n_hub, replace=False)
+        cand = rng.integers(0, n, size=(n, m))
+        use_hub = rng.random((n, m)) < 0.3
+        cand = np.where(use_hub, hubs[rng.integers(0, n_hub, size=(n, m))], cand)
+        cand[cand == np.arange(n)[:, None]] = -1
+        cand.sort(axis=1)
+        bad = cand < 0
+        bad[:, 1:] |= cand[:, 1:] == cand[:, :-1]
+        keys = rng.random((n, m))
+        keys[bad] = 2.0
+        order = np.argsort(keys, axis=1, kind="stable")
+        cand = np.take_along_axis(cand, order, axis=1)
+        short = np.nonzero((~bad).sum(axis=1) < k - 1)[0]
+        for i in short:  # rare: not enough distinct draws, fill deterministically
+            row = [int(v) for v in cand[i] if v >= 0]
+            row = list(dict.fromkeys(row))
+            j = (i + 1) % n
+            while len(row) < k - 1:
+                if j != i and j not in row:
+                    row.append(j)
+                j = (j + 1) % n
+            cand[i, : k - 1] = row[: k - 1]
+        idx[:, 1:] = cand[:, : k - 1]
+    gaps = rng.exponential(1.0, size=(n, k)).astype(np.float64)
+    gaps[:, 0] = 0.0
+    dist = np.cumsum(gaps, axis=1)
+    dist[:, 1:] += 0.5
+    return idx.astype(np.int32), dist.astype(np.float32)
