@@ -1,0 +1,94 @@
+"""ctypes binding of ``librsc.so`` (argument marshalling only).
+
+Every call takes torch tensors that live on the current HIP device and
+enqueues the library's kernels on torch's current stream.  Nothing here
+computes: there is no CPU fallback, and importing this module on a machine
+without the built library raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librsc.so")
+
+RSC_OK = 0
+STATUS_NAMES = {
+    0: "RSC_OK",
+    -1: "RSC_ERR_INVALID_ARG",
+    -2: "RSC_ERR_HIP",
+    -3: "RSC_ERR_NO_MEMORY",
+    -4: "RSC_ERR_CAPACITY",
+    -5: "RSC_ERR_OVERFLOW",
+    -6: "RSC_ERR_UNSUPPORTED",
+    -7: "RSC_ERR_WORKSPACE",
+    -8: "RSC_ERR_BAD_GRAPH",
+}
+RSC_FP32, RSC_BF16, RSC_FP8_E4M3 = 0, 1, 2
+
+# Every symbol include/rsc.h declares, with (restype, argtypes).
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+_SZ = ctypes.c_size_t
+
+
+class KnnOpts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("screen", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("reserved1", ctypes.c_int32)]
+
+
+class KnnStats(ctypes.Structure):
+    _fields_ = [("rescanned_rows", ctypes.c_int64), ("max_err_ratio", ctypes.c_float),
+                ("max_ref_norm", ctypes.c_float)]
+
+
+SIGNATURES = {
+    "rsc_abi_version": (ctypes.c_int, []),
+    "rsc_last_error": (ctypes.c_char_p, []),
+    "rsc_knn_workspace_bytes": (_SZ, [_I64, _I64, _I32, _I32, _P]),
+    "rsc_knn": (ctypes.c_int, [_P, _I64, _I32, _I32, _P, _P, _P, _SZ, _P]),
+    "rsc_knn_ex": (ctypes.c_int, [_P, _I64, _P, _I64, _I32, _I32, _P, _P, _P, _P, _SZ, _P]),
+    "rsc_knn_read_stats": (ctypes.c_int, [_P, _SZ, _P, _P]),
+    "rsc_connectivities_workspace_bytes": (_SZ, [_I64, _I32]),
+    "rsc_connectivities": (ctypes.c_int, [_P, _P, _I64, _I32, _P, _P, _P, _I64, _P, _P, _P, _P, _SZ, _P]),
+    "rsc_profile_enable": (ctypes.c_int, [ctypes.c_int]),
+    "rsc_profile_reset": (ctypes.c_int, []),
+    "rsc_profile_get": (ctypes.c_int, [ctypes.c_char_p, _P, _P]),
+}
+
+_lock = threading.Lock()
+_lib = None
+
+
+class RscError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+
+
+def load(path: str = LIB_PATH):
+    """Load the library (once).  Raises if it has not been built."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(path):
+                raise ImportError(
+                    f"{path} is missing: build it with `python -m paper_2603_02402_amd.build` "
+                    "(the kNN graph has no CPU fallback)")
+            lib = ctypes.CDLL(path)
+            for name, (res, args) in SIGNATURES.items():
+                fn = getattr(lib, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = lib
+    return _lib
+
+
+def check(status: int) -> None:
+    if status != RSC_OK:
+        msg = load().rsc_last_error()
+        raise RscError(status, msg.decode() if msg else "")

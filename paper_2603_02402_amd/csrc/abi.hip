@@ -1,0 +1,248 @@
+// Exported C ABI: argument validation, workspace sizing, error state and
+// optional kernel timing.  Everything numeric happens in knn.hip and
+// graph.hip; this file only checks and dispatches.
+
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "rsc_internal.hpp"
+
+namespace rsc {
+
+namespace {
+thread_local std::string g_error;
+
+struct ProfileEntry {
+    const char *name;
+    hipEvent_t start, stop;
+};
+
+struct Profiler {
+    std::mutex mu;
+    bool enabled = false;
+    std::vector<ProfileEntry> pending;
+    std::vector<hipEvent_t> free_events;
+    std::map<std::string, std::pair<double, int64_t>> totals;
+
+    hipEvent_t take_event() {
+        if (!free_events.empty()) {
+            hipEvent_t e = free_events.back();
+            free_events.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    // Resolve recorded pairs into totals (waits for them).
+    void drain() {
+        for (auto &p : pending) {
+            float ms = 0.f;
+            if (hipEventSynchronize(p.stop) == hipSuccess && hipEventElapsedTime(&ms, p.start, p.stop) == hipSuccess) {
+                auto &t = totals[p.name];
+                t.first += ms;
+                t.second += 1;
+            }
+            free_events.push_back(p.start);
+            free_events.push_back(p.stop);
+        }
+        pending.clear();
+    }
+};
+
+Profiler &profiler() {
+    static Profiler *p = new Profiler();  // leaked on purpose: outlives static destructors
+    return *p;
+}
+}  // namespace
+
+void set_error(const std::string &msg) { g_error = msg; }
+void clear_error() { g_error.clear(); }
+
+int hip_status(hipError_t e, const char *what) {
+    if (e == hipSuccess) return RSC_OK;
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return RSC_ERR_HIP;
+}
+
+int launch_status(const char *what) { return hip_status(hipGetLastError(), what); }
+
+ScopedTimer::ScopedTimer(const char *name, hipStream_t stream) : name_(name), stream_(stream), start_(nullptr) {
+    Profiler &p = profiler();
+    std::lock_guard<std::mutex> lock(p.mu);
+    if (!p.enabled) return;
+    hipEvent_t e = p.take_event();
+    if (e && hipEventRecord(e, stream) == hipSuccess) start_ = e;
+}
+
+ScopedTimer::~ScopedTimer() {
+    if (!start_) return;
+    Profiler &p = profiler();
+    std::lock_guard<std::mutex> lock(p.mu);
+    hipEvent_t e = p.take_event();
+    if (e && hipEventRecord(e, stream_) == hipSuccess)
+        p.pending.push_back({name_, static_cast<hipEvent_t>(start_), e});
+}
+
+}  // namespace rsc
+
+using namespace rsc;
+
+namespace {
+
+bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+int check_ws(void *ws, size_t have, size_t need) {
+    if (need > have) {
+        set_error("workspace too small: need " + std::to_string(need) + " bytes, got " + std::to_string(have));
+        return RSC_ERR_WORKSPACE;
+    }
+    if (!ws || !aligned(ws, 256)) {
+        set_error("workspace must be a non-null, 256-byte aligned device pointer");
+        return RSC_ERR_WORKSPACE;
+    }
+    return RSC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rsc_abi_version(void) { return RSC_ABI_VERSION; }
+
+const char *rsc_last_error(void) { return g_error.c_str(); }
+
+size_t rsc_knn_workspace_bytes(int64_t n_query, int64_t n_ref, int32_t d, int32_t k, const rsc_knn_opts *opts) {
+    KnnPlan p;
+    if (knn_plan(n_query, n_ref, d, k, opts, false, &p) != RSC_OK) return 0;
+    return knn_workspace(p, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+}
+
+static int knn_common(const float *Q, int64_t nq, const float *R, int64_t nr, int32_t d, int32_t k,
+                      const rsc_knn_opts *opts, bool self_mode, int32_t *out_idx, float *out_dist, void *ws,
+                      size_t ws_bytes, void *stream) {
+    clear_error();
+    KnnPlan p;
+    int st = knn_plan(nq, nr, d, k, opts, self_mode, &p);
+    if (st != RSC_OK) return st;
+    if (!R || (nq > 0 && (!Q || !out_idx || !out_dist))) {
+        set_error("null device pointer");
+        return RSC_ERR_INVALID_ARG;
+    }
+    if (!aligned(Q, 4) || !aligned(R, 4) || !aligned(out_idx, 4) || !aligned(out_dist, 4)) {
+        set_error("arrays must be 4-byte aligned");
+        return RSC_ERR_INVALID_ARG;
+    }
+    if ((st = check_ws(ws, ws_bytes, knn_workspace(p, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr))) !=
+        RSC_OK)
+        return st;
+    return knn_run(p, Q, R, out_idx, out_dist, ws, static_cast<hipStream_t>(stream));
+}
+
+int rsc_knn(const float *X, int64_t n, int32_t d, int32_t k, int32_t *out_idx, float *out_dist, void *workspace,
+            size_t workspace_bytes, void *stream) {
+    return knn_common(X, n, X, n, d, k, nullptr, true, out_idx, out_dist, workspace, workspace_bytes, stream);
+}
+
+int rsc_knn_ex(const float *Q, int64_t n_query, const float *R, int64_t n_ref, int32_t d, int32_t k,
+               const rsc_knn_opts *opts, int32_t *out_idx, float *out_dist, void *workspace, size_t workspace_bytes,
+               void *stream) {
+    return knn_common(Q, n_query, R, n_ref, d, k, opts, false, out_idx, out_dist, workspace, workspace_bytes,
+                      stream);
+}
+
+int rsc_knn_read_stats(const void *workspace, size_t workspace_bytes, rsc_knn_stats *out, void *stream) {
+    clear_error();
+    if (!workspace || !out || workspace_bytes < sizeof(KnnCounters)) {
+        set_error("need a kNN workspace and an output struct");
+        return RSC_ERR_INVALID_ARG;
+    }
+    KnnCounters c;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int st = hip_status(hipMemcpyAsync(&c, workspace, sizeof(c), hipMemcpyDeviceToHost, s), "read stats");
+    if (st != RSC_OK) return st;
+    if ((st = hip_status(hipStreamSynchronize(s), "synchronise")) != RSC_OK) return st;
+    out->rescanned_rows = c.flagged;
+    uint32_t rb = c.max_ratio_bits, nb = c.max_norm_bits;
+    std::memcpy(&out->max_err_ratio, &rb, 4);
+    std::memcpy(&out->max_ref_norm, &nb, 4);
+    return RSC_OK;
+}
+
+size_t rsc_connectivities_workspace_bytes(int64_t n, int32_t k) {
+    if (n < 1 || k < 1 || k > n || n > INT32_MAX - 1) return 0;
+    return graph_workspace_bytes(n, k);
+}
+
+int rsc_connectivities(const int32_t *idx, const float *dist, int64_t n, int32_t k, int64_t *indptr,
+                       int32_t *indices, float *data, int64_t cap, int64_t *nnz, double *rho, double *sigma,
+                       void *workspace, size_t workspace_bytes, void *stream) {
+    clear_error();
+    if (n < 1 || k < 1 || k > n) {
+        set_error("need n >= 1 and 1 <= k <= n");
+        return RSC_ERR_INVALID_ARG;
+    }
+    if (n > INT32_MAX - 1) {
+        set_error("n above 2^31-2 cannot be indexed by int32");
+        return RSC_ERR_OVERFLOW;
+    }
+    if (k > 65) {
+        set_error("k > 65 is not supported by this build");
+        return RSC_ERR_UNSUPPORTED;
+    }
+    if (!idx || !dist || !indptr || !nnz || (k > 1 && (!indices || !data))) {
+        set_error("null pointer");
+        return RSC_ERR_INVALID_ARG;
+    }
+    if (!aligned(idx, 4) || !aligned(dist, 4) || !aligned(indptr, 8) || !aligned(indices, 4) ||
+        !aligned(data, 4) || !aligned(rho, 8) || !aligned(sigma, 8)) {
+        set_error("misaligned array");
+        return RSC_ERR_INVALID_ARG;
+    }
+    const int64_t need = 2 * n * (int64_t)(k - 1);
+    if (cap < need) {
+        set_error("CSR capacity must be at least 2 n (k-1) = " + std::to_string(need));
+        return RSC_ERR_CAPACITY;
+    }
+    int st = check_ws(workspace, workspace_bytes, graph_workspace_bytes(n, k));
+    if (st != RSC_OK) return st;
+    return graph_run(idx, dist, n, k, indptr, indices, data, cap, nnz, rho, sigma, workspace,
+                     static_cast<hipStream_t>(stream));
+}
+
+int rsc_profile_enable(int enable) {
+    Profiler &p = profiler();
+    std::lock_guard<std::mutex> lock(p.mu);
+    p.enabled = enable != 0;
+    return RSC_OK;
+}
+
+int rsc_profile_reset(void) {
+    Profiler &p = profiler();
+    std::lock_guard<std::mutex> lock(p.mu);
+    p.drain();
+    p.totals.clear();
+    return RSC_OK;
+}
+
+int rsc_profile_get(const char *name, double *total_ms, int64_t *launches) {
+    clear_error();
+    if (!name || !total_ms || !launches) {
+        set_error("null argument");
+        return RSC_ERR_INVALID_ARG;
+    }
+    Profiler &p = profiler();
+    std::lock_guard<std::mutex> lock(p.mu);
+    p.drain();
+    auto it = p.totals.find(name);
+    *total_ms = it == p.totals.end() ? 0.0 : it->second.first;
+    *launches = it == p.totals.end() ? 0 : it->second.second;
+    return RSC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,85 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/rsc.h"
+
+namespace rsc {
+
+// Thread-local error message behind rsc_last_error().
+void set_error(const std::string &msg);
+void clear_error();
+
+// Record a HIP failure (if any) and turn it into RSC_ERR_HIP.
+int hip_status(hipError_t e, const char *what);
+// Check the last launch error.
+int launch_status(const char *what);
+
+// Optional per-kernel event timing (rsc_profile_*).  When enabled, a
+// ScopedTimer records one event before and one after the launches made in
+// its scope on `stream` and files the pair under `name`.
+class ScopedTimer {
+  public:
+    ScopedTimer(const char *name, hipStream_t stream);
+    ~ScopedTimer();
+    ScopedTimer(const ScopedTimer &) = delete;
+    ScopedTimer &operator=(const ScopedTimer &) = delete;
+
+  private:
+    const char *name_;
+    hipStream_t stream_;
+    void *start_;
+};
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+// Carves 256-byte aligned sub-buffers out of a workspace, or only counts.
+struct Carver {
+    char *base;
+    size_t used = 0;
+    explicit Carver(void *b) : base(static_cast<char *>(b)) {}
+    template <class T>
+    T *take(size_t count) {
+        size_t off = used;
+        used = align_up(used + count * sizeof(T));
+        return base ? reinterpret_cast<T *>(base + off) : nullptr;
+    }
+};
+
+// ---- kNN stages (knn.hip) -------------------------------------------------
+
+// Device counters of one kNN call, at the start of the workspace.
+struct KnnCounters {
+    int32_t flagged;          // rows whose certificate failed
+    uint32_t max_ratio_bits;  // float bits of the largest error ratio seen
+    uint32_t max_norm_bits;   // float bits of max_j ||y_j||
+    int32_t pad;
+};
+
+struct KnnPlan {
+    int64_t nq, nr;
+    int d, k, screen, kp;  // kp: heap capacity (32 or 64)
+    int dh;                // half of the padded contraction length
+    bool self_mode;        // queries are the references (self forced to slot 0)
+};
+
+// Fill a plan; returns RSC_OK or an error status (with message set).
+int knn_plan(int64_t nq, int64_t nr, int d, int k, const rsc_knn_opts *opts, bool self_mode, KnnPlan *plan);
+size_t knn_workspace(const KnnPlan &p, void *ws, KnnCounters **counters, float **norms, int32_t **cand_idx,
+                     float **cand_key, int32_t **flag_list);
+int knn_run(const KnnPlan &p, const float *Q, const float *R, int32_t *out_idx, float *out_dist, void *ws,
+            hipStream_t stream);
+
+// ---- graph stages (graph.hip) --------------------------------------------
+
+size_t graph_workspace_bytes(int64_t n, int k);
+int graph_run(const int32_t *idx, const float *dist, int64_t n, int k, int64_t *indptr, int32_t *indices,
+              float *data, int64_t cap, int64_t *nnz, double *rho, double *sigma, void *ws, hipStream_t stream);
+
+}  // namespace rsc

@@ -1,0 +1,153 @@
+"""The C ABI library loads, exports what include/rsc.h declares, and validates
+arguments on the host (no GPU needed: every case here fails validation
+before anything is enqueued)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rsc.h")
+LIB = os.path.join(ROOT, "paper_2603_02402_amd", "librsc.so")
+
+FAKE = ctypes.c_void_p(0x10000)  # never dereferenced: validation fails first
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(rsc_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        import paper_2603_02402_amd.build as b
+
+        b.build()
+    from paper_2603_02402_amd import _lib
+
+    return _lib.load(LIB)
+
+
+def test_header_declares_the_calls():
+    names = declared_functions()
+    for n in ["rsc_knn", "rsc_knn_ex", "rsc_connectivities", "rsc_knn_workspace_bytes",
+              "rsc_connectivities_workspace_bytes", "rsc_last_error", "rsc_abi_version"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_2603_02402_amd import _lib
+
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+        assert name in _lib.SIGNATURES, f"binding lacks {name}"
+
+
+def test_abi_version(lib):
+    assert lib.rsc_abi_version() == 1
+
+
+def test_workspace_sizes(lib):
+    from paper_2603_02402_amd import _lib
+
+    o = _lib.KnnOpts(0, 0, 0, 0)
+    n, d, k = 10000, 50, 15
+    ws = lib.rsc_knn_workspace_bytes(n, n, d, k, ctypes.byref(o))
+    # counters + norms + candidates (idx + key, width 32) + flag list
+    assert ws >= n * 4 + 2 * n * 32 * 4 + n * 4
+    assert ws % 256 == 0
+    assert lib.rsc_knn_workspace_bytes(n, n, d, 0, None) == 0
+    assert lib.rsc_knn_workspace_bytes(n, n, 0, k, None) == 0
+    assert lib.rsc_knn_workspace_bytes(5, 5, d, 6, None) == 0
+    g = lib.rsc_connectivities_workspace_bytes(n, k)
+    assert g >= n * (k - 1) * (8 + 4 + 1) + 2 * n * (k - 1) * 8
+    assert lib.rsc_connectivities_workspace_bytes(0, k) == 0
+
+
+def _knn(lib, n=100, d=50, k=15, X=FAKE, idx=FAKE, dist=FAKE, ws=FAKE, ws_bytes=1 << 30):
+    return lib.rsc_knn(X, n, d, k, idx, dist, ws, ws_bytes, None)
+
+
+def _err(lib):
+    return lib.rsc_last_error().decode()
+
+
+def test_knn_validation(lib):
+    assert _knn(lib, k=0) == -1
+    assert _knn(lib, k=101) == -1
+    assert _knn(lib, d=0) == -1
+    assert _knn(lib, n=0) == -1
+    assert _knn(lib, n=2**31) == -5 and "int32" in _err(lib)
+    assert _knn(lib, d=129) == -6
+    assert _knn(lib, k=64) == -6
+    assert _knn(lib, X=None) == -1
+    assert _knn(lib, idx=None) == -1
+    assert _knn(lib, X=ctypes.c_void_p(0x10002)) == -1 and "aligned" in _err(lib)
+    assert _knn(lib, ws=None) == -7
+    assert _knn(lib, ws=ctypes.c_void_p(0x10080)) == -7
+    assert _knn(lib, ws_bytes=1000) == -7 and "too small" in _err(lib)
+
+
+def test_knn_ex_validation(lib):
+    from paper_2603_02402_amd import _lib
+
+    def call(nq=10, nr=100, d=50, k=15, opts=None):
+        return lib.rsc_knn_ex(FAKE, nq, FAKE, nr, d, k, opts, FAKE, FAKE, FAKE, 1 << 30, None)
+
+    assert call(k=101) == -1
+    bad = _lib.KnnOpts(7, 0, 0, 0)
+    assert call(opts=ctypes.byref(bad)) == -1
+    narrow = _lib.KnnOpts(0, 15, 0, 0)
+    assert call(opts=ctypes.byref(narrow)) == -1 and "screen" in _err(lib)
+    wide = _lib.KnnOpts(0, 65, 0, 0)
+    assert call(opts=ctypes.byref(wide)) == -1
+
+
+def test_connectivities_validation(lib):
+    nnz = ctypes.c_int64(0)
+
+    def call(n=100, k=15, cap=None, ws_bytes=1 << 30, idx=FAKE, nnz_p=ctypes.byref(nnz)):
+        cap = 2 * n * (k - 1) if cap is None else cap
+        return lib.rsc_connectivities(idx, FAKE, n, k, FAKE, FAKE, FAKE, cap, nnz_p, None, None, FAKE, ws_bytes,
+                                      None)
+
+    assert call(k=0) == -1
+    assert call(k=101) == -1
+    assert call(n=2**31) == -5
+    assert call(cap=2 * 100 * 14 - 1) == -4 and "capacity" in _err(lib)
+    assert call(ws_bytes=100) == -7
+    assert call(idx=None) == -1
+    assert call(nnz_p=None) == -1
+
+
+def test_error_is_thread_local_and_cleared(lib):
+    assert _knn(lib, k=0) == -1
+    assert _err(lib) != ""
+    assert lib.rsc_knn_workspace_bytes(10, 10, 5, 3, None) > 0
+
+
+def test_profile_calls_without_gpu(lib):
+    assert lib.rsc_profile_enable(0) == 0
+    assert lib.rsc_profile_reset() == 0
+    ms = ctypes.c_double(-1)
+    cnt = ctypes.c_int64(-1)
+    assert lib.rsc_profile_get(b"screen_fp32", ctypes.byref(ms), ctypes.byref(cnt)) == 0
+    assert ms.value == 0.0 and cnt.value == 0
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    from paper_2603_02402_amd import _lib
+
+    with pytest.raises(ImportError):
+        _lib.load.__wrapped__ if hasattr(_lib.load, "__wrapped__") else None
+        saved = _lib._lib
+        try:
+            _lib._lib = None
+            _lib.load(str(tmp_path / "missing.so"))
+        finally:
+            _lib._lib = saved
