@@ -53,7 +53,7 @@ def cpu_baseline(X: np.ndarray, k: int, budget_s: float) -> dict:
     cores = oracle.max_threads()
     n = X.shape[0]
     # calibrate on a few rows, then size the sample to the time budget
-    probe = synth.sample_rows(n, max(cores, 8), seed=7)
+    probe = synth.sample_rows(n, max(64, 8 * cores), seed=7)
     t0 = time.perf_counter()
     oracle.knn_rows(X, probe, k)
     per_row = (time.perf_counter() - t0) / len(probe)
@@ -142,8 +142,8 @@ def main() -> int:
     value = n / (ms_per_step / 1e3)
 
     kernels = {}
-    for name in ["prep_norms", "screen_fp32", "rerank", "rescan", "graph_init", "smooth_knn", "union_count",
-                 "csr_scan", "union_fill", "row_sort"]:
+    for name in ["prep_pack", "screen_fp32", "rerank", "screen_escalate", "rerank_escalate", "rescan", "graph_init",
+                 "smooth_knn", "union_count", "csr_scan", "union_fill", "row_sort"]:
         tot, cnt = rsc.profile_get(name)
         if cnt:
             kernels[name] = round(tot / cnt, 4)
@@ -176,7 +176,8 @@ def main() -> int:
         "dtype": "fp32",
         "data": "synthetic",
         "config": {"workload": w["desc"], "form": "plain exact (FP32 MFMA screen, FP64 rerank + certificate)",
-                   "n": n, "d": d, "k": k, "nnz": int(g.nnz), "rescanned_rows": stats["rescanned_rows"],
+                   "n": n, "d": d, "k": k, "nnz": int(g.nnz), "escalated_rows": stats["escalated_rows"],
+                   "rescanned_rows": stats["rescanned_rows"],
                    "max_err_ratio": round(stats["max_err_ratio"], 4)},
         "kernel_ms": kernels,
         "roofline": roofline,

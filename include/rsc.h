@@ -92,7 +92,8 @@ typedef struct {
 
 /* Counters a kNN call leaves in its workspace (read with rsc_knn_read_stats). */
 typedef struct {
-    int64_t rescanned_rows; /* rows whose certificate failed and were recomputed exactly */
+    int64_t escalated_rows; /* rows the first screen could not certify (screened again, wider) */
+    int64_t rescanned_rows; /* rows no screen could certify (recomputed exhaustively in float64) */
     float max_err_ratio;    /* largest |screened key - exact key| / certificate bound seen */
     float max_ref_norm;     /* max_j ||y_j|| over the references, float32 */
 } rsc_knn_stats;

@@ -123,7 +123,8 @@ def read_knn_stats(workspace: Workspace) -> dict:
     s = KnnStats()
     ws = workspace.buf
     check(load().rsc_knn_read_stats(_ptr(ws), ws.numel(), ctypes.byref(s), _stream()))
-    return {"rescanned_rows": int(s.rescanned_rows), "max_err_ratio": float(s.max_err_ratio),
+    return {"escalated_rows": int(s.escalated_rows), "rescanned_rows": int(s.rescanned_rows),
+            "max_err_ratio": float(s.max_err_ratio),
             "max_ref_norm": float(s.max_ref_norm)}
 
 

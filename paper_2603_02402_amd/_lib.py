@@ -42,7 +42,8 @@ class KnnOpts(ctypes.Structure):
 
 
 class KnnStats(ctypes.Structure):
-    _fields_ = [("rescanned_rows", ctypes.c_int64), ("max_err_ratio", ctypes.c_float),
+    _fields_ = [("escalated_rows", ctypes.c_int64), ("rescanned_rows", ctypes.c_int64),
+                ("max_err_ratio", ctypes.c_float),
                 ("max_ref_norm", ctypes.c_float)]
 
 

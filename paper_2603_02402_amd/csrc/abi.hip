@@ -120,7 +120,7 @@ const char *rsc_last_error(void) { return g_error.c_str(); }
 size_t rsc_knn_workspace_bytes(int64_t n_query, int64_t n_ref, int32_t d, int32_t k, const rsc_knn_opts *opts) {
     KnnPlan p;
     if (knn_plan(n_query, n_ref, d, k, opts, false, &p) != RSC_OK) return 0;
-    return knn_workspace(p, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+    return knn_workspace(p, nullptr, nullptr);
 }
 
 static int knn_common(const float *Q, int64_t nq, const float *R, int64_t nr, int32_t d, int32_t k,
@@ -138,8 +138,7 @@ static int knn_common(const float *Q, int64_t nq, const float *R, int64_t nr, in
         set_error("arrays must be 4-byte aligned");
         return RSC_ERR_INVALID_ARG;
     }
-    if ((st = check_ws(ws, ws_bytes, knn_workspace(p, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr))) !=
-        RSC_OK)
+    if ((st = check_ws(ws, ws_bytes, knn_workspace(p, nullptr, nullptr))) != RSC_OK)
         return st;
     return knn_run(p, Q, R, out_idx, out_dist, ws, static_cast<hipStream_t>(stream));
 }
@@ -167,7 +166,8 @@ int rsc_knn_read_stats(const void *workspace, size_t workspace_bytes, rsc_knn_st
     int st = hip_status(hipMemcpyAsync(&c, workspace, sizeof(c), hipMemcpyDeviceToHost, s), "read stats");
     if (st != RSC_OK) return st;
     if ((st = hip_status(hipStreamSynchronize(s), "synchronise")) != RSC_OK) return st;
-    out->rescanned_rows = c.flagged;
+    out->escalated_rows = c.flagged;
+    out->rescanned_rows = c.rescanned;
     uint32_t rb = c.max_ratio_bits, nb = c.max_norm_bits;
     std::memcpy(&out->max_err_ratio, &rb, 4);
     std::memcpy(&out->max_ref_norm, &nb, 4);

@@ -56,10 +56,12 @@ struct Carver {
 
 // Device counters of one kNN call, at the start of the workspace.
 struct KnnCounters {
-    int32_t flagged;          // rows whose certificate failed
+    int32_t flagged;          // rows whose first certificate failed (escalated)
     uint32_t max_ratio_bits;  // float bits of the largest error ratio seen
     uint32_t max_norm_bits;   // float bits of max_j ||y_j||
-    int32_t pad;
+    int32_t flagged2;         // escalated rows whose second certificate failed
+    int32_t rescanned;        // rows recomputed exhaustively
+    int32_t pad[3];
 };
 
 struct KnnPlan {
@@ -67,12 +69,24 @@ struct KnnPlan {
     int d, k, screen, kp;  // kp: heap capacity (32 or 64)
     int dh;                // half of the padded contraction length
     bool self_mode;        // queries are the references (self forced to slot 0)
+    int64_t nblk;          // 32-row reference blocks
+    int splits;            // reference ranges of the main screen
+};
+
+struct KnnBuffers {
+    KnnCounters *counters;
+    float *packed, *norms;
+    int32_t *cand_idx;
+    float *cand_key;
+    int32_t *flag1, *flag2;
+    int32_t *esc_idx;
+    float *esc_key;
 };
 
 // Fill a plan; returns RSC_OK or an error status (with message set).
 int knn_plan(int64_t nq, int64_t nr, int d, int k, const rsc_knn_opts *opts, bool self_mode, KnnPlan *plan);
-size_t knn_workspace(const KnnPlan &p, void *ws, KnnCounters **counters, float **norms, int32_t **cand_idx,
-                     float **cand_key, int32_t **flag_list);
+// Bytes of workspace for a plan; with ws != nullptr also carves the buffers.
+size_t knn_workspace(const KnnPlan &p, void *ws, KnnBuffers *out);
 int knn_run(const KnnPlan &p, const float *Q, const float *R, int32_t *out_idx, float *out_dist, void *ws,
             hipStream_t stream);
 
