@@ -7,18 +7,20 @@
 //
 //   key_ij = ||y_j||^2 - 2 x_i . y_j      (= d_ij - ||x_i||^2, same order per row)
 //
-// Data path of the screen (one wave = 64 queries, one workgroup = 4 waves):
+// Data path of the screen (one wave = 32 queries, one workgroup = 4 waves):
 //   * the query operand (-2 x) stays in VGPRs for the whole launch;
 //   * references are repacked once into the MFMA A-operand order (one
 //     float4 per lane per four contraction steps, 1 KiB per wave load, fully
-//     coalesced) and streamed HBM/MALL/L2 -> VGPR with a one-block
-//     register prefetch; no LDS staging and no workgroup barrier;
-//   * ||y||^2 is loaded straight into the accumulator (the C input of the
-//     first v_mfma_f32_32x32x2_f32 of a block), so the MFMA chain produces
-//     the key itself;
-//   * the epilogue is one compare per pair against the query's current
-//     threshold; a key below it enters the query's max-heap of the S
-//     smallest keys in LDS (rare after the first few blocks).
+//     coalesced) and streamed HBM/MALL/L2 -> VGPR, each float4 of the next
+//     block loaded as soon as the current one has been consumed; no LDS and
+//     no workgroup barrier;
+//   * when the half-width leaves a spare contraction slot, ||y||^2 rides in
+//     it (times 1 on the query side), so the MFMA chain produces the key;
+//     otherwise the norm is added in the epilogue;
+//   * each lane keeps, in registers, the sorted 16 (or 32) smallest keys of
+//     the references its contraction half sees (every other group of four
+//     rows); a key below the lane's current 16th enters by an unrolled
+//     compare-and-shift, so the common case costs one compare per pair.
 // A launch may split the references into P ranges (blockIdx.y) to give
 // small problems enough workgroups; each range keeps its own heap.
 //
@@ -82,21 +84,46 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Packed reference layout for a contraction half-width DH (DHP = DH rounded
-// up to 4).  Block b holds rows 32b..32b+31:
-//   A[b][s4][lane] (float4): element u = R[32b + lane%32][(lane/32) DH + 4 s4 + u]
-//   N[b][h][4g + j]        : ||R[32b + 8g + 4h + j]||^2   (+inf past the end)
-// so that MFMA step s reads lane-contiguous data and the norms land in the
-// accumulator registers in output order.
-__global__ __launch_bounds__(256) void k_pack(const float *__restrict__ R, int64_t nr, int d, int DH, int DHP4,
-                                              int64_t nblk, f32x4 *__restrict__ Ap) {
-    const int64_t total = nblk * DHP4 * kWave;
+// Whether the contraction half-width DH leaves a spare slot in its last
+// float4 for the reference norm (the common d = 49, 50 case: DH = 25).
+__host__ __device__ constexpr bool norm_folded(int DH) { return (DH % 4) != 0; }
+__host__ __device__ constexpr int packed_s4(int DH) { return (DH + (norm_folded(DH) ? 1 : 0) + 3) / 4; }
+
+// Squared norms of the reference rows (float64 sum, rounded once) and the
+// largest norm.
+__global__ __launch_bounds__(256) void k_norms(const float *__restrict__ R, int64_t nr, int d,
+                                               float *__restrict__ nrow, uint32_t *__restrict__ max_norm_bits) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float nf = 0.f;
+    if (r < nr) {
+        const float *x = R + r * d;
+        double s = 0.0;
+        for (int t = 0; t < d; ++t) s += (double)x[t] * (double)x[t];
+        nf = (float)s;
+        nrow[r] = nf;
+    }
+    const float m = wave_max(sqrtf(nf));
+    if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(max_norm_bits, __float_as_uint(m));
+}
+
+// Packed reference layout for a contraction half-width DH.  Block b holds
+// rows 32b..32b+31:
+//   A[b][s4][lane] (float4): element u = step s = 4 s4 + u of lane (c, h) =
+//       R[32b + c][h DH + s] for s < DH; step DH of half 0 = ||R[32b + c]||^2
+//       when the norm is folded; 0 elsewhere (+inf norm past the end);
+//   N[b][h][4g + j] (only when not folded): ||R[32b + 8g + 4h + j]||^2, the
+//       accumulator order of the 32x32 output block (+inf past the end);
+// so that MFMA step s of a wave reads 1 KiB of lane-contiguous data.
+__global__ __launch_bounds__(256) void k_pack(const float *__restrict__ R, const float *__restrict__ nrow, int64_t nr,
+                                              int d, int DH, int S4, int folded, int64_t nblk,
+                                              f32x4 *__restrict__ Ap, float *__restrict__ Np) {
+    const int64_t total = nblk * S4 * kWave;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
         const int lane = (int)(e % kWave);
         const int64_t bs = e / kWave;
-        const int s4 = (int)(bs % DHP4);
-        const int64_t b = bs / DHP4;
+        const int s4 = (int)(bs % S4);
+        const int64_t b = bs / S4;
         const int64_t row = 32 * b + (lane & 31);
         const int h = lane >> 5;
         f32x4 v;
@@ -104,34 +131,24 @@ __global__ __launch_bounds__(256) void k_pack(const float *__restrict__ R, int64
         for (int u = 0; u < 4; ++u) {
             const int s = 4 * s4 + u;
             const int t = h * DH + s;
-            v[u] = (row < nr && s < DH && t < d) ? R[row * d + t] : 0.f;
+            float x = 0.f;
+            if (s < DH) {
+                if (row < nr && t < d) x = R[row * d + t];
+            } else if (folded && s == DH && h == 0) {
+                x = row < nr ? nrow[row] : INFINITY;
+            }
+            v[u] = x;
         }
         Ap[e] = v;
-    }
-}
-
-// Squared norms (float64 sum, rounded once) in the packed order, and the
-// largest norm.
-__global__ __launch_bounds__(256) void k_pack_norms(const float *__restrict__ R, int64_t nr, int d, int64_t nblk,
-                                                    float *__restrict__ Np, uint32_t *__restrict__ max_norm_bits) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    float nf = 0.f;
-    if (r < nblk * 32) {
-        float out = INFINITY;
-        if (r < nr) {
-            const float *x = R + r * d;
-            double s = 0.0;
-            for (int t = 0; t < d; ++t) s += (double)x[t] * (double)x[t];
-            out = (float)s;
-            nf = out;
+        if (!folded && s4 == 0) {
+            // lane (c, h) of block b also files the norm of row 32b + c into accumulator order
+            if (h == 0) {
+                const int i = lane & 31;
+                const int g = i >> 3, hh = (i >> 2) & 1, j = i & 3;
+                Np[b * 32 + hh * 16 + 4 * g + j] = row < nr ? nrow[row] : INFINITY;
+            }
         }
-        const int64_t b = r >> 5;
-        const int i = (int)(r & 31);
-        const int g = i >> 3, h = (i >> 2) & 1, j = i & 3;
-        Np[b * 32 + h * 16 + 4 * g + j] = out;
     }
-    const float m = wave_max(sqrtf(nf));
-    if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(max_norm_bits, __float_as_uint(m));
 }
 
 __global__ void k_init_counters(KnnCounters *c) {
@@ -147,11 +164,15 @@ __global__ void k_init_counters(KnnCounters *c) {
 // ---------------------------------------------------------------------------
 // Screen.
 //
-// Lane l handles query column c = l % 32 of each of its QB query blocks and
-// contraction half h = l / 32: dimension h*DH + s feeds MFMA step s.  Output
-// register v of a 32x32 block holds reference row 8(v/4) + 4h + (v%4).
+// Lane l handles query c = l % 32 of its wave and contraction half
+// h = l / 32: step s of the MFMA chain multiplies dimension h*DH + s.
+// Output register v of the 32x32 block holds reference row 8(v/4) + 4h +
+// (v%4), so each lane sees half of the references of every block and keeps
+// its own sorted list of the L smallest keys of that half.
 // Query slot i of the launch is row i, or row qlist[i] for i < min(*qcount,
 // qcap) when a list is given (the escalation pass).
+// Output: cand[(slot * 2P + 2p + h) * L + i], i-th smallest key of half h
+// of range p (index -1 / key +inf where fewer than L were seen).
 // ---------------------------------------------------------------------------
 struct ScreenArgs {
     const float *Q;
@@ -160,32 +181,54 @@ struct ScreenArgs {
     const int32_t *qcount;  // its device-side length
     int qcap;
     const f32x4 *Ap;
-    const float *Np;
+    const float *Np;        // norms in accumulator order (when not folded)
     int64_t nblk;
     int d;
-    int S;  // heap size (<= KP)
-    int P;  // reference ranges (gridDim.y)
-    int32_t *cand_idx;  // [slot][P][KP]
+    int P;                  // reference ranges (gridDim.y)
+    int32_t *cand_idx;
     float *cand_key;
 };
 
-template <int DH, int QB, int KP>
-__global__ __launch_bounds__(256, 2) void k_screen_fp32(ScreenArgs a) {
-    constexpr int QW = QB * 32;
-    constexpr int QG = kScreenWaves * QW;
-    constexpr int DHP = (DH + 3) & ~3;
-    constexpr int S4 = DHP / 4;
+// Insert (key, idx) into the ascending register list (lk, li), dropping the
+// largest entry.  Unrolled compare-and-shift: no dynamic register indexing.
+// Occupancy target (waves per SIMD) that the register budget of a screen
+// instantiation allows without spilling.
+__host__ __device__ constexpr int screen_min_waves(int DH, int L) { return (DH <= 25 && L == 16) ? 3 : 2; }
 
-    __shared__ float hk[KP * QG];
-    __shared__ int hi[KP * QG];
+template <int L>
+__device__ __forceinline__ void list_insert(float (&lk)[L], int (&li)[L], float key, int idx) {
+#pragma unroll
+    for (int i = L - 1; i > 0; --i) {
+        const bool shift = key < lk[i - 1];
+        const bool here = key < lk[i];
+        lk[i] = shift ? lk[i - 1] : (here ? key : lk[i]);
+        li[i] = shift ? li[i - 1] : (here ? idx : li[i]);
+    }
+    if (key < lk[0]) {
+        lk[0] = key;
+        li[0] = idx;
+    }
+}
 
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
+template <int DH, int L>
+__global__ __launch_bounds__(256, screen_min_waves(DH, L)) void k_screen_fp32(ScreenArgs a) {
+    constexpr bool NF = norm_folded(DH);
+    constexpr int STEPS = DH + (NF ? 1 : 0);
+    constexpr int S4 = packed_s4(DH);
+    constexpr int QG = kScreenWaves * 32;
+    constexpr int QCAP = 16;  // queued keys per lane (a block adds at most 16)
+
+    // Per-lane queue of keys that beat the lane's threshold, entry-major so
+    // that lanes appending their e-th entry touch consecutive words.
+    __shared__ float2 qbuf[QCAP * 256];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1), wave = tid >> 6;
     const int h = lane >> 5, c = lane & 31;
     const int p = blockIdx.y;
     const int64_t blk_per = (a.nblk + a.P - 1) / a.P;
     const int64_t blk0 = (int64_t)p * blk_per;
     const int64_t blk1 = std::min<int64_t>(a.nblk, blk0 + blk_per);
-    const int S = a.S;
 
     int64_t nslots = a.nq;
     if (a.qlist) {
@@ -194,136 +237,101 @@ __global__ __launch_bounds__(256, 2) void k_screen_fp32(ScreenArgs a) {
     }
 
     for (int64_t qblk = blockIdx.x; qblk * QG < nslots; qblk += gridDim.x) {
-        const int64_t slot_wave = qblk * QG + wave * QW;
+        const int64_t slot = qblk * QG + wave * 32 + c;
+        int64_t row = -1;
+        if (slot < nslots) row = a.qlist ? (int64_t)a.qlist[slot] : slot;
 
         // Query operand, resident for the whole range; -2 folded in (exact).
-        float b[QB][DH];
+        float b[STEPS];
 #pragma unroll
-        for (int qb = 0; qb < QB; ++qb) {
-            const int64_t slot = slot_wave + qb * 32 + c;
-            int64_t row = -1;
-            if (slot < nslots) row = a.qlist ? (int64_t)a.qlist[slot] : slot;
+        for (int s = 0; s < DH; ++s) {
+            const int t = h * DH + s;
+            b[s] = (row >= 0 && t < a.d) ? -2.f * a.Q[row * a.d + t] : 0.f;
+        }
+        if constexpr (NF) b[DH] = (row >= 0 && h == 0) ? 1.f : 0.f;
+
+        float lk[L];
+        int li[L];
 #pragma unroll
-            for (int s = 0; s < DH; ++s) {
-                const int t = h * DH + s;
-                b[qb][s] = (row >= 0 && t < a.d) ? -2.f * a.Q[row * a.d + t] : 0.f;
+        for (int i = 0; i < L; ++i) {
+            lk[i] = INFINITY;
+            li[i] = -1;
+        }
+        float thr = INFINITY;  // lk[L-1] as of the last flush
+        int count = 0;         // queued entries of this lane
+
+        // Move every queued key into the sorted list (all lanes at once).
+        auto flush = [&]() {
+            int maxc = count;
+            for (int o = 32; o > 0; o >>= 1) maxc = max(maxc, __shfl_xor(maxc, o, kWave));
+            for (int e = 0; e < maxc; ++e) {
+                if (e < count) {
+                    const float2 q = qbuf[e * 256 + tid];
+                    if (q.x < lk[L - 1]) list_insert<L>(lk, li, q.x, __float_as_int(q.y));
+                }
             }
-        }
+            count = 0;
+            thr = lk[L - 1];
+        };
 
-        // This wave's heaps: slots [wave*QW, wave*QW + QW) of every heap level.
-        for (int e = lane; e < KP * QW; e += kWave) {
-            const int lvl = e / QW, ql = e % QW;
-            hk[lvl * QG + wave * QW + ql] = INFINITY;
-            hi[lvl * QG + wave * QW + ql] = -1;
-        }
-
-        float thr[QB];
-#pragma unroll
-        for (int qb = 0; qb < QB; ++qb) thr[qb] = INFINITY;
-
-        f32x4 an[S4], nn[4];
-        auto fetch = [&](int64_t blk, f32x4 (&A)[S4], f32x4 (&N)[4]) {
-            const f32x4 *src = a.Ap + blk * (S4 * kWave) + lane;
+        f32x4 A[S4];
+        if (blk0 < blk1) {
+            const f32x4 *src = a.Ap + blk0 * (S4 * kWave) + lane;
 #pragma unroll
             for (int s4 = 0; s4 < S4; ++s4) A[s4] = src[s4 * kWave];
-            const f32x4 *ns = reinterpret_cast<const f32x4 *>(a.Np + blk * 32 + h * 16);
-#pragma unroll
-            for (int g = 0; g < 4; ++g) N[g] = ns[g];
-        };
-        if (blk0 < blk1) fetch(blk0, an, nn);
+        }
 
         for (int64_t blk = blk0; blk < blk1; ++blk) {
-            f32x4 ac[S4], nc[4];
+            f32x4 nv[4];
+            if constexpr (!NF) {
+                const f32x4 *ns = reinterpret_cast<const f32x4 *>(a.Np + blk * 32 + h * 16);
 #pragma unroll
-            for (int s4 = 0; s4 < S4; ++s4) ac[s4] = an[s4];
-#pragma unroll
-            for (int g = 0; g < 4; ++g) nc[g] = nn[g];
-            if (blk + 1 < blk1) fetch(blk + 1, an, nn);
-
-            f32x16 init;
-#pragma unroll
-            for (int v = 0; v < 16; ++v) init[v] = nc[v >> 2][v & 3];
-            f32x16 acc[QB];
-#pragma unroll
-            for (int qb = 0; qb < QB; ++qb) acc[qb] = init;
+                for (int g = 0; g < 4; ++g) nv[g] = ns[g];
+            }
+            const bool more = blk + 1 < blk1;
+            const f32x4 *nsrc = a.Ap + (blk + 1) * (S4 * kWave) + lane;
+            f32x16 acc = f32x16{};
 #pragma unroll
             for (int s4 = 0; s4 < S4; ++s4) {
+                const f32x4 cur = A[s4];
+                if (more) A[s4] = nsrc[s4 * kWave];  // next block, as soon as this float4 is consumed
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int s = 4 * s4 + u;
-                    if (s < DH) {
-#pragma unroll
-                        for (int qb = 0; qb < QB; ++qb)
-                            acc[qb] = __builtin_amdgcn_mfma_f32_32x32x2f32(ac[s4][u], b[qb][s], acc[qb], 0, 0, 0);
-                    }
+                    if (s < STEPS) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cur[u], b[s], acc, 0, 0, 0);
                 }
             }
-
-            bool hit = false;
+            if constexpr (!NF) {
 #pragma unroll
-            for (int qb = 0; qb < QB; ++qb) {
-                float mn = acc[qb][0];
-#pragma unroll
-                for (int v = 1; v < 16; ++v) mn = fminf(mn, acc[qb][v]);
-                hit |= mn < thr[qb];
+                for (int v = 0; v < 16; ++v) acc[v] += nv[v >> 2][v & 3];
             }
-            if (__ballot(hit) != 0ull) {
+
+            float mn = acc[0];
+#pragma unroll
+            for (int v = 1; v < 16; ++v) mn = fminf(mn, acc[v]);
+            if (__ballot(mn < thr) != 0ull) {
+                int hits = 0;
+#pragma unroll
+                for (int v = 0; v < 16; ++v) hits += acc[v] < thr ? 1 : 0;
+                if (__ballot(count + hits > QCAP) != 0ull) flush();
                 const int ref0 = (int)(blk * 32) + 4 * h;
 #pragma unroll
-                for (int qb = 0; qb < QB; ++qb) {
-                    const int ql = wave * QW + qb * 32 + c;
-                    float *hkq = hk + ql;
-                    int *hiq = hi + ql;
-                    // The two halves of a query share its heap: take turns.
-#pragma unroll
-                    for (int hh = 0; hh < 2; ++hh) {
-                        if (h == hh) {
-#pragma unroll
-                            for (int v = 0; v < 16; ++v) {
-                                const float key = acc[qb][v];
-                                if (key < thr[qb] && key < hkq[0]) {
-                                    // replace the root (largest kept key) and sift down
-                                    const int idx = ref0 + 8 * (v >> 2) + (v & 3);
-                                    int pos = 0;
-                                    while (true) {
-                                        int ch = 2 * pos + 1;
-                                        if (ch >= S) break;
-                                        float kc = hkq[ch * QG];
-                                        if (ch + 1 < S) {
-                                            const float k1 = hkq[(ch + 1) * QG];
-                                            if (k1 > kc) {
-                                                kc = k1;
-                                                ++ch;
-                                            }
-                                        }
-                                        if (!(kc > key)) break;
-                                        hkq[pos * QG] = kc;
-                                        hiq[pos * QG] = hiq[ch * QG];
-                                        pos = ch;
-                                    }
-                                    hkq[pos * QG] = key;
-                                    hiq[pos * QG] = idx;
-                                    thr[qb] = hkq[0];
-                                }
-                            }
-                        }
+                for (int v = 0; v < 16; ++v) {
+                    if (acc[v] < thr) {
+                        qbuf[count * 256 + tid] = make_float2(acc[v], __int_as_float(ref0 + 8 * (v >> 2) + (v & 3)));
+                        ++count;
                     }
-                    thr[qb] = hkq[0];
                 }
             }
         }
+        flush();
 
-        // Candidates of this range: lane (c, h) writes slots h, h+2, ... of its queries.
+        if (slot < nslots) {
+            const int64_t base = ((slot * a.P + p) * 2 + h) * L;
 #pragma unroll
-        for (int qb = 0; qb < QB; ++qb) {
-            const int64_t slot = slot_wave + qb * 32 + c;
-            if (slot < nslots) {
-                const int ql = wave * QW + qb * 32 + c;
-                const int64_t base = (slot * a.P + p) * KP;
-                for (int sl = h; sl < S; sl += 2) {
-                    a.cand_key[base + sl] = hk[sl * QG + ql];
-                    a.cand_idx[base + sl] = hi[sl * QG + ql];
-                }
+            for (int i = 0; i < L; ++i) {
+                a.cand_key[base + i] = lk[i];
+                a.cand_idx[base + i] = li[i];
             }
         }
     }
@@ -551,33 +559,34 @@ __global__ __launch_bounds__(64) void k_rescan(const float *__restrict__ Q, cons
     }
 }
 
-template <int DH, int QB, int KP>
+template <int DH, int L>
 int launch_screen(const ScreenArgs &a, unsigned gx, const char *name, hipStream_t stream) {
     ScopedTimer timer(name, stream);
-    hipLaunchKernelGGL((k_screen_fp32<DH, QB, KP>), dim3(gx, (unsigned)a.P), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL((k_screen_fp32<DH, L>), dim3(gx, (unsigned)a.P), dim3(256), 0, stream, a);
     return launch_status(name);
 }
 
-template <int QB, int KP>
+template <int L>
 int dispatch_screen(int dh, const ScreenArgs &a, unsigned gx, const char *name, hipStream_t s) {
     switch (dh) {
-        case 4: return launch_screen<4, QB, KP>(a, gx, name, s);
-        case 8: return launch_screen<8, QB, KP>(a, gx, name, s);
-        case 16: return launch_screen<16, QB, KP>(a, gx, name, s);
-        case 25: return launch_screen<25, QB, KP>(a, gx, name, s);
-        case 32: return launch_screen<32, QB, KP>(a, gx, name, s);
-        case 48: return launch_screen<48, 1, KP>(a, gx, name, s);
-        case 64: return launch_screen<64, 1, KP>(a, gx, name, s);
+        case 4: return launch_screen<4, L>(a, gx, name, s);
+        case 8: return launch_screen<8, L>(a, gx, name, s);
+        case 16: return launch_screen<16, L>(a, gx, name, s);
+        case 25: return launch_screen<25, L>(a, gx, name, s);
+        case 32: return launch_screen<32, L>(a, gx, name, s);
+        case 48: return launch_screen<48, L>(a, gx, name, s);
+        case 64: return launch_screen<64, L>(a, gx, name, s);
         default: set_error("internal: no screen kernel for this dimension"); return RSC_ERR_UNSUPPORTED;
     }
 }
 
-int screen(const KnnPlan &p, const ScreenArgs &a, unsigned gx, int kp, const char *name, hipStream_t s) {
-    if (kp == 32) return dispatch_screen<2, 32>(p.dh, a, gx, name, s);
-    return dispatch_screen<1, 64>(p.dh, a, gx, name, s);
+// One launch of the screen; `half_width` is the list length per contraction half.
+int screen(int dh, const ScreenArgs &a, unsigned gx, int half_width, const char *name, hipStream_t s) {
+    if (half_width == 16) return dispatch_screen<16>(dh, a, gx, name, s);
+    return dispatch_screen<32>(dh, a, gx, name, s);
 }
 
-int queries_per_group(int dh, int kp) { return kScreenWaves * 32 * ((kp == 32 && dh <= 32) ? 2 : 1); }
+constexpr int kQueriesPerGroup = kScreenWaves * 32;
 
 int pick_dh(int d) {
     const int half = (d + 1) / 2;
@@ -632,8 +641,8 @@ int knn_plan(int64_t nq, int64_t nr, int d, int k, const rsc_knn_opts *opts, boo
         return RSC_ERR_INVALID_ARG;
     }
     if (screen_w == 0) screen_w = k <= 16 ? 32 : 64;
-    if (screen_w <= k || screen_w > 64) {
-        set_error("screen width must satisfy k < screen <= 64");
+    if (screen_w <= k || (screen_w != 32 && screen_w != 64)) {
+        set_error("screen width must be 32 or 64 and larger than k");
         return RSC_ERR_INVALID_ARG;
     }
     plan->nq = nq;
@@ -641,24 +650,25 @@ int knn_plan(int64_t nq, int64_t nr, int d, int k, const rsc_knn_opts *opts, boo
     plan->d = d;
     plan->k = k;
     plan->screen = screen_w;
-    plan->kp = screen_w <= 32 ? 32 : 64;
+    plan->half = screen_w / 2;
     plan->dh = pick_dh(d);
     plan->self_mode = self_mode;
     plan->nblk = (nr + 31) / 32;
-    plan->splits = pick_splits(nq, plan->nblk, queries_per_group(plan->dh, plan->kp));
+    plan->splits = pick_splits(nq, plan->nblk, kQueriesPerGroup);
     return RSC_OK;
 }
 
 size_t knn_workspace(const KnnPlan &p, void *ws, KnnBuffers *out) {
     Carver cv(ws);
     KnnBuffers b;
-    const int dhp4 = ((p.dh + 3) & ~3) / 4;
+    const int s4 = packed_s4(p.dh);
     const int64_t esc_rows = std::min<int64_t>(p.nq, kEscalateCap);
     b.counters = cv.take<KnnCounters>(1);
-    b.packed = cv.take<float>((size_t)p.nblk * dhp4 * kWave * 4);
-    b.norms = cv.take<float>((size_t)p.nblk * 32);
-    b.cand_idx = cv.take<int32_t>((size_t)p.nq * p.splits * p.kp);
-    b.cand_key = cv.take<float>((size_t)p.nq * p.splits * p.kp);
+    b.nrow = cv.take<float>((size_t)p.nr);
+    b.packed = cv.take<float>((size_t)p.nblk * s4 * kWave * 4);
+    b.norms = cv.take<float>(norm_folded(p.dh) ? 1 : (size_t)p.nblk * 32);
+    b.cand_idx = cv.take<int32_t>((size_t)p.nq * p.splits * p.screen);
+    b.cand_key = cv.take<float>((size_t)p.nq * p.splits * p.screen);
     b.flag1 = cv.take<int32_t>((size_t)std::max<int64_t>(p.nq, 1));
     b.flag2 = cv.take<int32_t>((size_t)std::max<int64_t>(esc_rows, 1));
     b.esc_idx = cv.take<int32_t>((size_t)std::max<int64_t>(esc_rows, 1) * kEscalateSplits * kEscalateWidth);
@@ -672,24 +682,23 @@ int knn_run(const KnnPlan &p, const float *Q, const float *R, int32_t *out_idx, 
     KnnBuffers b;
     knn_workspace(p, ws, &b);
     int st;
-    const int dhp4 = ((p.dh + 3) & ~3) / 4;
+    const int s4 = packed_s4(p.dh);
     {
         ScopedTimer timer("prep_pack", stream);
         hipLaunchKernelGGL(k_init_counters, dim3(1), dim3(64), 0, stream, b.counters);
-        const int64_t tot = p.nblk * dhp4 * kWave;
-        const unsigned g1 = (unsigned)std::min<int64_t>((tot + 255) / 256, 65536);
-        hipLaunchKernelGGL(k_pack, dim3(g1), dim3(256), 0, stream, R, p.nr, p.d, p.dh, dhp4, p.nblk,
-                           reinterpret_cast<f32x4 *>(b.packed));
-        const unsigned g2 = (unsigned)((p.nblk * 32 + 255) / 256);
-        hipLaunchKernelGGL(k_pack_norms, dim3(g2), dim3(256), 0, stream, R, p.nr, p.d, p.nblk, b.norms,
+        hipLaunchKernelGGL(k_norms, dim3((unsigned)((p.nr + 255) / 256)), dim3(256), 0, stream, R, p.nr, p.d, b.nrow,
                            &b.counters->max_norm_bits);
+        const int64_t tot = p.nblk * s4 * kWave;
+        const unsigned g1 = (unsigned)std::min<int64_t>((tot + 255) / 256, 65536);
+        hipLaunchKernelGGL(k_pack, dim3(g1), dim3(256), 0, stream, R, b.nrow, p.nr, p.d, p.dh, s4,
+                           norm_folded(p.dh) ? 1 : 0, p.nblk, reinterpret_cast<f32x4 *>(b.packed), b.norms);
         if ((st = launch_status("prep_pack")) != RSC_OK) return st;
     }
     if (p.nq == 0) return RSC_OK;
 
-    // Error bound of the float32 key (norm folded into the MFMA sum, norms
-    // rounded once from float64): 2 (d + 3) units of roundoff times
-    // (2 ||x|| max||y|| + max||y||^2).
+    // Error bound of the float32 key (the norm enters the MFMA sum or is
+    // added after it; norms rounded once from float64): 2 (d + 3) units of
+    // roundoff times (2 ||x|| max||y|| + max||y||^2).
     const double eps_coef = 2.0 * (p.d + 3) * std::ldexp(1.0, -24);
 
     ScreenArgs sa{};
@@ -699,22 +708,22 @@ int knn_run(const KnnPlan &p, const float *Q, const float *R, int32_t *out_idx, 
     sa.Np = b.norms;
     sa.nblk = p.nblk;
     sa.d = p.d;
-    sa.S = p.screen;
     sa.P = p.splits;
     sa.cand_idx = b.cand_idx;
     sa.cand_key = b.cand_key;
-    const int qg = queries_per_group(p.dh, p.kp);
-    if ((st = screen(p, sa, (unsigned)((p.nq + qg - 1) / qg), p.kp, "screen_fp32", stream)) != RSC_OK) return st;
+    const unsigned gq = (unsigned)((p.nq + kQueriesPerGroup - 1) / kQueriesPerGroup);
+    if ((st = screen(p.dh, sa, gq, p.half, "screen_fp32", stream)) != RSC_OK) return st;
 
+    // Each (range, half) list is one candidate group of width `half`.
     RerankArgs ra{};
     ra.Q = Q;
     ra.nq = p.nq;
     ra.R = R;
     ra.d = p.d;
     ra.k = p.k;
-    ra.S = p.screen;
-    ra.KP = p.kp;
-    ra.P = p.splits;
+    ra.S = p.half;
+    ra.KP = p.half;
+    ra.P = 2 * p.splits;
     ra.self_mode = p.self_mode ? 1 : 0;
     ra.cand_idx = b.cand_idx;
     ra.cand_key = b.cand_key;
@@ -732,27 +741,22 @@ int knn_run(const KnnPlan &p, const float *Q, const float *R, int32_t *out_idx, 
 
     // Escalation: rows that failed, screened again 64 wide over many ranges.
     const int esc_cap = (int)std::min<int64_t>(p.nq, kEscalateCap);
-    KnnPlan pe = p;
-    pe.screen = kEscalateWidth;
-    pe.kp = 64;
     ScreenArgs se = sa;
     se.qlist = b.flag1;
     se.qcount = &b.counters->flagged;
     se.qcap = esc_cap;
-    se.S = kEscalateWidth;
     se.P = (int)std::min<int64_t>(kEscalateSplits, std::max<int64_t>(1, p.nblk));
     se.cand_idx = b.esc_idx;
     se.cand_key = b.esc_key;
-    const int qge = queries_per_group(p.dh, 64);
-    if ((st = screen(pe, se, (unsigned)((esc_cap + qge - 1) / qge), 64, "screen_escalate", stream)) != RSC_OK)
-        return st;
+    const unsigned ge = (unsigned)((esc_cap + kQueriesPerGroup - 1) / kQueriesPerGroup);
+    if ((st = screen(p.dh, se, ge, kEscalateWidth / 2, "screen_escalate", stream)) != RSC_OK) return st;
     RerankArgs re = ra;
     re.qlist = b.flag1;
     re.qcount = &b.counters->flagged;
     re.qcap = esc_cap;
-    re.S = kEscalateWidth;
-    re.KP = 64;
-    re.P = se.P;
+    re.S = kEscalateWidth / 2;
+    re.KP = kEscalateWidth / 2;
+    re.P = 2 * se.P;
     re.cand_idx = b.esc_idx;
     re.cand_key = b.esc_key;
     re.flag_out = b.flag2;

@@ -66,7 +66,7 @@ struct KnnCounters {
 
 struct KnnPlan {
     int64_t nq, nr;
-    int d, k, screen, kp;  // kp: heap capacity (32 or 64)
+    int d, k, screen, half;  // screen width (32 or 64) = 2 x list length per contraction half
     int dh;                // half of the padded contraction length
     bool self_mode;        // queries are the references (self forced to slot 0)
     int64_t nblk;          // 32-row reference blocks
@@ -75,7 +75,7 @@ struct KnnPlan {
 
 struct KnnBuffers {
     KnnCounters *counters;
-    float *packed, *norms;
+    float *nrow, *packed, *norms;
     int32_t *cand_idx;
     float *cand_key;
     int32_t *flag1, *flag2;
