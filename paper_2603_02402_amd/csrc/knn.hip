@@ -54,8 +54,8 @@ constexpr int kScreenWaves = 4;   // waves per screen workgroup
 constexpr int kMaxD = 128;
 constexpr int kMaxK = 63;
 constexpr int kRescanMax = 64;    // list capacity of the exhaustive rescan
-constexpr int kEscalateCap = 2048;  // rows handled by the escalation screen
-constexpr int kEscalateSplits = 32;
+constexpr int kEscalateCap = 8192;  // rows handled by the escalation screen
+constexpr int kEscalateSplits = 16;
 constexpr int kEscalateWidth = 64;
 
 // (d2, j) lexicographic order: smaller distance first, lower index on ties.
@@ -108,9 +108,11 @@ __global__ __launch_bounds__(256) void k_norms(const float *__restrict__ R, int6
 
 // Packed reference layout for a contraction half-width DH.  Block b holds
 // rows 32b..32b+31:
-//   A[b][s4][lane] (float4): element u = step s = 4 s4 + u of lane (c, h) =
-//       R[32b + c][h DH + s] for s < DH; step DH of half 0 = ||R[32b + c]||^2
-//       when the norm is folded; 0 elsewhere (+inf norm past the end);
+//   A[b][s4][lane] (float4): element u = step s = 4 s4 + u of lane (c, h).
+//       With the norm folded, step 0 of half 0 is ||R[32b + c]||^2 (+inf
+//       past the end; half 1 holds 0) and step 1 + t is R[32b + c][h DH + t];
+//       otherwise step t is R[32b + c][h DH + t].  0 elsewhere.  Putting the
+//       norm first keeps the partial sums of the key near its final size;
 //   N[b][h][4g + j] (only when not folded): ||R[32b + 8g + 4h + j]||^2, the
 //       accumulator order of the 32x32 output block (+inf past the end);
 // so that MFMA step s of a wave reads 1 KiB of lane-contiguous data.
@@ -127,15 +129,17 @@ __global__ __launch_bounds__(256) void k_pack(const float *__restrict__ R, const
         const int64_t row = 32 * b + (lane & 31);
         const int h = lane >> 5;
         f32x4 v;
+        const int off = folded ? 1 : 0;  // the norm occupies step 0 when folded
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int s = 4 * s4 + u;
-            const int t = h * DH + s;
+            const int sd = s - off;        // dimension step
+            const int t = h * DH + sd;
             float x = 0.f;
-            if (s < DH) {
+            if (folded && s == 0) {
+                if (h == 0) x = row < nr ? nrow[row] : INFINITY;
+            } else if (sd < DH) {
                 if (row < nr && t < d) x = R[row * d + t];
-            } else if (folded && s == DH && h == 0) {
-                x = row < nr ? nrow[row] : INFINITY;
             }
             v[u] = x;
         }
@@ -165,7 +169,8 @@ __global__ void k_init_counters(KnnCounters *c) {
 // Screen.
 //
 // Lane l handles query c = l % 32 of its wave and contraction half
-// h = l / 32: step s of the MFMA chain multiplies dimension h*DH + s.
+// h = l / 32: a step of the MFMA chain multiplies dimension h*DH + t (plus
+// the norm step, first, when folded).
 // Output register v of the 32x32 block holds reference row 8(v/4) + 4h +
 // (v%4), so each lane sees half of the references of every block and keeps
 // its own sorted list of the L smallest keys of that half.
@@ -242,13 +247,14 @@ __global__ __launch_bounds__(256, screen_min_waves(DH, L)) void k_screen_fp32(Sc
         if (slot < nslots) row = a.qlist ? (int64_t)a.qlist[slot] : slot;
 
         // Query operand, resident for the whole range; -2 folded in (exact).
+        constexpr int OFF = NF ? 1 : 0;  // step 0 carries the norm when folded
         float b[STEPS];
 #pragma unroll
         for (int s = 0; s < DH; ++s) {
             const int t = h * DH + s;
-            b[s] = (row >= 0 && t < a.d) ? -2.f * a.Q[row * a.d + t] : 0.f;
+            b[OFF + s] = (row >= 0 && t < a.d) ? -2.f * a.Q[row * a.d + t] : 0.f;
         }
-        if constexpr (NF) b[DH] = (row >= 0 && h == 0) ? 1.f : 0.f;
+        if constexpr (NF) b[0] = (row >= 0 && h == 0) ? 1.f : 0.f;
 
         float lk[L];
         int li[L];
@@ -414,9 +420,8 @@ __global__ __launch_bounds__(256) void k_rerank(RerankArgs a) {
     double xx = 0.0;
     for (int t = lane; t < a.d; t += kWave) xx += (double)x[t] * (double)x[t];
     xx = wave_sum(xx);
-    const float ymax_f = __uint_as_float(a.counters->max_norm_bits);
-    const double ym = (double)ymax_f * (1.0 + 1e-6);
-    const double eps = a.eps_coef * (2.0 * sqrt(xx) * ym + ym * ym);
+    const double xn = sqrt(xx) * (1.0 + 1e-12);
+    const double ymax = (double)__uint_as_float(a.counters->max_norm_bits) * (1.0 + 1e-6);
 
     // Smallest key any full range could have rejected.
     float tau = INFINITY;
@@ -445,10 +450,15 @@ __global__ __launch_bounds__(256) void k_rerank(RerankArgs a) {
             const int p = ci / a.S, e = ci - (ci / a.S) * a.S;
             const int j = a.cand_idx[cbase + p * a.KP + e];
             if (j >= 0 && !(a.self_mode && j == row)) {
-                d2 = exact_d2(x, a.R + (int64_t)j * a.d, a.d);
+                const float *y = a.R + (int64_t)j * a.d;
+                d2 = exact_d2(x, y, a.d);
                 jj = j;
+                double yy = 0.0;
+                for (int t = 0; t < a.d; ++t) yy += (double)y[t] * (double)y[t];
+                const double yn = sqrt(yy);
                 const float key = a.cand_key[cbase + p * a.KP + e];
-                ratio = fmaxf(ratio, (float)(fabs((double)key - (d2 - xx)) / eps));
+                const double err_bound = a.eps_coef * (2.0 * xn * yn + yy) + 1e-300;
+                ratio = fmaxf(ratio, (float)(fabs((double)key - (d2 - xx)) / err_bound));
             }
         }
         bitonic_sort64(d2, jj, lane);
@@ -465,7 +475,13 @@ __global__ __launch_bounds__(256) void k_rerank(RerankArgs a) {
     const int m = a.self_mode ? a.k - 1 : a.k;  // neighbours to certify
     bool ok = true;
     if (m > 0 && tau < INFINITY) {
+        // A rejected reference y had a screened key >= tau.  If ||y|| > Y =
+        // ||x|| + D_m it lies farther than D_m (triangle inequality); else its
+        // float32 key is off by at most eps(Y), so its true key is >= tau -
+        // eps(Y), which must exceed D_m^2 - ||x||^2.
         const double dm = __shfl(rd, m - 1, kWave);
+        const double Y = fmin(ymax, (xn + sqrt(dm)) * (1.0 + 1e-9));
+        const double eps = a.eps_coef * (2.0 * xn * Y + Y * Y);
         const double bound = (double)tau + xx - eps - 1e-12 * (fabs((double)tau) + xx);
         ok = dm < bound;
     }
