@@ -215,6 +215,23 @@ __device__ __forceinline__ void list_insert(float (&lk)[L], int (&li)[L], float 
     }
 }
 
+// Load float4 group s4 of a packed block (wave-uniform base wb).  A partial
+// last group (STEPS not a multiple of 4) is fetched with a narrower load so
+// that no dead register half is left pending under a load.
+template <int STEPS, int S4>
+__device__ __forceinline__ void load_group(f32x4 (&A)[S4], const f32x4 *wb, int s4, int lane) {
+    constexpr int REM = STEPS - 4 * (S4 - 1);
+    if (s4 < S4 - 1 || REM >= 3) {
+        A[s4] = wb[s4 * kWave + lane];
+    } else if (REM == 2) {
+        const float2 t = reinterpret_cast<const float2 *>(wb + s4 * kWave + lane)[0];
+        A[s4][0] = t.x;
+        A[s4][1] = t.y;
+    } else {
+        A[s4][0] = reinterpret_cast<const float *>(wb + s4 * kWave + lane)[0];
+    }
+}
+
 template <int DH, int L>
 __global__ __launch_bounds__(256, screen_min_waves(DH, L)) void k_screen_fp32(ScreenArgs a) {
     constexpr bool NF = norm_folded(DH);
@@ -280,11 +297,14 @@ __global__ __launch_bounds__(256, screen_min_waves(DH, L)) void k_screen_fp32(Sc
             thr = lk[L - 1];
         };
 
-        f32x4 A[S4];
+        f32x4 A[S4] = {};
         if (blk0 < blk1) {
-            const f32x4 *src = a.Ap + blk0 * (S4 * kWave) + lane;
+            const f32x4 *wb0 = a.Ap + blk0 * (S4 * kWave);
 #pragma unroll
-            for (int s4 = 0; s4 < S4; ++s4) A[s4] = src[s4 * kWave];
+            for (int s4 = 0; s4 < S4; ++s4) {
+                load_group<STEPS, S4>(A, wb0, s4, lane);
+                __builtin_amdgcn_sched_barrier(0);  // issue in group order, as the loop does
+            }
         }
 
         for (int64_t blk = blk0; blk < blk1; ++blk) {
@@ -294,18 +314,21 @@ __global__ __launch_bounds__(256, screen_min_waves(DH, L)) void k_screen_fp32(Sc
 #pragma unroll
                 for (int g = 0; g < 4; ++g) nv[g] = ns[g];
             }
-            const bool more = blk + 1 < blk1;
-            const f32x4 *nsrc = a.Ap + (blk + 1) * (S4 * kWave) + lane;
+            // Next block (the last block re-reads itself: always in bounds,
+            // so the loads need no branch and stay in flight across the MFMAs).
+            const int64_t nxt = blk + 1 < blk1 ? blk + 1 : blk;
+            const f32x4 *wb = a.Ap + nxt * (S4 * kWave);
             f32x16 acc = f32x16{};
 #pragma unroll
             for (int s4 = 0; s4 < S4; ++s4) {
-                const f32x4 cur = A[s4];
-                if (more) A[s4] = nsrc[s4 * kWave];  // next block, as soon as this float4 is consumed
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int s = 4 * s4 + u;
-                    if (s < STEPS) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(cur[u], b[s], acc, 0, 0, 0);
+                    if (s < STEPS) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(A[s4][u], b[s], acc, 0, 0, 0);
                 }
+                load_group<STEPS, S4>(A, wb, s4, lane);  // consumed: fetch its successor
+                // keep each load right behind the MFMAs that freed its registers
+                __builtin_amdgcn_sched_barrier(0);
             }
             if constexpr (!NF) {
 #pragma unroll
