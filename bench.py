@@ -72,6 +72,48 @@ def cpu_baseline(X: np.ndarray, k: int, budget_s: float) -> dict:
                       f"(FP64 brute-force kNN + smooth-kNN on their lists); {secs:.1f} s"}
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "screen_fp32_plain_1m_traffic.json")
+KNN_SOURCE = os.path.join(ROOT, "paper_2603_02402_amd", "csrc", "knn.hip")
+
+
+def measured_traffic():
+    """HBM-side bytes per screen launch from the committed PMC summary, or None
+    when the kernel source has changed since the counters were taken."""
+    import hashlib
+
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+        h = hashlib.sha256(open(KNN_SOURCE, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != h:
+        return None
+    return rec.get("traffic_bytes_per_launch")
+
+
+def traffic_probe() -> int:
+    """Program for the PMC runs: a torch copy of 1 GiB (counter calibration),
+    then one kNN graph step on the 1M-cell workload."""
+    import torch
+
+    import paper_2603_02402_amd as rsc
+    import synth
+
+    print("traffic probe: calibration copy of 1 GiB", flush=True)
+    a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    X = synth.workload("plain_1m")
+    idx, dist, g = rsc.knn_graph(torch.from_numpy(X).cuda(), 15)
+    torch.cuda.synchronize()
+    print(f"traffic probe: done, nnz {g.nnz}", flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,7 +123,10 @@ def main() -> int:
     ap.add_argument("--k", type=int, default=15)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic-probe", action="store_true", help="run the PMC calibration program and exit")
     args = ap.parse_args()
+    if args.traffic_probe:
+        return traffic_probe()
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported (the kNN graph here runs "
@@ -153,7 +198,8 @@ def main() -> int:
     if screen_ms:
         achieved = flops / (screen_ms / 1e3) / 1e12
         roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                    "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                    "traffic": measured_traffic() if args.workload == "plain_1m" and k == 15 else None,
                     "kernel": "k_screen_fp32 (FP32 MFMA 32x32x2 distance screen + per-query top-32 heap)",
                     "work_per_launch": f"2*d*n^2 = {flops:.3e} flop (d={d}, n={n})"}
 
