@@ -78,10 +78,16 @@ typedef enum { RSC_FP32 = 0, RSC_BF16 = 1, RSC_FP8_E4M3 = 2 } rsc_precision;
  * Options of the screening stage.  A zero-initialised struct (or NULL)
  * selects the default: FP32 screen of width 32 (64 for k > 16) followed by
  * the exactness certificate and rescan, i.e. the exact result.
- *   precision  arithmetic of the distance screen (only RSC_FP32 is
- *              implemented in this ABI version; others -> UNSUPPORTED).
- *   screen     candidates kept per query by the screen, k < screen <= 64;
- *              0 = default.
+ *   precision  arithmetic of the distance screen on the matrix cores:
+ *              RSC_FP32      exact result (certified, see rsc_knn);
+ *              RSC_BF16      BF16 operands, FP32 accumulation;
+ *              RSC_FP8_E4M3  OCP e4m3 operands with per-dimension absmax
+ *                            scaling (s_t = max|y_t| / 448), FP32 accumulation.
+ *              The reduced-precision forms keep the 64 smallest screened keys
+ *              per query and re-rank them with float64 distances; they are
+ *              approximate (no certificate): judge them by recall@k.
+ *   screen     candidates kept per query: 32 or 64 for RSC_FP32 (must exceed
+ *              k), 64 for the reduced-precision forms; 0 = default.
  */
 typedef struct {
     int32_t precision;
@@ -117,6 +123,11 @@ size_t rsc_knn_workspace_bytes(int64_t n_query, int64_t n_ref, int32_t d, int32_
  */
 int rsc_knn(const float *X, int64_t n, int32_t d, int32_t k, int32_t *out_idx, float *out_dist, void *workspace,
             size_t workspace_bytes, void *stream);
+
+/* rsc_knn with screening options (precision forms of the same square
+ * problem; opts may be NULL for the exact default). */
+int rsc_knn_opt(const float *X, int64_t n, int32_t d, int32_t k, const rsc_knn_opts *opts, int32_t *out_idx,
+                float *out_dist, void *workspace, size_t workspace_bytes, void *stream);
 
 /*
  * Rectangular form: k nearest rows of R for every row of Q (no self

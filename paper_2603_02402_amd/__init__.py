@@ -85,8 +85,10 @@ def knn(X, k: int, Q=None, precision: int = RSC_FP32, screen: int = 0, out=None,
 
     ``knn(X, k)``: every row of ``X`` (n x d float32) among the rows of ``X``;
     column 0 is the row itself.  ``knn(X, k, Q=Q)``: rows of ``Q`` among
-    the rows of ``X`` (all k columns from ``X``).  Returns ``(idx int32,
-    dist float32)``, each ``n_query x k``.
+    the rows of ``X`` (all k columns from ``X``).  ``precision`` selects the
+    screen (``RSC_FP32`` exact; ``RSC_BF16`` / ``RSC_FP8_E4M3`` approximate,
+    re-ranked in float64).  Returns ``(idx int32, dist float32)``, each
+    ``n_query x k``.
     """
     torch = _torch()
     _check_dev(X, Q)
@@ -98,8 +100,6 @@ def knn(X, k: int, Q=None, precision: int = RSC_FP32, screen: int = 0, out=None,
         raise ValueError("Q must be a float32 tensor with X's column count")
     lib = load()
     o = _opts(precision, screen)
-    if Q is None and (precision != RSC_FP32 or screen != 0):
-        raise ValueError("options are only accepted by the rectangular form in this ABI version")
     need = lib.rsc_knn_workspace_bytes(nq, n, d, k, ctypes.byref(o))
     if need == 0:
         # invalid sizes: let the call itself report the reason
@@ -110,8 +110,11 @@ def knn(X, k: int, Q=None, precision: int = RSC_FP32, screen: int = 0, out=None,
         dist = torch.empty((nq, k), dtype=torch.float32, device=X.device)
     else:
         idx, dist = out
-    if Q is None:
+    if Q is None and precision == RSC_FP32 and screen == 0:
         st = lib.rsc_knn(_ptr(X), n, d, k, _ptr(idx), _ptr(dist), _ptr(ws), ws.numel(), _stream())
+    elif Q is None:
+        st = lib.rsc_knn_opt(_ptr(X), n, d, k, ctypes.byref(o), _ptr(idx), _ptr(dist), _ptr(ws), ws.numel(),
+                             _stream())
     else:
         st = lib.rsc_knn_ex(_ptr(Q), nq, _ptr(X), n, d, k, ctypes.byref(o), _ptr(idx), _ptr(dist), _ptr(ws),
                             ws.numel(), _stream())

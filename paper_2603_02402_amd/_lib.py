@@ -52,6 +52,7 @@ SIGNATURES = {
     "rsc_last_error": (ctypes.c_char_p, []),
     "rsc_knn_workspace_bytes": (_SZ, [_I64, _I64, _I32, _I32, _P]),
     "rsc_knn": (ctypes.c_int, [_P, _I64, _I32, _I32, _P, _P, _P, _SZ, _P]),
+    "rsc_knn_opt": (ctypes.c_int, [_P, _I64, _I32, _I32, _P, _P, _P, _P, _SZ, _P]),
     "rsc_knn_ex": (ctypes.c_int, [_P, _I64, _P, _I64, _I32, _I32, _P, _P, _P, _P, _SZ, _P]),
     "rsc_knn_read_stats": (ctypes.c_int, [_P, _SZ, _P, _P]),
     "rsc_connectivities_workspace_bytes": (_SZ, [_I64, _I32]),

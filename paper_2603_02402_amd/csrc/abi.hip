@@ -119,6 +119,7 @@ const char *rsc_last_error(void) { return g_error.c_str(); }
 
 size_t rsc_knn_workspace_bytes(int64_t n_query, int64_t n_ref, int32_t d, int32_t k, const rsc_knn_opts *opts) {
     KnnPlan p;
+    // the square and rectangular forms need the same workspace
     if (knn_plan(n_query, n_ref, d, k, opts, false, &p) != RSC_OK) return 0;
     return knn_workspace(p, nullptr, nullptr);
 }
@@ -146,6 +147,11 @@ static int knn_common(const float *Q, int64_t nq, const float *R, int64_t nr, in
 int rsc_knn(const float *X, int64_t n, int32_t d, int32_t k, int32_t *out_idx, float *out_dist, void *workspace,
             size_t workspace_bytes, void *stream) {
     return knn_common(X, n, X, n, d, k, nullptr, true, out_idx, out_dist, workspace, workspace_bytes, stream);
+}
+
+int rsc_knn_opt(const float *X, int64_t n, int32_t d, int32_t k, const rsc_knn_opts *opts, int32_t *out_idx,
+                float *out_dist, void *workspace, size_t workspace_bytes, void *stream) {
+    return knn_common(X, n, X, n, d, k, opts, true, out_idx, out_dist, workspace, workspace_bytes, stream);
 }
 
 int rsc_knn_ex(const float *Q, int64_t n_query, const float *R, int64_t n_ref, int32_t d, int32_t k,

@@ -41,48 +41,20 @@
 #include <cmath>
 
 #include "rsc_internal.hpp"
+#include "screen_common.hpp"
 
 namespace rsc {
 
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
 namespace {
 
-constexpr int kWave = 64;
-constexpr int kScreenWaves = 4;   // waves per screen workgroup
+using namespace scr;
+
 constexpr int kMaxD = 128;
 constexpr int kMaxK = 63;
-constexpr int kRescanMax = 64;    // list capacity of the exhaustive rescan
+constexpr int kRescanMax = 64;      // list capacity of the exhaustive rescan
 constexpr int kEscalateCap = 8192;  // rows handled by the escalation screen
 constexpr int kEscalateSplits = 16;
 constexpr int kEscalateWidth = 64;
-
-// (d2, j) lexicographic order: smaller distance first, lower index on ties.
-__device__ __forceinline__ bool lex_before(double da, int ja, double db, int jb) {
-    return da < db || (da == db && ja < jb);
-}
-
-// Squared distance of two float32 rows in float64, dimensions in order,
-// every product and sum rounded separately (no contraction).
-__device__ __forceinline__ double exact_d2(const float *__restrict__ x, const float *__restrict__ y, int d) {
-    double s = 0.0;
-    for (int t = 0; t < d; ++t) {
-        double diff = __dsub_rn((double)x[t], (double)y[t]);
-        s = __dadd_rn(s, __dmul_rn(diff, diff));
-    }
-    return s;
-}
-
-__device__ __forceinline__ float wave_max(float v) {
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
-    return v;
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
-}
 
 // Whether the contraction half-width DH leaves a spare slot in its last
 // float4 for the reference norm (the common d = 49, 50 case: DH = 25).
@@ -179,41 +151,9 @@ __global__ void k_init_counters(KnnCounters *c) {
 // Output: cand[(slot * 2P + 2p + h) * L + i], i-th smallest key of half h
 // of range p (index -1 / key +inf where fewer than L were seen).
 // ---------------------------------------------------------------------------
-struct ScreenArgs {
-    const float *Q;
-    int64_t nq;
-    const int32_t *qlist;   // optional gather list
-    const int32_t *qcount;  // its device-side length
-    int qcap;
-    const f32x4 *Ap;
-    const float *Np;        // norms in accumulator order (when not folded)
-    int64_t nblk;
-    int d;
-    int P;                  // reference ranges (gridDim.y)
-    int32_t *cand_idx;
-    float *cand_key;
-};
-
-// Insert (key, idx) into the ascending register list (lk, li), dropping the
-// largest entry.  Unrolled compare-and-shift: no dynamic register indexing.
 // Occupancy target (waves per SIMD) that the register budget of a screen
 // instantiation allows without spilling.
 __host__ __device__ constexpr int screen_min_waves(int DH, int L) { return (DH <= 25 && L == 16) ? 3 : 2; }
-
-template <int L>
-__device__ __forceinline__ void list_insert(float (&lk)[L], int (&li)[L], float key, int idx) {
-#pragma unroll
-    for (int i = L - 1; i > 0; --i) {
-        const bool shift = key < lk[i - 1];
-        const bool here = key < lk[i];
-        lk[i] = shift ? lk[i - 1] : (here ? key : lk[i]);
-        li[i] = shift ? li[i - 1] : (here ? idx : li[i]);
-    }
-    if (key < lk[0]) {
-        lk[0] = key;
-        li[0] = idx;
-    }
-}
 
 // Load float4 group s4 of a packed block (wave-uniform base wb).  A partial
 // last group (STEPS not a multiple of 4) is fetched with a narrower load so
@@ -238,11 +178,9 @@ __global__ __launch_bounds__(256, screen_min_waves(DH, L)) void k_screen_fp32(Sc
     constexpr int STEPS = DH + (NF ? 1 : 0);
     constexpr int S4 = packed_s4(DH);
     constexpr int QG = kScreenWaves * 32;
-    constexpr int QCAP = 16;  // queued keys per lane (a block adds at most 16)
-
     // Per-lane queue of keys that beat the lane's threshold, entry-major so
     // that lanes appending their e-th entry touch consecutive words.
-    __shared__ float2 qbuf[QCAP * 256];
+    __shared__ float2 qbuf[kQueueCap * 256];
 
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1), wave = tid >> 6;
@@ -251,12 +189,8 @@ __global__ __launch_bounds__(256, screen_min_waves(DH, L)) void k_screen_fp32(Sc
     const int64_t blk_per = (a.nblk + a.P - 1) / a.P;
     const int64_t blk0 = (int64_t)p * blk_per;
     const int64_t blk1 = std::min<int64_t>(a.nblk, blk0 + blk_per);
-
-    int64_t nslots = a.nq;
-    if (a.qlist) {
-        const int cnt = *a.qcount;
-        nslots = std::min<int64_t>(std::min<int64_t>(cnt, a.qcap), a.nq);
-    }
+    const int64_t nslots = screen_slots(a);
+    const f32x4 *Ap = static_cast<const f32x4 *>(a.Ap);
 
     for (int64_t qblk = blockIdx.x; qblk * QG < nslots; qblk += gridDim.x) {
         const int64_t slot = qblk * QG + wave * 32 + c;
@@ -273,33 +207,13 @@ __global__ __launch_bounds__(256, screen_min_waves(DH, L)) void k_screen_fp32(Sc
         }
         if constexpr (NF) b[0] = (row >= 0 && h == 0) ? 1.f : 0.f;
 
-        float lk[L];
-        int li[L];
-#pragma unroll
-        for (int i = 0; i < L; ++i) {
-            lk[i] = INFINITY;
-            li[i] = -1;
-        }
-        float thr = INFINITY;  // lk[L-1] as of the last flush
-        int count = 0;         // queued entries of this lane
-
-        // Move every queued key into the sorted list (all lanes at once).
-        auto flush = [&]() {
-            int maxc = count;
-            for (int o = 32; o > 0; o >>= 1) maxc = max(maxc, __shfl_xor(maxc, o, kWave));
-            for (int e = 0; e < maxc; ++e) {
-                if (e < count) {
-                    const float2 q = qbuf[e * 256 + tid];
-                    if (q.x < lk[L - 1]) list_insert<L>(lk, li, q.x, __float_as_int(q.y));
-                }
-            }
-            count = 0;
-            thr = lk[L - 1];
-        };
+        LaneTopK<L> top;
+        top.init();
+        float2 *q = qbuf + tid;
 
         f32x4 A[S4] = {};
         if (blk0 < blk1) {
-            const f32x4 *wb0 = a.Ap + blk0 * (S4 * kWave);
+            const f32x4 *wb0 = Ap + blk0 * (S4 * kWave);
 #pragma unroll
             for (int s4 = 0; s4 < S4; ++s4) {
                 load_group<STEPS, S4>(A, wb0, s4, lane);
@@ -317,7 +231,7 @@ __global__ __launch_bounds__(256, screen_min_waves(DH, L)) void k_screen_fp32(Sc
             // Next block (the last block re-reads itself: always in bounds,
             // so the loads need no branch and stay in flight across the MFMAs).
             const int64_t nxt = blk + 1 < blk1 ? blk + 1 : blk;
-            const f32x4 *wb = a.Ap + nxt * (S4 * kWave);
+            const f32x4 *wb = Ap + nxt * (S4 * kWave);
             f32x16 acc = f32x16{};
 #pragma unroll
             for (int s4 = 0; s4 < S4; ++s4) {
@@ -335,34 +249,10 @@ __global__ __launch_bounds__(256, screen_min_waves(DH, L)) void k_screen_fp32(Sc
                 for (int v = 0; v < 16; ++v) acc[v] += nv[v >> 2][v & 3];
             }
 
-            float mn = acc[0];
-#pragma unroll
-            for (int v = 1; v < 16; ++v) mn = fminf(mn, acc[v]);
-            if (__ballot(mn < thr) != 0ull) {
-                int hits = 0;
-#pragma unroll
-                for (int v = 0; v < 16; ++v) hits += acc[v] < thr ? 1 : 0;
-                if (__ballot(count + hits > QCAP) != 0ull) flush();
-                const int ref0 = (int)(blk * 32) + 4 * h;
-#pragma unroll
-                for (int v = 0; v < 16; ++v) {
-                    if (acc[v] < thr) {
-                        qbuf[count * 256 + tid] = make_float2(acc[v], __int_as_float(ref0 + 8 * (v >> 2) + (v & 3)));
-                        ++count;
-                    }
-                }
-            }
+            top.offer(acc, (int)(blk * 32) + 4 * h, q, 256);
         }
-        flush();
-
-        if (slot < nslots) {
-            const int64_t base = ((slot * a.P + p) * 2 + h) * L;
-#pragma unroll
-            for (int i = 0; i < L; ++i) {
-                a.cand_key[base + i] = lk[i];
-                a.cand_idx[base + i] = li[i];
-            }
-        }
+        top.flush(q, 256);
+        if (slot < nslots) top.store(a, slot, p, h);
     }
 }
 
@@ -380,6 +270,7 @@ struct RerankArgs {
     const float *R;
     int d, k, S, KP, P;
     int self_mode;
+    int certify;            // 0: approximate screen, never flag rows
     const int32_t *cand_idx;
     const float *cand_key;
     double eps_coef;
@@ -497,7 +388,7 @@ __global__ __launch_bounds__(256) void k_rerank(RerankArgs a) {
 
     const int m = a.self_mode ? a.k - 1 : a.k;  // neighbours to certify
     bool ok = true;
-    if (m > 0 && tau < INFINITY) {
+    if (a.certify && m > 0 && tau < INFINITY) {
         // A rejected reference y had a screened key >= tau.  If ||y|| > Y =
         // ||x|| + D_m it lies farther than D_m (triangle inequality); else its
         // float32 key is off by at most eps(Y), so its true key is >= tau -
@@ -671,18 +562,22 @@ int knn_plan(int64_t nq, int64_t nr, int d, int k, const rsc_knn_opts *opts, boo
     }
     int precision = opts ? opts->precision : RSC_FP32;
     int screen_w = opts ? opts->screen : 0;
-    if (precision != RSC_FP32) {
-        if (precision == RSC_BF16 || precision == RSC_FP8_E4M3) {
-            set_error("reduced-precision screens are not implemented in this build");
-            return RSC_ERR_UNSUPPORTED;
-        }
+    if (precision != RSC_FP32 && precision != RSC_BF16 && precision != RSC_FP8_E4M3) {
         set_error("unknown precision");
         return RSC_ERR_INVALID_ARG;
     }
-    if (screen_w == 0) screen_w = k <= 16 ? 32 : 64;
-    if (screen_w <= k || (screen_w != 32 && screen_w != 64)) {
-        set_error("screen width must be 32 or 64 and larger than k");
-        return RSC_ERR_INVALID_ARG;
+    if (precision == RSC_FP32) {
+        if (screen_w == 0) screen_w = k <= 16 ? 32 : 64;
+        if (screen_w <= k || (screen_w != 32 && screen_w != 64)) {
+            set_error("screen width must be 32 or 64 and larger than k");
+            return RSC_ERR_INVALID_ARG;
+        }
+    } else {
+        if (screen_w == 0) screen_w = 64;
+        if (screen_w != 64) {
+            set_error("reduced-precision screens keep 64 candidates (screen = 0 or 64)");
+            return RSC_ERR_INVALID_ARG;
+        }
     }
     plan->nq = nq;
     plan->nr = nr;
@@ -693,19 +588,29 @@ int knn_plan(int64_t nq, int64_t nr, int d, int k, const rsc_knn_opts *opts, boo
     plan->dh = pick_dh(d);
     plan->self_mode = self_mode;
     plan->nblk = (nr + 31) / 32;
-    plan->splits = pick_splits(nq, plan->nblk, kQueriesPerGroup);
+    plan->precision = precision;
+    plan->splits = pick_splits(nq, plan->nblk,
+                               precision == RSC_FP32 ? kQueriesPerGroup : lowp_queries_per_group(precision, d));
     return RSC_OK;
 }
 
 size_t knn_workspace(const KnnPlan &p, void *ws, KnnBuffers *out) {
     Carver cv(ws);
-    KnnBuffers b;
+    KnnBuffers b{};
+    const bool fp32 = p.precision == RSC_FP32;
     const int s4 = packed_s4(p.dh);
-    const int64_t esc_rows = std::min<int64_t>(p.nq, kEscalateCap);
+    const int64_t esc_rows = fp32 ? std::min<int64_t>(p.nq, kEscalateCap) : 0;
     b.counters = cv.take<KnnCounters>(1);
-    b.nrow = cv.take<float>((size_t)p.nr);
-    b.packed = cv.take<float>((size_t)p.nblk * s4 * kWave * 4);
-    b.norms = cv.take<float>(norm_folded(p.dh) ? 1 : (size_t)p.nblk * 32);
+    if (fp32) {
+        b.nrow = cv.take<float>((size_t)p.nr);
+        b.packed = cv.take<float>((size_t)p.nblk * s4 * kWave * 4);
+        b.norms = cv.take<float>(norm_folded(p.dh) ? 1 : (size_t)p.nblk * 32);
+    } else {
+        b.packed = reinterpret_cast<float *>(cv.take<char>(lowp_packed_bytes(p.precision, p.nblk, p.d)));
+        b.norms = cv.take<float>((size_t)p.nblk * 32);
+        b.scal = cv.take<float>(2 * 128 + 1);
+        b.amax = cv.take<uint32_t>(256);
+    }
     b.cand_idx = cv.take<int32_t>((size_t)p.nq * p.splits * p.screen);
     b.cand_key = cv.take<float>((size_t)p.nq * p.splits * p.screen);
     b.flag1 = cv.take<int32_t>((size_t)std::max<int64_t>(p.nq, 1));
@@ -716,10 +621,56 @@ size_t knn_workspace(const KnnPlan &p, void *ws, KnnBuffers *out) {
     return cv.used;
 }
 
+// Reduced-precision form: screen, then rerank without a certificate.
+int knn_run_lowp(const KnnPlan &p, const float *Q, const float *R, int32_t *out_idx, float *out_dist,
+                 const KnnBuffers &b, hipStream_t stream) {
+    int st;
+    hipLaunchKernelGGL(k_init_counters, dim3(1), dim3(64), 0, stream, b.counters);
+    if ((st = launch_status("init_counters")) != RSC_OK) return st;
+    if ((st = lowp_prepare(p, Q, R, b.packed, b.norms, b.scal, b.amax, stream)) != RSC_OK) return st;
+    if (p.nq == 0) return RSC_OK;
+    ScreenArgs sa{};
+    sa.Q = Q;
+    sa.nq = p.nq;
+    sa.Ap = b.packed;
+    sa.Np = b.norms;
+    sa.qscale = b.scal;
+    sa.nblk = p.nblk;
+    sa.d = p.d;
+    sa.P = p.splits;
+    sa.cand_idx = b.cand_idx;
+    sa.cand_key = b.cand_key;
+    const int qg = lowp_queries_per_group(p.precision, p.d);
+    if ((st = lowp_screen(p, sa, (unsigned)((p.nq + qg - 1) / qg), stream)) != RSC_OK) return st;
+    RerankArgs ra{};
+    ra.Q = Q;
+    ra.nq = p.nq;
+    ra.R = R;
+    ra.d = p.d;
+    ra.k = p.k;
+    ra.S = p.half;
+    ra.KP = p.half;
+    ra.P = 2 * p.splits;
+    ra.self_mode = p.self_mode ? 1 : 0;
+    ra.certify = 0;
+    ra.cand_idx = b.cand_idx;
+    ra.cand_key = b.cand_key;
+    ra.eps_coef = 1.0;
+    ra.counters = b.counters;
+    ra.flag_out = b.flag1;
+    ra.flag_count = &b.counters->flagged;
+    ra.out_idx = out_idx;
+    ra.out_dist = out_dist;
+    ScopedTimer timer("rerank", stream);
+    hipLaunchKernelGGL(k_rerank, dim3((unsigned)((p.nq + 3) / 4)), dim3(256), 0, stream, ra);
+    return launch_status("rerank");
+}
+
 int knn_run(const KnnPlan &p, const float *Q, const float *R, int32_t *out_idx, float *out_dist, void *ws,
             hipStream_t stream) {
     KnnBuffers b;
     knn_workspace(p, ws, &b);
+    if (p.precision != RSC_FP32) return knn_run_lowp(p, Q, R, out_idx, out_dist, b, stream);
     int st;
     const int s4 = packed_s4(p.dh);
     {
@@ -743,7 +694,7 @@ int knn_run(const KnnPlan &p, const float *Q, const float *R, int32_t *out_idx, 
     ScreenArgs sa{};
     sa.Q = Q;
     sa.nq = p.nq;
-    sa.Ap = reinterpret_cast<const f32x4 *>(b.packed);
+    sa.Ap = b.packed;
     sa.Np = b.norms;
     sa.nblk = p.nblk;
     sa.d = p.d;
@@ -764,6 +715,7 @@ int knn_run(const KnnPlan &p, const float *Q, const float *R, int32_t *out_idx, 
     ra.KP = p.half;
     ra.P = 2 * p.splits;
     ra.self_mode = p.self_mode ? 1 : 0;
+    ra.certify = 1;
     ra.cand_idx = b.cand_idx;
     ra.cand_key = b.cand_key;
     ra.eps_coef = eps_coef;

@@ -1,0 +1,452 @@
+// Reduced-precision distance screens (BF16, FP8-e4m3) on gfx950 MFMA.
+//
+// The precision form of the neighbour search: the distance contraction runs
+// in BF16 (v_mfma_f32_32x32x16_bf16) or in OCP FP8-e4m3 with per-dimension
+// scaling (v_mfma_scale_f32_32x32x64_f8f6f4, unit block scales), always
+// accumulating in FP32.  Each query keeps its 64 smallest screened keys (32
+// per contraction half), which are then re-ranked with float64 distances of
+// the original float32 data by the same rerank kernel as the exact path.
+// No certificate is attempted: the result is approximate by design and is
+// judged by recall@k and distance error against exact search.
+//
+// Keys are ||y~||^2 - 2 x~ . y~ where y~, x~ are the rounded vectors, so the
+// screen ranks by the exact distance between the rounded points:
+//   BF16: the squared norm of the BF16-rounded reference, split into a BF16
+//         high part and a BF16 low part that ride in two spare contraction
+//         slots (the query side holds 1.0 there), so the MFMA chain yields
+//         the key and the padding to a multiple of 16 costs nothing extra;
+//   FP8:  reference codes q(y_t / s_t) with s_t = absmax_t / 448 (round to
+//         nearest even, saturating at 448), query codes q(-2 G x_t s_t) with a
+//         power-of-two G that fills the e4m3 range; the dequantised norm
+//         G ||s . q(y/s)||^2 is the accumulator's initial value, so the chain
+//         yields G times the key (same order).
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "rsc_internal.hpp"
+#include "screen_common.hpp"
+
+namespace rsc {
+
+namespace {
+
+using namespace scr;
+
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr float kFp8Max = 448.f;  // largest finite e4m3 (OCP "fn") value
+constexpr int kLowpQB = 1;        // query blocks (of 32) per wave
+
+// float32 -> bfloat16 bits, round to nearest even (finite inputs; inf kept).
+__device__ inline uint32_t bf16_bits(float x) {
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7f800000u) == 0x7f800000u) return u >> 16;  // inf / nan
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+__device__ inline float bf16_value(uint32_t b) { return __uint_as_float(b << 16); }
+
+// float32 -> OCP e4m3 ("fn": no infinities, 0x7f / 0xff are NaN) code,
+// round to nearest even, saturating to +-448.
+__device__ inline uint32_t e4m3_code(float x) {
+    const uint32_t sign = (__float_as_uint(x) >> 24) & 0x80u;
+    const float a = fabsf(x);
+    if (!(a < kFp8Max)) return sign | 0x7eu;  // saturate (also catches inf)
+    const uint32_t bits = __float_as_uint(a);
+    const int e = (int)((bits >> 23) & 0xff) - 127;
+    if (e < -6) {
+        // subnormal range: multiples of 2^-9; rintf is round-half-even
+        const uint32_t m = (uint32_t)rintf(a * 512.f);  // 0..8; 8 is the smallest normal
+        return sign | m;
+    }
+    uint32_t mant = bits & 0x7fffffu;
+    uint32_t r = mant >> 20;
+    const uint32_t rem = mant & 0xfffffu;
+    if (rem > 0x80000u || (rem == 0x80000u && (r & 1u))) ++r;
+    int ee = e + 7;
+    if (r == 8) {
+        r = 0;
+        ++ee;
+    }
+    uint32_t code = ((uint32_t)ee << 3) | r;
+    if (code > 0x7eu) code = 0x7eu;
+    return sign | code;
+}
+
+__device__ inline float e4m3_value(uint32_t code) {
+    const float s = (code & 0x80u) ? -1.f : 1.f;
+    const uint32_t e = (code >> 3) & 0xfu, m = code & 7u;
+    if (e == 0) return s * (float)m * (1.f / 512.f);
+    return s * ldexpf(1.f + (float)m * 0.125f, (int)e - 7);
+}
+
+// ---------------------------------------------------------------------------
+// BF16 packing.  Block b, step s, lane (c, h): 8 bf16 for contraction index
+// kk = 16 s + 8 h + e: dimension kk < d; kk == d: high part of the norm of
+// the rounded row; kk == d + 1: its low part; 0 elsewhere.  Past the last
+// row: 0, and +inf as the norm's high part.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_pack_bf16(const float *__restrict__ R, int64_t nr, int d, int KS,
+                                                   int64_t nblk, i32x4 *__restrict__ Ap) {
+    const int64_t total = nblk * KS * kWave;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int lane = (int)(e % kWave);
+        const int64_t bs = e / kWave;
+        const int s = (int)(bs % KS);
+        const int64_t b = bs / KS;
+        const int64_t row = 32 * b + (lane & 31);
+        const int h = lane >> 5;
+        const int k0 = 16 * s + 8 * h;
+        float nhi = 0.f, nlo = 0.f;
+        if (k0 <= d + 1 && k0 + 8 > d) {  // this group holds a norm slot
+            if (row < nr) {
+                double n = 0.0;
+                for (int t = 0; t < d; ++t) {
+                    const double v = bf16_value(bf16_bits(R[row * d + t]));
+                    n += v * v;
+                }
+                const float nf = (float)n;
+                nhi = bf16_value(bf16_bits(nf));
+                nlo = bf16_value(bf16_bits(nf - nhi));
+            } else {
+                nhi = INFINITY;
+            }
+        }
+        uint32_t w[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            uint32_t two = 0;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int kk = k0 + 2 * p + q;
+                float v = 0.f;
+                if (kk < d) {
+                    if (row < nr) v = R[row * d + kk];
+                } else if (kk == d) {
+                    v = nhi;
+                } else if (kk == d + 1) {
+                    v = nlo;
+                }
+                two |= bf16_bits(v) << (16 * q);
+            }
+            w[p] = two;
+        }
+        Ap[e] = i32x4{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
+    }
+}
+
+__global__ void k_fill_u32(uint32_t *p, int n, uint32_t v) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// FP8 scaling and packing.
+// ---------------------------------------------------------------------------
+// Per-dimension max |x| over the rows of X (float bits, atomic max).
+__global__ __launch_bounds__(256) void k_absmax(const float *__restrict__ X, int64_t n, int d,
+                                                uint32_t *__restrict__ amax_bits) {
+    __shared__ uint32_t local[128];
+    for (int t = threadIdx.x; t < d; t += blockDim.x) local[t] = 0u;
+    __syncthreads();
+    const int64_t total = n * d;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int t = (int)(e % d);
+        atomicMax(&local[t], __float_as_uint(fabsf(X[e])));
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < d; t += blockDim.x) atomicMax(&amax_bits[t], local[t]);
+}
+
+// scal[0..d): reference scale s_t = absmax_t / 448 (1 for an all-zero
+// dimension); scal[d..2d): query multiplier -2 G s_t; scal[2d]: G.
+__global__ void k_fp8_scales(const uint32_t *__restrict__ amax_r, const uint32_t *__restrict__ amax_q, int d,
+                             float *__restrict__ scal) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    float m = 0.f;
+    for (int t = 0; t < d; ++t) {
+        const float ar = __uint_as_float(amax_r[t]);
+        const float s = ar > 0.f ? ar / kFp8Max : 1.f;
+        scal[t] = s;
+        m = fmaxf(m, 2.f * __uint_as_float(amax_q[t]) * s);
+    }
+    float G = 1.f;
+    if (m > 0.f) G = ldexpf(1.f, (int)floorf(log2f(kFp8Max / m)));
+    for (int t = 0; t < d; ++t) scal[d + t] = -2.f * G * scal[t];
+    scal[2 * d] = G;
+}
+
+// Block b, step s, lane (c, h): 32 e4m3 codes for kk = 64 s + 32 h + e
+// (dimension kk < d, else 0).  Norms: G ||s . q(y/s)||^2 in accumulator
+// order (+inf past the last row).
+__global__ __launch_bounds__(256) void k_pack_fp8(const float *__restrict__ R, int64_t nr, int d, int KS,
+                                                  int64_t nblk, const float *__restrict__ scal,
+                                                  i32x8 *__restrict__ Ap, float *__restrict__ Np) {
+    const int64_t total = nblk * KS * kWave;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int lane = (int)(e % kWave);
+        const int64_t bs = e / kWave;
+        const int s = (int)(bs % KS);
+        const int64_t b = bs / KS;
+        const int64_t row = 32 * b + (lane & 31);
+        const int h = lane >> 5;
+        const int k0 = 64 * s + 32 * h;
+        i32x8 w;
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            uint32_t four = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int kk = k0 + 4 * p + q;
+                uint32_t code = 0;
+                if (kk < d && row < nr) code = e4m3_code(R[row * d + kk] / scal[kk]);
+                four |= code << (8 * q);
+            }
+            w[p] = (int)four;
+        }
+        Ap[e] = w;
+        if (s == 0 && h == 0) {
+            float out = INFINITY;
+            if (row < nr) {
+                double n = 0.0;
+                for (int t = 0; t < d; ++t) {
+                    const double v = (double)e4m3_value(e4m3_code(R[row * d + t] / scal[t])) * scal[t];
+                    n += v * v;
+                }
+                out = (float)(n * scal[2 * d]);
+            }
+            const int i = lane & 31;
+            const int g = i >> 3, hh = (i >> 2) & 1, j = i & 3;
+            Np[b * 32 + hh * 16 + 4 * g + j] = out;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Screen.  Lane l handles query c = l % 32 of each of its QB query blocks
+// and contraction half h = l / 32; output register v of a 32x32 block holds
+// reference row 8(v/4) + 4h + (v%4).
+// ---------------------------------------------------------------------------
+template <int PREC>
+struct LowpOp;
+template <>
+struct LowpOp<RSC_BF16> {
+    using T = i32x4;
+    static constexpr int kPerStep = 16;
+    __device__ static f32x16 mfma(T a, T b, f32x16 c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
+                                                       c, 0, 0, 0);
+    }
+};
+template <>
+struct LowpOp<RSC_FP8_E4M3> {
+    using T = i32x8;
+    static constexpr int kPerStep = 64;
+    __device__ static f32x16 mfma(T a, T b, f32x16 c) {
+        // format 0 = e4m3 for both operands; block scales 127 = 2^0
+        return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 127, 0, 127);
+    }
+};
+
+template <int PREC, int KS, int L, int QB>
+__global__ __launch_bounds__(256, 2) void k_screen_lowp(ScreenArgs a) {
+    using Op = LowpOp<PREC>;
+    using T = typename Op::T;
+    constexpr int QW = QB * 32;
+    constexpr int QG = kScreenWaves * QW;
+    constexpr bool kNormInAcc = PREC == RSC_FP8_E4M3;
+
+    __shared__ float2 qbuf[QB * kQueueCap * 256];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1), wave = tid >> 6;
+    const int h = lane >> 5, c = lane & 31;
+    const int p = blockIdx.y;
+    const int64_t blk_per = (a.nblk + a.P - 1) / a.P;
+    const int64_t blk0 = (int64_t)p * blk_per;
+    const int64_t blk1 = std::min<int64_t>(a.nblk, blk0 + blk_per);
+    const int64_t nslots = screen_slots(a);
+    const T *Ap = static_cast<const T *>(a.Ap);
+
+    for (int64_t qblk = blockIdx.x; qblk * QG < nslots; qblk += gridDim.x) {
+        int64_t slot[QB];
+        T bq[QB][KS];
+#pragma unroll
+        for (int qb = 0; qb < QB; ++qb) {
+            slot[qb] = qblk * QG + wave * QW + qb * 32 + c;
+            int64_t row = -1;
+            if (slot[qb] < nslots) row = a.qlist ? (int64_t)a.qlist[slot[qb]] : slot[qb];
+            const float *x = a.Q + (row >= 0 ? row : 0) * a.d;
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                T v;
+                if constexpr (PREC == RSC_BF16) {
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) {
+                        uint32_t two = 0;
+#pragma unroll
+                        for (int q = 0; q < 2; ++q) {
+                            const int kk = 16 * s + 8 * h + 2 * w + q;
+                            float f = 0.f;
+                            if (row >= 0) f = kk < a.d ? -2.f * x[kk] : (kk <= a.d + 1 ? 1.f : 0.f);
+                            two |= bf16_bits(f) << (16 * q);
+                        }
+                        v[w] = (int)two;
+                    }
+                } else {
+#pragma unroll
+                    for (int w = 0; w < 8; ++w) {
+                        uint32_t four = 0;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int kk = 64 * s + 32 * h + 4 * w + q;
+                            uint32_t code = 0;
+                            if (row >= 0 && kk < a.d) code = e4m3_code(x[kk] * a.qscale[a.d + kk]);
+                            four |= code << (8 * q);
+                        }
+                        v[w] = (int)four;
+                    }
+                }
+                bq[qb][s] = v;
+            }
+        }
+
+        LaneTopK<L> top[QB];
+#pragma unroll
+        for (int qb = 0; qb < QB; ++qb) top[qb].init();
+
+        T A[KS] = {};
+        f32x4 nv[4] = {};
+        if (blk0 < blk1) {
+#pragma unroll
+            for (int s = 0; s < KS; ++s) A[s] = Ap[(blk0 * KS + s) * kWave + lane];
+            if constexpr (kNormInAcc) {
+                const f32x4 *ns = reinterpret_cast<const f32x4 *>(a.Np + blk0 * 32 + h * 16);
+#pragma unroll
+                for (int g = 0; g < 4; ++g) nv[g] = ns[g];
+            }
+        }
+
+        for (int64_t blk = blk0; blk < blk1; ++blk) {
+            f32x16 init = f32x16{};
+            if constexpr (kNormInAcc) {
+#pragma unroll
+                for (int v = 0; v < 16; ++v) init[v] = nv[v >> 2][v & 3];
+            }
+            const int64_t nxt = blk + 1 < blk1 ? blk + 1 : blk;  // in bounds, no branch
+            f32x16 acc[QB];
+#pragma unroll
+            for (int qb = 0; qb < QB; ++qb) acc[qb] = init;
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+#pragma unroll
+                for (int qb = 0; qb < QB; ++qb) acc[qb] = Op::mfma(A[s], bq[qb][s], acc[qb]);
+                A[s] = Ap[(nxt * KS + s) * kWave + lane];
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if constexpr (kNormInAcc) {
+                const f32x4 *ns = reinterpret_cast<const f32x4 *>(a.Np + nxt * 32 + h * 16);
+#pragma unroll
+                for (int g = 0; g < 4; ++g) nv[g] = ns[g];
+            }
+            const int ref0 = (int)(blk * 32) + 4 * h;
+#pragma unroll
+            for (int qb = 0; qb < QB; ++qb) top[qb].offer(acc[qb], ref0, qbuf + qb * kQueueCap * 256 + tid, 256);
+        }
+#pragma unroll
+        for (int qb = 0; qb < QB; ++qb) {
+            top[qb].flush(qbuf + qb * kQueueCap * 256 + tid, 256);
+            if (slot[qb] < nslots) top[qb].store(a, slot[qb], p, h);
+        }
+    }
+}
+
+template <int PREC, int KS, int L, int QB>
+int launch_lowp(const ScreenArgs &a, unsigned gx, const char *name, hipStream_t stream) {
+    ScopedTimer timer(name, stream);
+    hipLaunchKernelGGL((k_screen_lowp<PREC, KS, L, QB>), dim3(gx, (unsigned)a.P), dim3(256), 0, stream, a);
+    return launch_status(name);
+}
+
+}  // namespace
+
+int lowp_steps(int precision, int d) {
+    if (precision == RSC_BF16) return (d + 2 + 15) / 16;
+    return (d + 63) / 64;
+}
+
+int lowp_qb(int precision, int d) {
+    (void)precision;
+    (void)d;
+    return kLowpQB;
+}
+
+int lowp_queries_per_group(int precision, int d) { return scr::kScreenWaves * 32 * lowp_qb(precision, d); }
+
+size_t lowp_packed_bytes(int precision, int64_t nblk, int d) {
+    const int ks = lowp_steps(precision, d);
+    return (size_t)nblk * ks * kWave * (precision == RSC_BF16 ? 16 : 32);
+}
+
+int lowp_prepare(const KnnPlan &p, const float *Q, const float *R, void *packed, float *norms, float *scal,
+                 uint32_t *amax, hipStream_t stream) {
+    const int ks = lowp_steps(p.precision, p.d);
+    const int64_t tot = p.nblk * ks * kWave;
+    const unsigned g1 = (unsigned)std::min<int64_t>((tot + 255) / 256, 65536);
+    ScopedTimer timer("prep_pack", stream);
+    if (p.precision == RSC_BF16) {
+        hipLaunchKernelGGL(k_pack_bf16, dim3(g1), dim3(256), 0, stream, R, p.nr, p.d, ks, p.nblk,
+                           static_cast<i32x4 *>(packed));
+        return launch_status("pack_bf16");
+    }
+    // FP8: per-dimension absmax of references (and of queries when distinct)
+    uint32_t *amax_r = amax, *amax_q = amax + 128;
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, stream, amax, 256, 0u);
+    const unsigned ga = (unsigned)std::min<int64_t>((p.nr * p.d + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_absmax, dim3(ga), dim3(256), 0, stream, R, p.nr, p.d, amax_r);
+    if (!p.self_mode && p.nq > 0) {
+        const unsigned gq = (unsigned)std::min<int64_t>((p.nq * p.d + 255) / 256, 2048);
+        hipLaunchKernelGGL(k_absmax, dim3(gq), dim3(256), 0, stream, Q, p.nq, p.d, amax_q);
+    } else {
+        amax_q = amax_r;
+    }
+    hipLaunchKernelGGL(k_fp8_scales, dim3(1), dim3(64), 0, stream, amax_r, amax_q, p.d, scal);
+    hipLaunchKernelGGL(k_pack_fp8, dim3(g1), dim3(256), 0, stream, R, p.nr, p.d, ks, p.nblk, scal,
+                       static_cast<i32x8 *>(packed), norms);
+    return launch_status("pack_fp8");
+}
+
+int lowp_screen(const KnnPlan &p, const scr::ScreenArgs &a, unsigned gx, hipStream_t s) {
+    const int ks = lowp_steps(p.precision, p.d);
+    if (p.precision == RSC_BF16) {
+        switch (ks) {
+            case 1: return launch_lowp<RSC_BF16, 1, 32, kLowpQB>(a, gx, "screen_bf16", s);
+            case 2: return launch_lowp<RSC_BF16, 2, 32, kLowpQB>(a, gx, "screen_bf16", s);
+            case 3: return launch_lowp<RSC_BF16, 3, 32, kLowpQB>(a, gx, "screen_bf16", s);
+            case 4: return launch_lowp<RSC_BF16, 4, 32, kLowpQB>(a, gx, "screen_bf16", s);
+            case 5: return launch_lowp<RSC_BF16, 5, 32, kLowpQB>(a, gx, "screen_bf16", s);
+            case 6: return launch_lowp<RSC_BF16, 6, 32, kLowpQB>(a, gx, "screen_bf16", s);
+            case 7: return launch_lowp<RSC_BF16, 7, 32, kLowpQB>(a, gx, "screen_bf16", s);
+            case 8: return launch_lowp<RSC_BF16, 8, 32, kLowpQB>(a, gx, "screen_bf16", s);
+            case 9: return launch_lowp<RSC_BF16, 9, 32, kLowpQB>(a, gx, "screen_bf16", s);
+            default: break;
+        }
+    } else {
+        switch (ks) {
+            case 1: return launch_lowp<RSC_FP8_E4M3, 1, 32, kLowpQB>(a, gx, "screen_fp8", s);
+            case 2: return launch_lowp<RSC_FP8_E4M3, 2, 32, kLowpQB>(a, gx, "screen_fp8", s);
+            default: break;
+        }
+    }
+    set_error("internal: no reduced-precision screen for this dimension");
+    return RSC_ERR_UNSUPPORTED;
+}
+
+}  // namespace rsc

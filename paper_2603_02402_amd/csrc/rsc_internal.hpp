@@ -71,11 +71,14 @@ struct KnnPlan {
     bool self_mode;        // queries are the references (self forced to slot 0)
     int64_t nblk;          // 32-row reference blocks
     int splits;            // reference ranges of the main screen
+    int precision;         // rsc_precision of the screen
 };
 
 struct KnnBuffers {
     KnnCounters *counters;
     float *nrow, *packed, *norms;
+    float *scal;      // FP8 per-dimension scales
+    uint32_t *amax;   // FP8 per-dimension absmax bits
     int32_t *cand_idx;
     float *cand_key;
     int32_t *flag1, *flag2;
@@ -89,6 +92,18 @@ int knn_plan(int64_t nq, int64_t nr, int d, int k, const rsc_knn_opts *opts, boo
 size_t knn_workspace(const KnnPlan &p, void *ws, KnnBuffers *out);
 int knn_run(const KnnPlan &p, const float *Q, const float *R, int32_t *out_idx, float *out_dist, void *ws,
             hipStream_t stream);
+
+namespace scr {
+struct ScreenArgs;
+}
+// Reduced-precision screens (knn_lowp.hip).
+int lowp_steps(int precision, int d);
+int lowp_qb(int precision, int d);
+int lowp_queries_per_group(int precision, int d);
+size_t lowp_packed_bytes(int precision, int64_t nblk, int d);
+int lowp_prepare(const KnnPlan &p, const float *Q, const float *R, void *packed, float *norms, float *scal,
+                 uint32_t *amax, hipStream_t stream);
+int lowp_screen(const KnnPlan &p, const scr::ScreenArgs &a, unsigned gx, hipStream_t s);
 
 // ---- graph stages (graph.hip) --------------------------------------------
 

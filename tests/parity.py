@@ -145,3 +145,18 @@ def check_graph_properties(indptr, indices, data, n, k, rho=None, sigma=None, di
             g = np.maximum(dist[ok, 1:] - rho[ok, None], 0)
             s = np.exp(-g / sigma[ok, None]).sum(axis=1)
             assert np.abs(s - np.log2(k)).max() <= 1e-6
+
+
+def tie_aware_recall(dist_g, dist_o, k, self_mode=True):
+    """Recall@k of an approximate result with exact distances.
+
+    A returned neighbour counts as a hit when its distance is within the
+    exact k-th distance (x (1 + 1e-5) for near-ties).  ``dist_g`` are the
+    float64-exact distances the rerank returned for the approximate lists;
+    ``dist_o`` the oracle's.  Returns the mean over rows.
+    """
+    first = 1 if self_mode else 0
+    dg = np.asarray(dist_g, dtype=np.float64)[:, first:]
+    dk = np.asarray(dist_o, dtype=np.float64)[:, -1:]
+    hits = (dg <= dk * (1 + NEAR_TIE)).sum(axis=1)
+    return float(np.minimum(hits, k - first).mean() / (k - first))
