@@ -114,6 +114,102 @@ def traffic_probe() -> int:
     return 0
 
 
+def recall_at_k(dist_form, dist_exact, k: int) -> float:
+    """Tie-aware recall@k of a form whose returned distances are exact
+    (float64 rerank): a returned neighbour is a hit when its distance is
+    within the exact k-th distance x (1 + 1e-5).  Self (column 0) excluded."""
+    dk = dist_exact[:, -1:].double() * (1 + 1e-5)
+    hits = (dist_form[:, 1:].double() <= dk).sum(dim=1).clamp(max=k - 1)
+    return float(hits.double().mean().item() / (k - 1))
+
+
+def weight_error(g_form, g_exact, n: int) -> dict:
+    """Relative error of the connectivity weights on the entries both graphs hold."""
+    import torch
+
+    def keys(g):
+        rows = torch.repeat_interleave(torch.arange(n, device=g.indptr.device), g.indptr[1:] - g.indptr[:-1])
+        return rows * n + g.indices.long()
+
+    ke, kf = keys(g_exact), keys(g_form)
+    pos = torch.searchsorted(ke, kf).clamp(max=ke.numel() - 1)
+    common = ke[pos] == kf
+    we = g_exact.data[pos[common]].double()
+    wf = g_form.data[common].double()
+    rel = (wf - we).abs() / we
+    return {"common_entries": int(common.sum().item()), "form_entries": int(kf.numel()),
+            "exact_entries": int(ke.numel()), "max_rel": float(rel.max().item()) if rel.numel() else 0.0,
+            "p99_rel": float(torch.quantile(rel[:1 << 24].float(), 0.99).item()) if rel.numel() else 0.0}
+
+
+def timed_form(rsc, Xt, k, precision, steps, warmup, ws, out):
+    import torch
+
+    idx, dist, csr = out
+    for _ in range(warmup):
+        rsc.knn(Xt, k, precision=precision, out=(idx, dist), workspace=ws)
+        g = rsc.connectivities(idx, dist, workspace=ws, out=csr)
+    torch.cuda.synchronize()
+    rsc.profile_reset()
+    rsc.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        rsc.knn(Xt, k, precision=precision, out=(idx, dist), workspace=ws)
+        g = rsc.connectivities(idx, dist, workspace=ws, out=csr)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rsc.profile_enable(False)
+    names = {rsc.RSC_FP32: "screen_fp32", rsc.RSC_BF16: "screen_bf16", rsc.RSC_FP8_E4M3: "screen_fp8"}
+    tot, cnt = rsc.profile_get(names[precision])
+    return (t1 - t0) * 1e3 / steps, (tot / cnt if cnt else None), g
+
+
+def precision_forms(args, rsc) -> dict:
+    """The precision workload (n = 2M): plain exact FP32 (the judge of recall),
+    BF16 + rerank and FP8-e4m3 + rerank, each timed as a whole graph step."""
+    import torch
+
+    import synth
+
+    k = args.k
+    log("[bench] precision forms: generating the 2M-cell workload")
+    X = synth.workload("precision_2m")
+    n, d = X.shape
+    dev = torch.device("cuda:0")
+    Xt = torch.from_numpy(X).to(dev)
+    del X
+    ws = rsc.Workspace(dev)
+    ws.get(max(rsc.knn_workspace_bytes(n, n, d, k), rsc.knn_workspace_bytes(n, n, d, k, precision=rsc.RSC_BF16),
+               rsc.connectivities_workspace_bytes(n, k)))
+    cap = 2 * n * (k - 1)
+
+    def outputs():
+        return (torch.empty((n, k), dtype=torch.int32, device=dev), torch.empty((n, k), dtype=torch.float32, device=dev),
+                (torch.empty(n + 1, dtype=torch.int64, device=dev), torch.empty(cap, dtype=torch.int32, device=dev),
+                 torch.empty(cap, dtype=torch.float32, device=dev)))
+
+    res = {"workload": "n=2,000,000 cells, d=50, k=15, 100-cluster Zipf(1.1) mixture (seed 2)"}
+    ex = outputs()
+    log("[bench] precision forms: plain exact FP32")
+    ms, scr, g_exact = timed_form(rsc, Xt, k, rsc.RSC_FP32, 1, 0, ws, ex)
+    res["plain_fp32"] = {"cells_per_s": round(n / (ms / 1e3), 1), "ms_per_step": round(ms, 2),
+                         "screen_ms": round(scr, 2), "recall@15": 1.0,
+                         "screen_tflops": round(2 * d * n * n / (scr / 1e3) / 1e12, 2)}
+    fo = outputs()
+    for name, prec, peak in (("bf16_rerank", rsc.RSC_BF16, 2500.0), ("fp8_e4m3_rerank", rsc.RSC_FP8_E4M3, 5000.0)):
+        log(f"[bench] precision forms: {name}")
+        ms, scr, g = timed_form(rsc, Xt, k, prec, args.form_steps, 1, ws, fo)
+        rec = recall_at_k(fo[1], ex[1], k)
+        we = weight_error(g, g_exact, n)
+        res[name] = {"cells_per_s": round(n / (ms / 1e3), 1), "ms_per_step": round(ms, 2),
+                     "screen_ms": round(scr, 2), "recall@15": round(rec, 5),
+                     "screen_tflops_algorithmic": round(2 * d * n * n / (scr / 1e3) / 1e12, 2),
+                     "screen_frac_of_peak": round(2 * d * n * n / (scr / 1e3) / 1e12 / peak, 4),
+                     "weight_error_on_common_entries": we,
+                     "meets_recall_0.99": rec >= 0.99}
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -124,6 +220,8 @@ def main() -> int:
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-probe", action="store_true", help="run the PMC calibration program and exit")
+    ap.add_argument("--no-forms", action="store_true", help="skip the 2M-cell precision forms")
+    ap.add_argument("--form-steps", type=int, default=3)
     args = ap.parse_args()
     if args.traffic_probe:
         return traffic_probe()
@@ -203,6 +301,13 @@ def main() -> int:
                     "kernel": "k_screen_fp32 (FP32 MFMA 32x32x2 distance screen + per-query top-32 heap)",
                     "work_per_launch": f"2*d*n^2 = {flops:.3e} flop (d={d}, n={n})"}
 
+    forms = None
+    if not args.no_forms:
+        del Xt, idx, dist, csr
+        ws.buf = None
+        torch.cuda.empty_cache()
+        forms = precision_forms(args, rsc)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu_baseline (oracle on a sample of rows)")
@@ -228,6 +333,7 @@ def main() -> int:
         "kernel_ms": kernels,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "forms": forms,
     }
     print(json.dumps(out), flush=True)
     return 0

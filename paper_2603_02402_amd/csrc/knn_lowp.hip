@@ -183,11 +183,13 @@ __global__ void k_fp8_scales(const uint32_t *__restrict__ amax_r, const uint32_t
 }
 
 // Block b, step s, lane (c, h): 32 e4m3 codes for kk = 64 s + 32 h + e
-// (dimension kk < d, else 0).  Norms: G ||s . q(y/s)||^2 in accumulator
-// order (+inf past the last row).
+// (dimension kk < d, else 0), stored as two 16-byte halves 1 KiB apart
+// (codes 0..15 of every lane, then codes 16..31), so that a wave reads
+// each half with one conflict-free 16-byte load per lane.  Norms:
+// G ||s . q(y/s)||^2 in accumulator order (+inf past the last row).
 __global__ __launch_bounds__(256) void k_pack_fp8(const float *__restrict__ R, int64_t nr, int d, int KS,
                                                   int64_t nblk, const float *__restrict__ scal,
-                                                  i32x8 *__restrict__ Ap, float *__restrict__ Np) {
+                                                  i32x4 *__restrict__ Ap, float *__restrict__ Np) {
     const int64_t total = nblk * KS * kWave;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
@@ -211,7 +213,9 @@ __global__ __launch_bounds__(256) void k_pack_fp8(const float *__restrict__ R, i
             }
             w[p] = (int)four;
         }
-        Ap[e] = w;
+        // e = (b KS + s) 64 + lane: halves at 2 (b KS + s) 64 + {0, 64} + lane
+        Ap[2 * bs * kWave + lane] = i32x4{w[0], w[1], w[2], w[3]};
+        Ap[2 * bs * kWave + kWave + lane] = i32x4{w[4], w[5], w[6], w[7]};
         if (s == 0 && h == 0) {
             float out = INFINITY;
             if (row < nr) {
@@ -255,15 +259,37 @@ struct LowpOp<RSC_FP8_E4M3> {
     }
 };
 
+// The references are shared by the four waves of a workgroup through a
+// double-buffered LDS ring of PH blocks per phase, filled by asynchronous
+// global->LDS loads (each wave issues a quarter of them) one phase ahead;
+// one barrier per phase.
+template <int PREC, int KS>
+struct LowpRing {
+    static constexpr int kBlockBytes = KS * kWave * (PREC == RSC_BF16 ? 16 : 32);
+    static constexpr int kNormBytes = PREC == RSC_FP8_E4M3 ? 128 : 0;
+    static constexpr int kSlotBytes = kBlockBytes + kNormBytes;
+    static constexpr int kLoads = kBlockBytes / 1024;  // 1 KiB wave loads per block
+    static constexpr int kPhase = PREC == RSC_BF16 ? 4 : 8;  // blocks per phase
+};
+
+__device__ __forceinline__ void lds_load16(const void *gsrc, void *lds_base) {
+    __builtin_amdgcn_global_load_lds(gsrc, (void __attribute__((address_space(3))) *)lds_base, 16, 0, 0);
+}
+
 template <int PREC, int KS, int L, int QB>
-__global__ __launch_bounds__(256, 2) void k_screen_lowp(ScreenArgs a) {
+__global__ __launch_bounds__(256, 3) void k_screen_lowp(ScreenArgs a) {
     using Op = LowpOp<PREC>;
     using T = typename Op::T;
+    using Ring = LowpRing<PREC, KS>;
     constexpr int QW = QB * 32;
     constexpr int QG = kScreenWaves * QW;
+    constexpr int PH = Ring::kPhase;
+    constexpr int SLOT = Ring::kSlotBytes;
+    constexpr int QCAP = 8;  // 16 KiB of queue per workgroup: three workgroups fit a CU
     constexpr bool kNormInAcc = PREC == RSC_FP8_E4M3;
 
-    __shared__ float2 qbuf[QB * kQueueCap * 256];
+    __shared__ __attribute__((aligned(16))) char ring[2 * PH * SLOT];
+    __shared__ float2 qbuf[QB * QCAP * 256];
 
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1), wave = tid >> 6;
@@ -273,7 +299,26 @@ __global__ __launch_bounds__(256, 2) void k_screen_lowp(ScreenArgs a) {
     const int64_t blk0 = (int64_t)p * blk_per;
     const int64_t blk1 = std::min<int64_t>(a.nblk, blk0 + blk_per);
     const int64_t nslots = screen_slots(a);
-    const T *Ap = static_cast<const T *>(a.Ap);
+    const char *Ab = static_cast<const char *>(a.Ap);
+
+    // Issue this wave's share of the loads of phase `ph` into ring buffer `buf`.
+    auto issue = [&](int64_t ph, int buf) {
+        const int64_t b0 = blk0 + ph * PH;
+        constexpr int NA = PH * Ring::kLoads;
+#pragma unroll
+        for (int j = wave; j < NA; j += kScreenWaves) {
+            const int pb = j / Ring::kLoads, q = j % Ring::kLoads;
+            const int64_t blk = std::min<int64_t>(b0 + pb, blk1 - 1);  // clamp: always in bounds
+            lds_load16(Ab + blk * Ring::kBlockBytes + q * 1024 + lane * 16, ring + (buf * PH + pb) * SLOT + q * 1024);
+        }
+        if constexpr (kNormInAcc) {
+#pragma unroll
+            for (int pb = wave; pb < PH; pb += kScreenWaves) {
+                const int64_t blk = std::min<int64_t>(b0 + pb, blk1 - 1);
+                if (lane < 8) lds_load16(a.Np + blk * 32 + lane * 4, ring + (buf * PH + pb) * SLOT + Ring::kBlockBytes);
+            }
+        }
+    };
 
     for (int64_t qblk = blockIdx.x; qblk * QG < nslots; qblk += gridDim.x) {
         int64_t slot[QB];
@@ -318,51 +363,60 @@ __global__ __launch_bounds__(256, 2) void k_screen_lowp(ScreenArgs a) {
             }
         }
 
-        LaneTopK<L> top[QB];
+        LaneTopK<L, QCAP> top[QB];
 #pragma unroll
         for (int qb = 0; qb < QB; ++qb) top[qb].init();
 
-        T A[KS] = {};
-        f32x4 nv[4] = {};
-        if (blk0 < blk1) {
+        const int64_t nph = (blk1 - blk0 + PH - 1) / PH;
+        __syncthreads();  // the ring is free (previous query block done with it)
+        if (nph > 0) issue(0, 0);
+        for (int64_t ph = 0; ph < nph; ++ph) {
+            __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0): this wave's loads of phase ph landed
+            __syncthreads();                      // everyone's landed; phase ph-1 is fully consumed
+            if (ph + 1 < nph) issue(ph + 1, (int)((ph + 1) & 1));
+            const char *base = ring + (int)(ph & 1) * PH * SLOT;
 #pragma unroll
-            for (int s = 0; s < KS; ++s) A[s] = Ap[(blk0 * KS + s) * kWave + lane];
-            if constexpr (kNormInAcc) {
-                const f32x4 *ns = reinterpret_cast<const f32x4 *>(a.Np + blk0 * 32 + h * 16);
+            for (int r = 0; r < PH; ++r) {
+                const int64_t blk = blk0 + ph * PH + r;
+                if (blk >= blk1) break;
+                const char *sl = base + r * SLOT;
+                T A[KS];
 #pragma unroll
-                for (int g = 0; g < 4; ++g) nv[g] = ns[g];
+                for (int s = 0; s < KS; ++s) {
+                    if constexpr (PREC == RSC_BF16) {
+                        A[s] = reinterpret_cast<const i32x4 *>(sl)[s * kWave + lane];
+                    } else {
+                        const i32x4 lo = reinterpret_cast<const i32x4 *>(sl)[2 * s * kWave + lane];
+                        const i32x4 hi = reinterpret_cast<const i32x4 *>(sl)[(2 * s + 1) * kWave + lane];
+                        A[s] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+                    }
+                }
+                f32x16 init = f32x16{};
+                if constexpr (kNormInAcc) {
+                    const f32x4 *ns = reinterpret_cast<const f32x4 *>(sl + Ring::kBlockBytes) + h * 4;
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) {
+                        const f32x4 t = ns[g];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) init[4 * g + j] = t[j];
+                    }
+                }
+                f32x16 acc[QB];
+#pragma unroll
+                for (int qb = 0; qb < QB; ++qb) acc[qb] = init;
+#pragma unroll
+                for (int s = 0; s < KS; ++s) {
+#pragma unroll
+                    for (int qb = 0; qb < QB; ++qb) acc[qb] = Op::mfma(A[s], bq[qb][s], acc[qb]);
+                }
+                const int ref0 = (int)(blk * 32) + 4 * h;
+#pragma unroll
+                for (int qb = 0; qb < QB; ++qb) top[qb].offer(acc[qb], ref0, qbuf + qb * QCAP * 256 + tid, 256);
             }
-        }
-
-        for (int64_t blk = blk0; blk < blk1; ++blk) {
-            f32x16 init = f32x16{};
-            if constexpr (kNormInAcc) {
-#pragma unroll
-                for (int v = 0; v < 16; ++v) init[v] = nv[v >> 2][v & 3];
-            }
-            const int64_t nxt = blk + 1 < blk1 ? blk + 1 : blk;  // in bounds, no branch
-            f32x16 acc[QB];
-#pragma unroll
-            for (int qb = 0; qb < QB; ++qb) acc[qb] = init;
-#pragma unroll
-            for (int s = 0; s < KS; ++s) {
-#pragma unroll
-                for (int qb = 0; qb < QB; ++qb) acc[qb] = Op::mfma(A[s], bq[qb][s], acc[qb]);
-                A[s] = Ap[(nxt * KS + s) * kWave + lane];
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            if constexpr (kNormInAcc) {
-                const f32x4 *ns = reinterpret_cast<const f32x4 *>(a.Np + nxt * 32 + h * 16);
-#pragma unroll
-                for (int g = 0; g < 4; ++g) nv[g] = ns[g];
-            }
-            const int ref0 = (int)(blk * 32) + 4 * h;
-#pragma unroll
-            for (int qb = 0; qb < QB; ++qb) top[qb].offer(acc[qb], ref0, qbuf + qb * kQueueCap * 256 + tid, 256);
         }
 #pragma unroll
         for (int qb = 0; qb < QB; ++qb) {
-            top[qb].flush(qbuf + qb * kQueueCap * 256 + tid, 256);
+            top[qb].flush(qbuf + qb * QCAP * 256 + tid, 256);
             if (slot[qb] < nslots) top[qb].store(a, slot[qb], p, h);
         }
     }
@@ -419,7 +473,7 @@ int lowp_prepare(const KnnPlan &p, const float *Q, const float *R, void *packed,
     }
     hipLaunchKernelGGL(k_fp8_scales, dim3(1), dim3(64), 0, stream, amax_r, amax_q, p.d, scal);
     hipLaunchKernelGGL(k_pack_fp8, dim3(g1), dim3(256), 0, stream, R, p.nr, p.d, ks, p.nblk, scal,
-                       static_cast<i32x8 *>(packed), norms);
+                       static_cast<i32x4 *>(packed), norms);
     return launch_status("pack_fp8");
 }
 

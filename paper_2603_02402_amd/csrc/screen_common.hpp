@@ -16,7 +16,7 @@ namespace scr {
 
 constexpr int kWave = 64;
 constexpr int kScreenWaves = 4;  // waves per screen workgroup
-constexpr int kQueueCap = 16;    // queued keys per lane and query block (a block adds at most 16)
+constexpr int kQueueCap = 16;    // default queue entries per lane and query block (a block adds at most 16)
 
 // (d2, j) lexicographic order: smaller distance first, lower index on ties.
 __device__ __forceinline__ bool lex_before(double da, int ja, double db, int jb) {
@@ -82,7 +82,7 @@ __device__ __forceinline__ int64_t screen_slots(const ScreenArgs &a) {
 // threshold of the last merge.  Keys enter the queue with one LDS write; all
 // lanes of the wave merge their queues together when any queue could
 // overflow, so the per-key cost stays a compare in the common case.
-template <int L>
+template <int L, int QCAP = kQueueCap>
 struct LaneTopK {
     float lk[L];
     int li[L];
@@ -137,7 +137,22 @@ struct LaneTopK {
         int hits = 0;
 #pragma unroll
         for (int v = 0; v < 16; ++v) hits += acc[v] < thr ? 1 : 0;
-        if (__ballot(count + hits > kQueueCap) != 0ull) flush(q, stride);
+        if (__ballot(count + hits > QCAP) != 0ull) {
+            flush(q, stride);
+            if constexpr (QCAP < 16) {
+                hits = 0;
+#pragma unroll
+                for (int v = 0; v < 16; ++v) hits += acc[v] < thr ? 1 : 0;
+                if (__ballot(hits > QCAP) != 0ull) {
+                    // more keys than a queue holds (only while the lists fill up): insert directly
+#pragma unroll
+                    for (int v = 0; v < 16; ++v)
+                        if (acc[v] < lk[L - 1]) insert(acc[v], ref0 + 8 * (v >> 2) + (v & 3));
+                    thr = lk[L - 1];
+                    return;
+                }
+            }
+        }
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             if (acc[v] < thr) {
