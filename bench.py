@@ -210,6 +210,57 @@ def precision_forms(args, rsc) -> dict:
     return res
 
 
+def batched_form(args, rsc) -> dict:
+    """64 independent samples (log-uniform 2k..200k cells, 10-40 clusters each):
+    per-sample exact kNN in one persistent launch + connectivities."""
+    import torch
+
+    import synth
+
+    k = args.k
+    log("[bench] batched form: generating 64 samples")
+    X, off = synth.batched_samples()
+    n, d = X.shape
+    dev = torch.device("cuda:0")
+    Xt = torch.from_numpy(X).to(dev)
+    del X
+    ws = rsc.Workspace(dev)
+    ws.get(max(rsc.knn_batched_workspace_bytes(off, d, k), rsc.connectivities_workspace_bytes(n, k)))
+    cap = 2 * n * (k - 1)
+    idx = torch.empty((n, k), dtype=torch.int32, device=dev)
+    dist = torch.empty((n, k), dtype=torch.float32, device=dev)
+    csr = (torch.empty(n + 1, dtype=torch.int64, device=dev), torch.empty(cap, dtype=torch.int32, device=dev),
+           torch.empty(cap, dtype=torch.float32, device=dev))
+    log("[bench] batched form: autotune")
+    chosen, table = rsc.knn_batched_autotune(Xt, off, k, workspace=ws)
+    for _ in range(1):
+        rsc.knn_batched(Xt, off, k, out=(idx, dist), workspace=ws)
+        rsc.connectivities(idx, dist, workspace=ws, out=csr)
+    torch.cuda.synchronize()
+    rsc.profile_reset()
+    rsc.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.form_steps):
+        rsc.knn_batched(Xt, off, k, out=(idx, dist), workspace=ws)
+        stats = rsc.read_knn_stats(ws)
+        g = rsc.connectivities(idx, dist, workspace=ws, out=csr)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rsc.profile_enable(False)
+    ms = (t1 - t0) * 1e3 / args.form_steps
+    tot, cnt = rsc.profile_get("screen_batched")
+    scr = tot / cnt
+    sizes = np.diff(off)
+    flops = float(2 * d * (sizes.astype(np.float64) ** 2).sum())
+    return {"workload": f"64 samples, {n} cells, sizes log-uniform in [2000, 200000] (seed 4), d=50, k=15",
+            "cells_per_s": round(n / (ms / 1e3), 1), "ms_per_step": round(ms, 2), "screen_ms": round(scr, 2),
+            "screen_tflops": round(flops / (scr / 1e3) / 1e12, 2),
+            "screen_frac_of_fp32_peak": round(flops / (scr / 1e3) / 1e12 / PEAK_FP32_TFLOPS, 4),
+            "autotune_choice": chosen, "autotune_screen_ms": {kk: round(v, 2) for kk, v in table.items()},
+            "escalated_rows": stats["escalated_rows"], "rescanned_rows": stats["rescanned_rows"], "nnz": int(g.nnz),
+            "exact": True}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -307,6 +358,8 @@ def main() -> int:
         ws.buf = None
         torch.cuda.empty_cache()
         forms = precision_forms(args, rsc)
+        torch.cuda.empty_cache()
+        forms["batched_fp32"] = batched_form(args, rsc)
 
     cpu = None
     if not args.no_cpu_baseline:

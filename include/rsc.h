@@ -144,6 +144,45 @@ int rsc_knn_ex(const float *Q, int64_t n_query, const float *R, int64_t n_ref, i
 int rsc_knn_read_stats(const void *workspace, size_t workspace_bytes, rsc_knn_stats *out, void *stream);
 
 /* ---------------------------------------------------------------------- */
+/* Batched exact kNN (many independent samples, one persistent launch)     */
+/* ---------------------------------------------------------------------- */
+
+/* Number of scheduling policies the batched autotuner measures. */
+#define RSC_BATCH_POLICIES 6
+
+/*
+ * A batch is S samples stored back to back in one matrix X: sample s is rows
+ * offsets[s] .. offsets[s+1]-1 (offsets is a HOST int64 array of S+1
+ * entries, offsets[0] = 0, every sample at least k rows, total <= 2^31-2).
+ * Each sample is its own exact kNN problem (the paper analyses large
+ * collections chunk by chunk along the cell axis: Methods, "Memory
+ * management and scaling"); results use global row ids, so the kNN graph is
+ * block-diagonal and rsc_connectivities applied to the whole output gives the
+ * per-sample connectivities at once.
+ */
+size_t rsc_knn_batched_workspace_bytes(const int64_t *offsets, int32_t S, int32_t d, int32_t k);
+
+/* Exact kNN of every sample (same output layout and exactness as rsc_knn,
+ * neighbours drawn from the row's own sample).  Uses the scheduling policy
+ * the autotuner chose for this batch shape, else a default.  Synchronises
+ * `stream` once (to upload the work list into the workspace). */
+int rsc_knn_batched(const float *X, const int64_t *offsets, int32_t S, int32_t d, int32_t k, int32_t *out_idx,
+                    float *out_dist, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Time every scheduling policy on this batch (screen only, HIP events) and
+ * remember the fastest for batches of the same shape (device, d, k and the
+ * histogram of log2 sample sizes); with RSC_AUTOTUNE_CACHE=<file> in the
+ * environment the choice is also read from / written to that file.
+ * chosen (host, may be NULL): the policy index; times_ms (host, may be NULL):
+ * RSC_BATCH_POLICIES measured times.  Synchronises `stream`. */
+int rsc_knn_batched_autotune(const float *X, const int64_t *offsets, int32_t S, int32_t d, int32_t k,
+                             void *workspace, size_t workspace_bytes, void *stream, int32_t *chosen,
+                             float *times_ms);
+
+/* Human-readable description of a policy index ("" if out of range). */
+const char *rsc_batch_policy_name(int32_t policy);
+
+/* ---------------------------------------------------------------------- */
 /* Connectivities (fuzzy simplicial set)                                   */
 /* ---------------------------------------------------------------------- */
 

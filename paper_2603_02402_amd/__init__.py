@@ -20,7 +20,8 @@ from ._lib import RSC_BF16, RSC_FP8_E4M3, RSC_FP32, KnnOpts, KnnStats, RscError,
 __all__ = [
     "knn", "knn_graph", "connectivities", "knn_workspace_bytes", "connectivities_workspace_bytes",
     "read_knn_stats", "profile_enable", "profile_reset", "profile_get", "RscError", "Workspace",
-    "RSC_FP32", "RSC_BF16", "RSC_FP8_E4M3", "abi_version",
+    "RSC_FP32", "RSC_BF16", "RSC_FP8_E4M3", "abi_version", "knn_batched", "knn_batched_autotune",
+    "knn_batched_workspace_bytes",
 ]
 
 
@@ -178,6 +179,56 @@ def knn_graph(X, k: int, workspace: Workspace | None = None):
     idx, dist = knn(X, k, workspace=ws)
     g = connectivities(idx, dist, workspace=ws)
     return idx, dist, g
+
+
+def _host_offsets(offsets):
+    import numpy as np
+
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    return off, off.ctypes.data_as(ctypes.c_void_p)
+
+
+def knn_batched_workspace_bytes(offsets, d: int, k: int) -> int:
+    off, p = _host_offsets(offsets)
+    return int(load().rsc_knn_batched_workspace_bytes(p, len(off) - 1, d, k))
+
+
+def knn_batched(X, offsets, k: int, out=None, workspace: Workspace | None = None):
+    """Exact kNN of every sample of a batch (rows ``offsets[s]..offsets[s+1]-1``
+    of ``X``; ``offsets`` on the host).  Returns global-row ``(idx, dist)``."""
+    torch = _torch()
+    _check_dev(X)
+    n, d = X.shape
+    off, p = _host_offsets(offsets)
+    S = len(off) - 1
+    lib = load()
+    need = lib.rsc_knn_batched_workspace_bytes(p, S, d, k)
+    ws = (workspace or Workspace(X.device)).get(need if need else 256)
+    if out is None:
+        idx = torch.empty((n, k), dtype=torch.int32, device=X.device)
+        dist = torch.empty((n, k), dtype=torch.float32, device=X.device)
+    else:
+        idx, dist = out
+    check(lib.rsc_knn_batched(_ptr(X), p, S, d, k, _ptr(idx), _ptr(dist), _ptr(ws), ws.numel(), _stream()))
+    return idx, dist
+
+
+def knn_batched_autotune(X, offsets, k: int, workspace: Workspace | None = None):
+    """Measure the batched scheduling policies on this batch; returns
+    ``(chosen_index, {policy_name: ms})``."""
+    _check_dev(X)
+    n, d = X.shape
+    off, p = _host_offsets(offsets)
+    S = len(off) - 1
+    lib = load()
+    need = lib.rsc_knn_batched_workspace_bytes(p, S, d, k)
+    ws = (workspace or Workspace(X.device)).get(need if need else 256)
+    chosen = ctypes.c_int32(-1)
+    times = (ctypes.c_float * _lib.RSC_BATCH_POLICIES)()
+    check(lib.rsc_knn_batched_autotune(_ptr(X), p, S, d, k, _ptr(ws), ws.numel(), _stream(), ctypes.byref(chosen),
+                                       times))
+    names = [lib.rsc_batch_policy_name(i).decode() for i in range(_lib.RSC_BATCH_POLICIES)]
+    return int(chosen.value), dict(zip(names, [float(t) for t in times]))
 
 
 def profile_enable(on: bool = True) -> None:

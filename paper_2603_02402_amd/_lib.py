@@ -28,6 +28,7 @@ STATUS_NAMES = {
     -8: "RSC_ERR_BAD_GRAPH",
 }
 RSC_FP32, RSC_BF16, RSC_FP8_E4M3 = 0, 1, 2
+RSC_BATCH_POLICIES = 6
 
 # Every symbol include/rsc.h declares, with (restype, argtypes).
 _P = ctypes.c_void_p
@@ -55,6 +56,10 @@ SIGNATURES = {
     "rsc_knn_opt": (ctypes.c_int, [_P, _I64, _I32, _I32, _P, _P, _P, _P, _SZ, _P]),
     "rsc_knn_ex": (ctypes.c_int, [_P, _I64, _P, _I64, _I32, _I32, _P, _P, _P, _P, _SZ, _P]),
     "rsc_knn_read_stats": (ctypes.c_int, [_P, _SZ, _P, _P]),
+    "rsc_knn_batched_workspace_bytes": (_SZ, [_P, _I32, _I32, _I32]),
+    "rsc_knn_batched": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, _P, _P, _P, _SZ, _P]),
+    "rsc_knn_batched_autotune": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, _P, _SZ, _P, _P, _P]),
+    "rsc_batch_policy_name": (ctypes.c_char_p, [_I32]),
     "rsc_connectivities_workspace_bytes": (_SZ, [_I64, _I32]),
     "rsc_connectivities": (ctypes.c_int, [_P, _P, _I64, _I32, _P, _P, _P, _I64, _P, _P, _P, _P, _SZ, _P]),
     "rsc_profile_enable": (ctypes.c_int, [ctypes.c_int]),

@@ -180,6 +180,48 @@ int rsc_knn_read_stats(const void *workspace, size_t workspace_bytes, rsc_knn_st
     return RSC_OK;
 }
 
+size_t rsc_knn_batched_workspace_bytes(const int64_t *offsets, int32_t S, int32_t d, int32_t k) {
+    if (d < 1 || d > 128 || k < 1 || k > 63) return 0;
+    return batched_workspace_bytes(offsets, S, d, k);
+}
+
+int rsc_knn_batched(const float *X, const int64_t *offsets, int32_t S, int32_t d, int32_t k, int32_t *out_idx,
+                    float *out_dist, void *workspace, size_t workspace_bytes, void *stream) {
+    clear_error();
+    if (d < 1 || k < 1) {
+        set_error("need d >= 1 and k >= 1");
+        return RSC_ERR_INVALID_ARG;
+    }
+    if (d > 128 || k > 63) {
+        set_error("d > 128 or k > 63 is not supported by this build");
+        return RSC_ERR_UNSUPPORTED;
+    }
+    if (!aligned(X, 4) || !aligned(out_idx, 4) || !aligned(out_dist, 4) || !aligned(workspace, 256)) {
+        set_error("misaligned array or workspace");
+        return RSC_ERR_INVALID_ARG;
+    }
+    return batched_run(X, offsets, S, d, k, out_idx, out_dist, workspace, workspace_bytes,
+                       static_cast<hipStream_t>(stream));
+}
+
+int rsc_knn_batched_autotune(const float *X, const int64_t *offsets, int32_t S, int32_t d, int32_t k,
+                             void *workspace, size_t workspace_bytes, void *stream, int32_t *chosen,
+                             float *times_ms) {
+    clear_error();
+    if (d < 1 || k < 1 || d > 128 || k > 63) {
+        set_error("need 1 <= d <= 128 and 1 <= k <= 63");
+        return RSC_ERR_INVALID_ARG;
+    }
+    if (!aligned(X, 4) || !aligned(workspace, 256)) {
+        set_error("misaligned array or workspace");
+        return RSC_ERR_INVALID_ARG;
+    }
+    return batched_autotune(X, offsets, S, d, k, workspace, workspace_bytes, static_cast<hipStream_t>(stream),
+                            chosen, times_ms);
+}
+
+const char *rsc_batch_policy_name(int32_t policy) { return batched_policy_name(policy); }
+
 size_t rsc_connectivities_workspace_bytes(int64_t n, int32_t k) {
     if (n < 1 || k < 1 || k > n || n > INT32_MAX - 1) return 0;
     return graph_workspace_bytes(n, k);

@@ -42,6 +42,7 @@
 
 #include "rsc_internal.hpp"
 #include "screen_common.hpp"
+#include "screen_fp32.hpp"
 
 namespace rsc {
 
@@ -55,11 +56,6 @@ constexpr int kRescanMax = 64;      // list capacity of the exhaustive rescan
 constexpr int kEscalateCap = 8192;  // rows handled by the escalation screen
 constexpr int kEscalateSplits = 16;
 constexpr int kEscalateWidth = 64;
-
-// Whether the contraction half-width DH leaves a spare slot in its last
-// float4 for the reference norm (the common d = 49, 50 case: DH = 25).
-__host__ __device__ constexpr bool norm_folded(int DH) { return (DH % 4) != 0; }
-__host__ __device__ constexpr int packed_s4(int DH) { return (DH + (norm_folded(DH) ? 1 : 0) + 3) / 4; }
 
 // Squared norms of the reference rows (float64 sum, rounded once) and the
 // largest norm.
@@ -90,7 +86,9 @@ __global__ __launch_bounds__(256) void k_norms(const float *__restrict__ R, int6
 // so that MFMA step s of a wave reads 1 KiB of lane-contiguous data.
 __global__ __launch_bounds__(256) void k_pack(const float *__restrict__ R, const float *__restrict__ nrow, int64_t nr,
                                               int d, int DH, int S4, int folded, int64_t nblk,
-                                              f32x4 *__restrict__ Ap, float *__restrict__ Np) {
+                                              f32x4 *__restrict__ Ap, float *__restrict__ Np,
+                                              const int32_t *__restrict__ blk_sample, const int64_t *__restrict__ boff,
+                                              const int64_t *__restrict__ soff) {
     const int64_t total = nblk * S4 * kWave;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
@@ -98,7 +96,15 @@ __global__ __launch_bounds__(256) void k_pack(const float *__restrict__ R, const
         const int64_t bs = e / kWave;
         const int s4 = (int)(bs % S4);
         const int64_t b = bs / S4;
-        const int64_t row = 32 * b + (lane & 31);
+        // row of lane (c, h); batched: blocks of sample s start at boff[s] and
+        // hold rows soff[s]..soff[s+1]-1 (the last block of a sample is padded)
+        int64_t row = 32 * b + (lane & 31), row_end = nr;
+        if (blk_sample) {
+            const int smp = blk_sample[b];
+            row = soff[smp] + 32 * (b - boff[smp]) + (lane & 31);
+            row_end = soff[smp + 1];
+        }
+        const bool live = row < row_end;
         const int h = lane >> 5;
         f32x4 v;
         const int off = folded ? 1 : 0;  // the norm occupies step 0 when folded
@@ -109,9 +115,9 @@ __global__ __launch_bounds__(256) void k_pack(const float *__restrict__ R, const
             const int t = h * DH + sd;
             float x = 0.f;
             if (folded && s == 0) {
-                if (h == 0) x = row < nr ? nrow[row] : INFINITY;
+                if (h == 0) x = live ? nrow[row] : INFINITY;
             } else if (sd < DH) {
-                if (row < nr && t < d) x = R[row * d + t];
+                if (live && t < d) x = R[row * d + t];
             }
             v[u] = x;
         }
@@ -121,7 +127,7 @@ __global__ __launch_bounds__(256) void k_pack(const float *__restrict__ R, const
             if (h == 0) {
                 const int i = lane & 31;
                 const int g = i >> 3, hh = (i >> 2) & 1, j = i & 3;
-                Np[b * 32 + hh * 16 + 4 * g + j] = row < nr ? nrow[row] : INFINITY;
+                Np[b * 32 + hh * 16 + 4 * g + j] = live ? nrow[row] : INFINITY;
             }
         }
     }
@@ -151,108 +157,23 @@ __global__ void k_init_counters(KnnCounters *c) {
 // Output: cand[(slot * 2P + 2p + h) * L + i], i-th smallest key of half h
 // of range p (index -1 / key +inf where fewer than L were seen).
 // ---------------------------------------------------------------------------
-// Occupancy target (waves per SIMD) that the register budget of a screen
-// instantiation allows without spilling.
-__host__ __device__ constexpr int screen_min_waves(int DH, int L) { return (DH <= 25 && L == 16) ? 3 : 2; }
-
-// Load float4 group s4 of a packed block (wave-uniform base wb).  A partial
-// last group (STEPS not a multiple of 4) is fetched with a narrower load so
-// that no dead register half is left pending under a load.
-template <int STEPS, int S4>
-__device__ __forceinline__ void load_group(f32x4 (&A)[S4], const f32x4 *wb, int s4, int lane) {
-    constexpr int REM = STEPS - 4 * (S4 - 1);
-    if (s4 < S4 - 1 || REM >= 3) {
-        A[s4] = wb[s4 * kWave + lane];
-    } else if (REM == 2) {
-        const float2 t = reinterpret_cast<const float2 *>(wb + s4 * kWave + lane)[0];
-        A[s4][0] = t.x;
-        A[s4][1] = t.y;
-    } else {
-        A[s4][0] = reinterpret_cast<const float *>(wb + s4 * kWave + lane)[0];
-    }
-}
-
 template <int DH, int L>
 __global__ __launch_bounds__(256, screen_min_waves(DH, L)) void k_screen_fp32(ScreenArgs a) {
-    constexpr bool NF = norm_folded(DH);
-    constexpr int STEPS = DH + (NF ? 1 : 0);
-    constexpr int S4 = packed_s4(DH);
-    constexpr int QG = kScreenWaves * 32;
-    // Per-lane queue of keys that beat the lane's threshold, entry-major so
-    // that lanes appending their e-th entry touch consecutive words.
+    // Per-lane queue of keys that beat the lane's threshold (see LaneTopK).
     __shared__ float2 qbuf[kQueueCap * 256];
-
+    constexpr int QG = kScreenWaves * 32;
     const int tid = threadIdx.x;
-    const int lane = tid & (kWave - 1), wave = tid >> 6;
-    const int h = lane >> 5, c = lane & 31;
+    const int wave = tid >> 6, c = tid & 31;
     const int p = blockIdx.y;
     const int64_t blk_per = (a.nblk + a.P - 1) / a.P;
     const int64_t blk0 = (int64_t)p * blk_per;
     const int64_t blk1 = std::min<int64_t>(a.nblk, blk0 + blk_per);
     const int64_t nslots = screen_slots(a);
-    const f32x4 *Ap = static_cast<const f32x4 *>(a.Ap);
-
     for (int64_t qblk = blockIdx.x; qblk * QG < nslots; qblk += gridDim.x) {
         const int64_t slot = qblk * QG + wave * 32 + c;
         int64_t row = -1;
         if (slot < nslots) row = a.qlist ? (int64_t)a.qlist[slot] : slot;
-
-        // Query operand, resident for the whole range; -2 folded in (exact).
-        constexpr int OFF = NF ? 1 : 0;  // step 0 carries the norm when folded
-        float b[STEPS];
-#pragma unroll
-        for (int s = 0; s < DH; ++s) {
-            const int t = h * DH + s;
-            b[OFF + s] = (row >= 0 && t < a.d) ? -2.f * a.Q[row * a.d + t] : 0.f;
-        }
-        if constexpr (NF) b[0] = (row >= 0 && h == 0) ? 1.f : 0.f;
-
-        LaneTopK<L> top;
-        top.init();
-        float2 *q = qbuf + tid;
-
-        f32x4 A[S4] = {};
-        if (blk0 < blk1) {
-            const f32x4 *wb0 = Ap + blk0 * (S4 * kWave);
-#pragma unroll
-            for (int s4 = 0; s4 < S4; ++s4) {
-                load_group<STEPS, S4>(A, wb0, s4, lane);
-                __builtin_amdgcn_sched_barrier(0);  // issue in group order, as the loop does
-            }
-        }
-
-        for (int64_t blk = blk0; blk < blk1; ++blk) {
-            f32x4 nv[4];
-            if constexpr (!NF) {
-                const f32x4 *ns = reinterpret_cast<const f32x4 *>(a.Np + blk * 32 + h * 16);
-#pragma unroll
-                for (int g = 0; g < 4; ++g) nv[g] = ns[g];
-            }
-            // Next block (the last block re-reads itself: always in bounds,
-            // so the loads need no branch and stay in flight across the MFMAs).
-            const int64_t nxt = blk + 1 < blk1 ? blk + 1 : blk;
-            const f32x4 *wb = Ap + nxt * (S4 * kWave);
-            f32x16 acc = f32x16{};
-#pragma unroll
-            for (int s4 = 0; s4 < S4; ++s4) {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int s = 4 * s4 + u;
-                    if (s < STEPS) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(A[s4][u], b[s], acc, 0, 0, 0);
-                }
-                load_group<STEPS, S4>(A, wb, s4, lane);  // consumed: fetch its successor
-                // keep each load right behind the MFMAs that freed its registers
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            if constexpr (!NF) {
-#pragma unroll
-                for (int v = 0; v < 16; ++v) acc[v] += nv[v >> 2][v & 3];
-            }
-
-            top.offer(acc, (int)(blk * 32) + 4 * h, q, 256);
-        }
-        top.flush(q, 256);
-        if (slot < nslots) top.store(a, slot, p, h);
+        screen_fp32_tile<DH, L>(a, slot < nslots ? slot : -1, row, blk0, blk1, p, 0, qbuf);
     }
 }
 
@@ -261,25 +182,6 @@ __global__ __launch_bounds__(256, screen_min_waves(DH, L)) void k_screen_fp32(Sc
 // are streamed 64 at a time; the m best (d2, j) are kept sorted across the
 // lanes (lane i = i-th smallest) by bitonic sort + merge.
 // ---------------------------------------------------------------------------
-struct RerankArgs {
-    const float *Q;
-    int64_t nq;
-    const int32_t *qlist;   // optional: slot -> row
-    const int32_t *qcount;
-    int qcap;
-    const float *R;
-    int d, k, S, KP, P;
-    int self_mode;
-    int certify;            // 0: approximate screen, never flag rows
-    const int32_t *cand_idx;
-    const float *cand_key;
-    double eps_coef;
-    KnnCounters *counters;
-    int32_t *flag_out;   // rows that fail the certificate
-    int32_t *flag_count;
-    int32_t *out_idx;
-    float *out_dist;
-};
 
 __device__ __forceinline__ void bitonic_sort64(double &d2, int &jj, int lane) {
 #pragma unroll
@@ -428,7 +330,8 @@ __global__ __launch_bounds__(64) void k_rescan(const float *__restrict__ Q, cons
                                                const int32_t *__restrict__ count1, int cap1,
                                                const int32_t *__restrict__ list2,
                                                const int32_t *__restrict__ count2, int32_t *__restrict__ out_idx,
-                                               float *__restrict__ out_dist, KnnCounters *__restrict__ counters) {
+                                               float *__restrict__ out_dist, KnnCounters *__restrict__ counters,
+                                               const int64_t *__restrict__ soff, int nsamples) {
     __shared__ double ld[kRescanMax * kWave];
     __shared__ int lj[kRescanMax * kWave];
     const int lane = threadIdx.x;
@@ -440,11 +343,22 @@ __global__ __launch_bounds__(64) void k_rescan(const float *__restrict__ Q, cons
     for (int f = blockIdx.x; f < count; f += gridDim.x) {
         const int64_t q = f < c2 ? list2[f] : list1[cap1 + (f - c2)];
         const float *x = Q + q * d;
+        // references: all rows, or the rows of q's own sample (batched form)
+        int64_t j0 = 0, j1 = nr;
+        if (soff) {
+            int lo = 0, hi = nsamples - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) / 2;
+                if (soff[mid] <= q) lo = mid; else hi = mid - 1;
+            }
+            j0 = soff[lo];
+            j1 = soff[lo + 1];
+        }
         for (int s = 0; s < m; ++s) {
             ld[s * kWave + lane] = INFINITY;
             lj[s * kWave + lane] = INT_MAX;
         }
-        for (int64_t j = lane; j < nr; j += kWave) {
+        for (int64_t j = j0 + lane; j < j1; j += kWave) {
             if (self_mode && j == q) continue;
             const double v = exact_d2(x, R + j * d, d);
             if (m > 0 && lex_before(v, (int)j, ld[(m - 1) * kWave + lane], lj[(m - 1) * kWave + lane])) {
@@ -538,6 +452,41 @@ int pick_splits(int64_t nq, int64_t nblk, int qg) {
 }
 
 }  // namespace
+
+// Error bound of the float32 key (the norm enters the MFMA sum or is added
+// after it; norms rounded once from float64): 2 (d + 3) units of roundoff
+// times (2 ||x|| ||y|| + ||y||^2).
+double knn_eps_coefficient(int d) { return 2.0 * (d + 3) * std::ldexp(1.0, -24); }
+
+int knn_prep_fp32(const KnnPlan &p, const float *R, const KnnBuffers &b, const int32_t *blk_sample,
+                  const int64_t *boff, const int64_t *soff, hipStream_t stream) {
+    const int s4 = packed_s4(p.dh);
+    ScopedTimer timer("prep_pack", stream);
+    hipLaunchKernelGGL(k_init_counters, dim3(1), dim3(64), 0, stream, b.counters);
+    hipLaunchKernelGGL(k_norms, dim3((unsigned)((p.nr + 255) / 256)), dim3(256), 0, stream, R, p.nr, p.d, b.nrow,
+                       &b.counters->max_norm_bits);
+    const int64_t tot = p.nblk * s4 * kWave;
+    const unsigned g1 = (unsigned)std::min<int64_t>((tot + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_pack, dim3(g1), dim3(256), 0, stream, R, b.nrow, p.nr, p.d, p.dh, s4,
+                       norm_folded(p.dh) ? 1 : 0, p.nblk, reinterpret_cast<f32x4 *>(b.packed), b.norms, blk_sample,
+                       boff, soff);
+    return launch_status("prep_pack");
+}
+
+int knn_launch_rerank(const RerankArgs &ra, int64_t slots, const char *name, hipStream_t stream) {
+    ScopedTimer timer(name, stream);
+    hipLaunchKernelGGL(k_rerank, dim3((unsigned)((slots + 3) / 4)), dim3(256), 0, stream, ra);
+    return launch_status(name);
+}
+
+int knn_launch_rescan(const KnnPlan &p, const float *Q, const float *R, const KnnBuffers &b, int esc_cap,
+                      int32_t *out_idx, float *out_dist, const int64_t *soff, int nsamples, hipStream_t stream) {
+    ScopedTimer timer("rescan", stream);
+    hipLaunchKernelGGL(k_rescan, dim3(1024), dim3(64), 0, stream, Q, R, p.nr, p.d, p.k, p.self_mode ? 1 : 0, b.flag1,
+                       &b.counters->flagged, esc_cap, b.flag2, &b.counters->flagged2, out_idx, out_dist, b.counters,
+                       soff, nsamples);
+    return launch_status("rescan");
+}
 
 int knn_plan(int64_t nq, int64_t nr, int d, int k, const rsc_knn_opts *opts, bool self_mode, KnnPlan *plan) {
     if (nq < 0 || nr < 1) {
@@ -661,9 +610,7 @@ int knn_run_lowp(const KnnPlan &p, const float *Q, const float *R, int32_t *out_
     ra.flag_count = &b.counters->flagged;
     ra.out_idx = out_idx;
     ra.out_dist = out_dist;
-    ScopedTimer timer("rerank", stream);
-    hipLaunchKernelGGL(k_rerank, dim3((unsigned)((p.nq + 3) / 4)), dim3(256), 0, stream, ra);
-    return launch_status("rerank");
+    return knn_launch_rerank(ra, p.nq, "rerank", stream);
 }
 
 int knn_run(const KnnPlan &p, const float *Q, const float *R, int32_t *out_idx, float *out_dist, void *ws,
@@ -672,24 +619,10 @@ int knn_run(const KnnPlan &p, const float *Q, const float *R, int32_t *out_idx, 
     knn_workspace(p, ws, &b);
     if (p.precision != RSC_FP32) return knn_run_lowp(p, Q, R, out_idx, out_dist, b, stream);
     int st;
-    const int s4 = packed_s4(p.dh);
-    {
-        ScopedTimer timer("prep_pack", stream);
-        hipLaunchKernelGGL(k_init_counters, dim3(1), dim3(64), 0, stream, b.counters);
-        hipLaunchKernelGGL(k_norms, dim3((unsigned)((p.nr + 255) / 256)), dim3(256), 0, stream, R, p.nr, p.d, b.nrow,
-                           &b.counters->max_norm_bits);
-        const int64_t tot = p.nblk * s4 * kWave;
-        const unsigned g1 = (unsigned)std::min<int64_t>((tot + 255) / 256, 65536);
-        hipLaunchKernelGGL(k_pack, dim3(g1), dim3(256), 0, stream, R, b.nrow, p.nr, p.d, p.dh, s4,
-                           norm_folded(p.dh) ? 1 : 0, p.nblk, reinterpret_cast<f32x4 *>(b.packed), b.norms);
-        if ((st = launch_status("prep_pack")) != RSC_OK) return st;
-    }
+    if ((st = knn_prep_fp32(p, R, b, nullptr, nullptr, nullptr, stream)) != RSC_OK) return st;
     if (p.nq == 0) return RSC_OK;
 
-    // Error bound of the float32 key (the norm enters the MFMA sum or is
-    // added after it; norms rounded once from float64): 2 (d + 3) units of
-    // roundoff times (2 ||x|| max||y|| + max||y||^2).
-    const double eps_coef = 2.0 * (p.d + 3) * std::ldexp(1.0, -24);
+    const double eps_coef = knn_eps_coefficient(p.d);
 
     ScreenArgs sa{};
     sa.Q = Q;
@@ -724,11 +657,7 @@ int knn_run(const KnnPlan &p, const float *Q, const float *R, int32_t *out_idx, 
     ra.flag_count = &b.counters->flagged;
     ra.out_idx = out_idx;
     ra.out_dist = out_dist;
-    {
-        ScopedTimer timer("rerank", stream);
-        hipLaunchKernelGGL(k_rerank, dim3((unsigned)((p.nq + 3) / 4)), dim3(256), 0, stream, ra);
-        if ((st = launch_status("rerank")) != RSC_OK) return st;
-    }
+    if ((st = knn_launch_rerank(ra, p.nq, "rerank", stream)) != RSC_OK) return st;
 
     // Escalation: rows that failed, screened again 64 wide over many ranges.
     const int esc_cap = (int)std::min<int64_t>(p.nq, kEscalateCap);
@@ -752,19 +681,8 @@ int knn_run(const KnnPlan &p, const float *Q, const float *R, int32_t *out_idx, 
     re.cand_key = b.esc_key;
     re.flag_out = b.flag2;
     re.flag_count = &b.counters->flagged2;
-    {
-        ScopedTimer timer("rerank_escalate", stream);
-        hipLaunchKernelGGL(k_rerank, dim3((unsigned)((esc_cap + 3) / 4)), dim3(256), 0, stream, re);
-        if ((st = launch_status("rerank_escalate")) != RSC_OK) return st;
-    }
-    {
-        ScopedTimer timer("rescan", stream);
-        hipLaunchKernelGGL(k_rescan, dim3(1024), dim3(64), 0, stream, Q, R, p.nr, p.d, p.k, p.self_mode ? 1 : 0,
-                           b.flag1, &b.counters->flagged, esc_cap, b.flag2, &b.counters->flagged2, out_idx,
-                           out_dist, b.counters);
-        if ((st = launch_status("rescan")) != RSC_OK) return st;
-    }
-    return RSC_OK;
+    if ((st = knn_launch_rerank(re, esc_cap, "rerank_escalate", stream)) != RSC_OK) return st;
+    return knn_launch_rescan(p, Q, R, b, esc_cap, out_idx, out_dist, nullptr, 0, stream);
 }
 
 }  // namespace rsc

@@ -86,12 +86,45 @@ struct KnnBuffers {
     float *esc_key;
 };
 
+// Arguments of the float64 rerank (knn.hip).
+struct RerankArgs {
+    const float *Q;
+    int64_t nq;
+    const int32_t *qlist;   // optional: slot -> row
+    const int32_t *qcount;
+    int qcap;
+    const float *R;
+    int d, k, S, KP, P;
+    int self_mode;
+    int certify;            // 0: approximate screen, never flag rows
+    const int32_t *cand_idx;
+    const float *cand_key;
+    double eps_coef;
+    KnnCounters *counters;
+    int32_t *flag_out;   // rows that fail the certificate
+    int32_t *flag_count;
+    int32_t *out_idx;
+    float *out_dist;
+};
+
 // Fill a plan; returns RSC_OK or an error status (with message set).
 int knn_plan(int64_t nq, int64_t nr, int d, int k, const rsc_knn_opts *opts, bool self_mode, KnnPlan *plan);
 // Bytes of workspace for a plan; with ws != nullptr also carves the buffers.
 size_t knn_workspace(const KnnPlan &p, void *ws, KnnBuffers *out);
 int knn_run(const KnnPlan &p, const float *Q, const float *R, int32_t *out_idx, float *out_dist, void *ws,
             hipStream_t stream);
+
+// Pieces of the exact path reused by the batched form (knn.hip).
+double knn_eps_coefficient(int d);
+// init counters, norms, FP32 packing (optionally per sample: blk_sample,
+// boff, soff device arrays).
+int knn_prep_fp32(const KnnPlan &p, const float *R, const KnnBuffers &b, const int32_t *blk_sample,
+                  const int64_t *boff, const int64_t *soff, hipStream_t stream);
+int knn_launch_rerank(const RerankArgs &ra, int64_t slots, const char *name, hipStream_t stream);
+// exhaustive float64 rescan of the rows flagged in b (first certificate only
+// when there was no escalation); soff/nsamples restrict each row to its sample.
+int knn_launch_rescan(const KnnPlan &p, const float *Q, const float *R, const KnnBuffers &b, int esc_cap,
+                      int32_t *out_idx, float *out_dist, const int64_t *soff, int nsamples, hipStream_t stream);
 
 namespace scr {
 struct ScreenArgs;
@@ -104,6 +137,14 @@ size_t lowp_packed_bytes(int precision, int64_t nblk, int d);
 int lowp_prepare(const KnnPlan &p, const float *Q, const float *R, void *packed, float *norms, float *scal,
                  uint32_t *amax, hipStream_t stream);
 int lowp_screen(const KnnPlan &p, const scr::ScreenArgs &a, unsigned gx, hipStream_t s);
+
+// Batched form (knn_batched.hip).
+size_t batched_workspace_bytes(const int64_t *offsets, int S, int d, int k);
+int batched_run(const float *X, const int64_t *offsets, int S, int d, int k, int32_t *out_idx, float *out_dist,
+                void *ws, size_t ws_bytes, hipStream_t s);
+int batched_autotune(const float *X, const int64_t *offsets, int S, int d, int k, void *ws, size_t ws_bytes,
+                     hipStream_t s, int32_t *chosen, float *times_ms);
+const char *batched_policy_name(int pol);
 
 // ---- graph stages (graph.hip) --------------------------------------------
 

@@ -151,3 +151,25 @@ def test_binding_fails_loudly_without_library(tmp_path):
             _lib.load(str(tmp_path / "missing.so"))
         finally:
             _lib._lib = saved
+
+
+def test_batched_validation(lib):
+    import numpy as np
+
+    def call(off, d=50, k=15, ws_bytes=1 << 40):
+        off = np.ascontiguousarray(np.asarray(off, dtype=np.int64))
+        return lib.rsc_knn_batched(FAKE, off.ctypes.data_as(ctypes.c_void_p), len(off) - 1, d, k, FAKE, FAKE,
+                                   ctypes.c_void_p(0x100000), ws_bytes, None)
+
+    assert call([1, 100]) == -1 and "offsets[0]" in _err(lib)
+    assert call([0, 100, 110]) == -1 and "at least k" in _err(lib)
+    assert call([0, 100], k=64) == -6
+    assert call([0, 100], d=0) == -1
+    assert call([0, 100, 300], ws_bytes=100) == -7
+    off = np.array([0, 100, 300], dtype=np.int64)
+    p = off.ctypes.data_as(ctypes.c_void_p)
+    assert lib.rsc_knn_batched_workspace_bytes(p, 2, 50, 15) > 0
+    bad = np.array([0, 100, 105], dtype=np.int64)
+    assert lib.rsc_knn_batched_workspace_bytes(bad.ctypes.data_as(ctypes.c_void_p), 2, 50, 15) == 0
+    assert lib.rsc_batch_policy_name(0) != b""
+    assert lib.rsc_batch_policy_name(99) == b""

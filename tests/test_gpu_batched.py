@@ -1,0 +1,121 @@
+"""Batched form: many independent samples in one persistent launch, parity
+per sample with the FP64 oracle (global row ids, block-diagonal graph)."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from tests.parity import check_graph_properties, compare_knn
+
+pytestmark = pytest.mark.gpu
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rsc():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_02402_amd as rsc
+
+    rsc.load()
+    return rsc
+
+
+def small_batch(sizes, d=50, seed=0):
+    parts = [synth.mixture(int(n), d=d, n_clusters=5, seed=seed + 17 * s) for s, n in enumerate(sizes)]
+    off = np.zeros(len(sizes) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes)
+    return np.concatenate(parts), off
+
+
+def run_batched(rsc, X, off, k, autotune=False):
+    import torch
+
+    Xt = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    ws = rsc.Workspace()
+    tuned = None
+    if autotune:
+        tuned = rsc.knn_batched_autotune(Xt, off, k, workspace=ws)
+    idx, dist = rsc.knn_batched(Xt, off, k, workspace=ws)
+    torch.cuda.synchronize()
+    return idx.cpu().numpy(), dist.cpu().numpy(), rsc.read_knn_stats(ws), tuned
+
+
+def check_against_oracle(oracle_mod, X, off, idx, dist, k, rows_per_sample=None):
+    for s in range(len(off) - 1):
+        a, b = int(off[s]), int(off[s + 1])
+        Xs = X[a:b]
+        if rows_per_sample is None:
+            rows = np.arange(b - a)
+            io, _, do = oracle_mod.knn(Xs, k)
+        else:
+            rows = synth.sample_rows(b - a, rows_per_sample, seed=s)
+            io, _, do = oracle_mod.knn_rows(Xs, rows, k)
+        gi = idx[a + rows] - a
+        assert ((idx[a + rows] >= a) & (idx[a + rows] < b)).all(), f"sample {s}: neighbour outside the sample"
+        compare_knn(Xs, rows, gi, dist[a + rows], io, do, oracle_mod, k)
+
+
+def test_small_batch_full_parity(rsc, oracle_mod):
+    sizes = [15, 16, 31, 32, 33, 100, 257, 1000, 2049, 3000, 15]
+    X, off = small_batch(sizes, seed=3)
+    idx, dist, stats, _ = run_batched(rsc, X, off, 15)
+    log(f"[batched] small batch {sizes}: stats {stats}")
+    check_against_oracle(oracle_mod, X, off, idx, dist, 15)
+
+
+@pytest.mark.parametrize("d,k", [(3, 5), (64, 15), (50, 2), (50, 32)])
+def test_shapes(rsc, oracle_mod, d, k):
+    sizes = [k, 40, 500, 1234, 77]
+    X, off = small_batch(sizes, d=d, seed=d + k)
+    idx, dist, _, _ = run_batched(rsc, X, off, k)
+    check_against_oracle(oracle_mod, X, off, idx, dist, k)
+
+
+def test_autotune_and_determinism(rsc, oracle_mod):
+    sizes = np.rint(np.exp(np.random.default_rng(5).uniform(np.log(2000), np.log(60000), size=12))).astype(int)
+    X, off = small_batch(sizes, seed=11)
+    i1, d1, _, tuned = run_batched(rsc, X, off, 15, autotune=True)
+    chosen, times = tuned
+    log(f"[batched] autotune chose {chosen}: {times}")
+    assert 0 <= chosen < 6 and all(t > 0 for t in times.values())
+    i2, d2, _, _ = run_batched(rsc, X, off, 15)
+    np.testing.assert_array_equal(i1, i2)
+    np.testing.assert_array_equal(d1.view(np.uint32), d2.view(np.uint32))
+    check_against_oracle(oracle_mod, X, off, i1, d1, 15, rows_per_sample=16)
+
+
+def test_batched_graph_block_diagonal(rsc):
+    import torch
+
+    sizes = [300, 1000, 45, 2000]
+    X, off = small_batch(sizes, seed=21)
+    Xt = torch.from_numpy(X).cuda()
+    idx, dist = rsc.knn_batched(Xt, off, 15)
+    g = rsc.connectivities(idx, dist)
+    torch.cuda.synchronize()
+    indptr, indices, data = g.indptr.cpu().numpy(), g.indices.cpu().numpy(), g.data.cpu().numpy()
+    n = X.shape[0]
+    check_graph_properties(indptr, indices, data, n, 15, g.rho.cpu().numpy(), g.sigma.cpu().numpy(),
+                           dist.cpu().numpy())
+    rows = np.repeat(np.arange(n), np.diff(indptr))
+    samp_r = np.searchsorted(off, rows, side="right") - 1
+    samp_c = np.searchsorted(off, indices, side="right") - 1
+    assert (samp_r == samp_c).all(), "edge across samples"
+
+
+def test_batched_64_samples_sampled_parity(rsc, oracle_mod):
+    """The 64-sample workload (sizes log-uniform in [2k, 200k]), oracle on sampled rows of each sample."""
+    X, off = synth.batched_samples()
+    log(f"[batched] 64 samples, {off[-1]} cells")
+    idx, dist, stats, _ = run_batched(rsc, X, off, 15)
+    log(f"[batched] stats {stats}")
+    check_against_oracle(oracle_mod, X, off, idx, dist, 15, rows_per_sample=3)
