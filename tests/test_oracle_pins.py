@@ -259,3 +259,69 @@ def test_union_rejects_duplicate_neighbour(oracle_mod):
     a = np.ones((3, 2))
     with pytest.raises(ValueError):
         oracle_mod.fuzzy_union(idx, a)
+
+
+# ---- router network (oracle/mlp.py) -------------------------------------------------
+
+
+def _mlp_small(seed=0, d=5, hidden=7, parts=11, n=13, m=4):
+    from oracle import mlp
+
+    rng = np.random.default_rng(seed)
+    params = mlp.init_params(d, hidden, parts, seed=seed)
+    # non-zero biases so that every term of the backward pass is exercised
+    params = [p + (0.1 * rng.standard_normal(p.shape) if p.ndim == 1 else 0) for p in params]
+    X = rng.standard_normal((n, d))
+    lab = rng.integers(0, parts, size=(n, m))
+    return mlp, params, X, mlp.soft_targets(lab, parts)
+
+
+def test_mlp_backward_matches_finite_differences():
+    mlp, params, X, T = _mlp_small()
+    grads = mlp.backward(params, X, T)
+    h = 1e-6
+    for pi, (w, g) in enumerate(zip(params, grads)):
+        flat = w.reshape(-1)
+        num = np.zeros_like(flat)
+        for i in range(flat.size):
+            old = flat[i]
+            flat[i] = old + h
+            lp = mlp.loss(params, X, T)
+            flat[i] = old - h
+            lm = mlp.loss(params, X, T)
+            flat[i] = old
+            num[i] = (lp - lm) / (2 * h)
+        np.testing.assert_allclose(g.reshape(-1), num, rtol=1e-5, atol=1e-8, err_msg=f"param {pi}")
+
+
+def test_mlp_loss_and_gradient_invariants():
+    mlp, params, X, T = _mlp_small(seed=3)
+    np.testing.assert_allclose(T.sum(axis=1), 1.0)
+    assert mlp.loss(params, X, T) > 0
+    grads = mlp.backward(params, X, T)
+    # softmax gradients sum to zero over the partitions for every row
+    assert abs(grads[5].sum()) < 1e-12
+    # uniform logits: loss = log P whatever the targets
+    zero = [np.zeros_like(p) for p in params]
+    np.testing.assert_allclose(mlp.loss(zero, X, T), np.log(11), rtol=1e-12)
+
+
+def test_adam_first_step_is_sign_step():
+    mlp, params, X, T = _mlp_small(seed=4)
+    grads = mlp.backward(params, X, T)
+    state = [(np.zeros_like(p), np.zeros_like(p)) for p in params]
+    new = mlp.adam_step(params, grads, state, lr=1e-3, step=1)
+    for w0, w1, g in zip(params, new, grads):
+        big = np.abs(g) > 1e-4
+        np.testing.assert_allclose((w1 - w0)[big], -1e-3 * np.sign(g[big]), rtol=1e-3)
+
+
+def test_top_partitions_brute_force():
+    mlp, params, X, T = _mlp_small(seed=5, parts=40, n=30)
+    order, mass = mlp.top_partitions(params, X, 6)
+    _, z = mlp.forward(params, X)
+    p = np.exp(mlp.log_softmax(z))
+    for i in range(X.shape[0]):
+        ranked = sorted(range(40), key=lambda j: (-z[i, j], j))[:6]
+        assert order[i].tolist() == ranked
+        assert mass[i] == pytest.approx(sum(p[i, j] for j in ranked), rel=1e-12)
