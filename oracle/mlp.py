@@ -102,3 +102,53 @@ def top_partitions(params, X, probes: int):
     order = np.lexsort((np.broadcast_to(np.arange(z.shape[1]), z.shape), -z), axis=1)[:, :probes]
     mass = np.take_along_axis(p, order, axis=1).sum(axis=1)
     return order, mass
+
+
+def bf16_round(x):
+    """Round to the nearest bfloat16 value (ties to even), returned in float64.
+
+    bfloat16 keeps the float32 sign, exponent and top 7 mantissa bits; the
+    float32 value is rounded first (round to nearest even), then the low 16
+    bits with ties to even.
+    """
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    finite = (u & 0x7F800000) != 0x7F800000
+    lsb = (u >> 16) & 1
+    r = np.where(finite, (u + 0x7FFF + lsb) >> 16, u >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def forward_bf16(params, X, rounding=True):
+    """Forward pass with the roundings of the BF16 matrix-core kernels:
+    inputs, weights and hidden activations rounded to bfloat16, biases and
+    logits kept exact.  ``rounding=False`` makes it ``forward``."""
+    rnd = bf16_round if rounding else (lambda v: np.asarray(v, dtype=np.float64))
+    W1, b1, W2, b2, W3, b3 = params
+    x = rnd(X)
+    h1 = rnd(np.maximum(x @ rnd(W1).T + b1, 0.0))
+    h2 = rnd(np.maximum(h1 @ rnd(W2).T + b2, 0.0))
+    z = h2 @ rnd(W3).T + b3
+    return (x, h1, h2), z
+
+
+def backward_bf16(params, X, targets, rounding=True):
+    """Gradients with the roundings of the BF16 kernels: the output error
+    (softmax - target) / n and the back-propagated hidden errors are rounded
+    to bfloat16 before they enter the next product; weight gradients are
+    exact sums of those rounded factors.  ``rounding=False`` gives
+    ``backward``."""
+    rnd = bf16_round if rounding else (lambda v: np.asarray(v, dtype=np.float64))
+    W1, b1, W2, b2, W3, b3 = params
+    (x, h1, h2), z = forward_bf16(params, X, rounding)
+    n = X.shape[0]
+    dz = rnd((np.exp(log_softmax(z)) - targets) / n)
+    dW3 = dz.T @ h2
+    db3 = dz.sum(axis=0)
+    dh2 = rnd((dz @ rnd(W3)) * (h2 > 0))
+    dW2 = dh2.T @ h1
+    db2 = dh2.sum(axis=0)
+    dh1 = rnd((dh2 @ rnd(W2)) * (h1 > 0))
+    dW1 = dh1.T @ x
+    db1 = dh1.sum(axis=0)
+    return [dW1, db1, dW2, db2, dW3, db3]

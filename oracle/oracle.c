@@ -321,3 +321,68 @@ int64_t oracle_fuzzy_union(const int32_t *idx, const double *a, int64_t n, int k
     free(e);
     return nnz;
 }
+
+/*
+ * Exact kNN restricted to given candidate sets (the routed form's result
+ * for a query is the exact nearest neighbours among the references of the
+ * partitions it probes).
+ *
+ * Query q is row q of X; its candidates are cand_ids[cand_off[q] ..
+ * cand_off[q+1]) (row ids of X, each at most once; q itself may be among
+ * them and is ignored).  Slot 0 is q with distance 0; slots 1..k-1 hold the
+ * nearest candidates by (d2, index); slots left empty get index -1 and an
+ * infinite distance.  Returns 0, or -1 on bad arguments.
+ */
+int oracle_knn_subset(const float *X, int64_t n, int d, int k, const int64_t *cand_off,
+                      const int64_t *cand_ids, int32_t *out_idx, double *out_d2, float *out_dist) {
+    if (n < 0 || d < 1 || k < 1) return -1;
+    int fail = 0;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t q = 0; q < n; ++q) {
+        const float *x = X + q * (int64_t)d;
+        double *bd = (double *)malloc(sizeof(double) * (size_t)k);
+        int64_t *bj = (int64_t *)malloc(sizeof(int64_t) * (size_t)k);
+        if (!bd || !bj) {
+            fail = 1;
+            free(bd);
+            free(bj);
+            continue;
+        }
+        bd[0] = 0.0;
+        bj[0] = q;
+        int cnt = 1; /* slots [1, cnt) sorted ascending */
+        for (int64_t c = cand_off[q]; c < cand_off[q + 1]; ++c) {
+            int64_t j = cand_ids[c];
+            if (j < 0 || j >= n) {
+                fail = 1;
+                break;
+            }
+            if (j == q) continue;
+            double v = sq_dist(x, X + j * (int64_t)d, d);
+            int p;
+            if (cnt < k) {
+                p = cnt++;
+            } else if (k > 1 && before(v, j, bd[k - 1], bj[k - 1])) {
+                p = k - 1;
+            } else {
+                continue;
+            }
+            while (p > 1 && before(v, j, bd[p - 1], bj[p - 1])) {
+                bd[p] = bd[p - 1];
+                bj[p] = bj[p - 1];
+                --p;
+            }
+            bd[p] = v;
+            bj[p] = j;
+        }
+        for (int s = 0; s < k; ++s) {
+            int64_t o = q * (int64_t)k + s;
+            out_idx[o] = (int32_t)(s < cnt ? bj[s] : -1);
+            if (out_d2) out_d2[o] = s < cnt ? bd[s] : INFINITY;
+            if (out_dist) out_dist[o] = s < cnt ? (float)sqrt(bd[s]) : INFINITY;
+        }
+        free(bd);
+        free(bj);
+    }
+    return fail ? -1 : 0;
+}

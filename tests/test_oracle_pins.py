@@ -325,3 +325,152 @@ def test_top_partitions_brute_force():
         ranked = sorted(range(40), key=lambda j: (-z[i, j], j))[:6]
         assert order[i].tolist() == ranked
         assert mass[i] == pytest.approx(sum(p[i, j] for j in ranked), rel=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Routed form: candidate-set kNN, k-means partitions, BF16 emulation.
+# ---------------------------------------------------------------------------
+
+def test_knn_subset_reduces_to_knn_and_to_sub_problems():
+    from oracle import knn, knn_subset
+
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((120, 6)).astype(np.float32)
+    n = X.shape[0]
+    # every row a candidate: the plain exact kNN
+    off = np.arange(n + 1, dtype=np.int64) * n
+    ids = np.tile(np.arange(n, dtype=np.int64), n)
+    a = knn_subset(X, 7, off, ids)
+    b = knn(X, 7)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    # candidates = a fixed subset S (plus self): kNN of X[S ∪ {q}] mapped back
+    S = np.sort(rng.choice(n, 40, replace=False))
+    off = np.arange(n + 1, dtype=np.int64) * S.size
+    idx, d2, _ = knn_subset(X, 5, off, np.tile(S, n))
+    for q in range(0, n, 7):
+        rows = np.union1d(S, [q])
+        sub_i, sub_d2, _ = knn(X[rows], 5, Q=X[q:q + 1], self_ids=np.searchsorted(rows, [q]))
+        assert np.array_equal(rows[sub_i[0]], idx[q]) and np.array_equal(sub_d2[0], d2[q])
+    # fewer candidates than k: padded with -1 / inf
+    off = np.zeros(n + 1, dtype=np.int64)
+    off[1:] = 2
+    off = np.cumsum(off)
+    ids = np.tile(np.array([0, 1], dtype=np.int64), n)
+    idx, d2, _ = knn_subset(X, 5, off, ids)
+    assert (idx[5, 3:] == -1).all() and np.isinf(d2[5, 3:]).all()
+    assert idx[0, 0] == 0 and idx[0, 1] == 1 and idx[0, 2] == -1
+
+
+def test_kmeans_matches_sklearn_lloyd():
+    from sklearn.cluster import KMeans
+
+    from oracle import partition
+
+    rng = np.random.default_rng(11)
+    centres = rng.normal(0, 6, size=(12, 5))
+    X = (centres[rng.integers(0, 12, 1500)] + rng.standard_normal((1500, 5))).astype(np.float32)
+    init = rng.choice(1500, 12, replace=False)
+    for iters in (1, 3, 10):
+        C, labels, relocated = partition.kmeans(X, init, iters)
+        assert relocated == 0
+        km = KMeans(n_clusters=12, init=X[init].astype(np.float64), n_init=1, max_iter=iters, tol=0.0,
+                    algorithm="lloyd").fit(X.astype(np.float64))
+        assert np.array_equal(labels, km.labels_)
+        np.testing.assert_allclose(C, km.cluster_centers_, rtol=1e-6, atol=1e-6)
+
+
+def test_kmeans_relocates_empty_partition_by_hand():
+    from oracle import partition
+
+    # 1-D rows 0, 0, 5, 5.5, 6 with initial centroids rows 0, 1, 2 = (0, 0, 5):
+    # rows 0 and 1 tie between centroids 0 and 1 and go to 0 (lower index),
+    # centroid 1 is empty and takes the farthest row from its centroid: row 4
+    # (distance 1 to centroid 5).  New centroids: mean(0, 0) = 0, 6,
+    # mean(5, 5.5) = 5.25; final labels 0, 0, 2, 2, 1.
+    X = np.array([[0.0], [0.0], [5.0], [5.5], [6.0]], dtype=np.float32)
+    C, labels, relocated = partition.kmeans(X, np.array([0, 1, 2]), 1)
+    assert relocated == 1
+    assert np.array_equal(C[:, 0], np.array([0.0, 6.0, 5.25], dtype=np.float32))
+    assert labels.tolist() == [0, 0, 2, 2, 1]
+
+
+def test_kmeans_mean_is_correctly_rounded():
+    from oracle import partition
+
+    # values whose float32 sum loses bits: mean of 1 + 2^-23 (x3) and 1 is
+    # 1 + 0.75 * 2^-23, correctly rounded to 1 + 2^-23
+    v = np.array([1 + 2**-23, 1 + 2**-23, 1 + 2**-23, 1.0], dtype=np.float32)
+    C = partition.centroid_means(v[:, None], np.zeros(4, dtype=np.int32), 1, np.zeros((1, 1), np.float32))
+    assert C[0, 0] == np.float32(1 + 2**-23)
+
+
+def test_inverted_lists_brute_force():
+    from oracle import partition
+
+    rng = np.random.default_rng(5)
+    labels = rng.integers(0, 9, 300).astype(np.int32)
+    labels[labels == 4] = 3  # an empty partition
+    off, perm = partition.inverted_lists(labels, 9)
+    for p in range(9):
+        assert perm[off[p]:off[p + 1]].tolist() == [i for i in range(300) if labels[i] == p]
+    assert off[4] == off[5]
+
+
+def test_routed_knn_special_cases():
+    from oracle import knn, partition
+
+    rng = np.random.default_rng(8)
+    X = rng.standard_normal((200, 4)).astype(np.float32)
+    labels = rng.integers(0, 6, 200).astype(np.int32)
+    off, perm = partition.inverted_lists(labels, 6)
+    exact = knn(X, 6)
+    all_probes = np.tile(np.arange(6, dtype=np.int32), (200, 1))
+    a = partition.routed_knn(X, 6, off, perm, all_probes)
+    assert np.array_equal(a[0], exact[0])
+    own = labels[:, None].copy()
+    b = partition.routed_knn(X, 6, off, perm, own, exact_rows=np.arange(200) % 2 == 0)
+    assert np.array_equal(b[0][::2], exact[0][::2])
+    for q in range(1, 200, 2):  # own partition only: brute force within it
+        members = [j for j in range(200) if labels[j] == labels[q] and j != q]
+        d2 = [float(np.sum((X[q].astype(np.float64) - X[j].astype(np.float64)) ** 2)) for j in members]
+        best = [members[i] for i in np.lexsort((members, d2))[:5]]
+        got = [j for j in b[0][q, 1:] if j >= 0]
+        assert got == best
+    assert partition.recall(a[0], exact[0]) == 1.0
+
+
+def test_bf16_round_matches_torch():
+    import torch
+
+    from oracle.mlp import bf16_round
+
+    rng = np.random.default_rng(2)
+    x = np.concatenate([rng.standard_normal(5000) * 10 ** rng.uniform(-30, 30, 5000),
+                        # exact halfway cases: low 16 bits 0x8000, both parities
+                        (np.arange(1, 200, dtype=np.uint32) << 16 | 0x8000).view(np.float32).astype(np.float64),
+                        [0.0, -0.0, np.inf, -np.inf]]).astype(np.float32)
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(bf16_round(x), ref)
+
+
+def test_bf16_emulation_reduces_to_exact_and_stays_close():
+    from oracle import mlp
+
+    rng = np.random.default_rng(4)
+    d, H, P, n, m = 6, 64, 64, 40, 3
+    params = mlp.init_params(d, H, P, seed=1)
+    params = [p + (0.05 * rng.standard_normal(p.shape) if p.ndim == 1 else 0) for p in params]
+    X = rng.standard_normal((n, d))
+    t = mlp.soft_targets(rng.integers(0, P, (n, m)), P)
+    exact = mlp.backward(params, X, t)
+    plain = mlp.backward_bf16(params, X, t, rounding=False)
+    for a, b in zip(exact, plain):
+        assert np.array_equal(a, b)
+    assert np.array_equal(mlp.forward_bf16(params, X, rounding=False)[1], mlp.forward(params, X)[1])
+    # each bfloat16 rounding moves a value by at most 2^-9 relative; about ten
+    # of them compound along the path to dW1 (inputs, three weights, two
+    # activations, three errors), so the gradients stay within 2^-4
+    rounded = mlp.backward_bf16(params, X, t)
+    for a, b in zip(exact, rounded):
+        assert np.linalg.norm(a - b) <= 2**-4 * np.linalg.norm(a)
+        assert np.linalg.norm(a - b) > 0
