@@ -261,6 +261,114 @@ def batched_form(args, rsc) -> dict:
             "exact": True}
 
 
+def routed_form(args, rsc) -> dict:
+    """The learned-router form: base n = 5M cells (500-cluster Zipf mixture),
+    P = 4096 k-means partitions, a 50-256-256-4096 router trained on the
+    exact-kNN partition labels of a held-out 1M-cell draw, top-32 probes,
+    exact search for rows whose probed softmax mass is below 0.9.
+
+    The index (partitions, labels, training) is built once and timed on its
+    own; a timed step is the routed kNN of every base cell plus the
+    connectivities.  Recall@15 is judged against the exact path on sampled
+    rows, and nearest-centroid probing with the same probe count is measured
+    beside it (the method without the router)."""
+    import torch
+
+    import synth
+
+    k, P, probes, thr = args.k, synth.ROUTED["parts"], args.routed_probes, args.routed_threshold
+    log(f"[bench] routed form: generating base {args.routed_n} + train {args.routed_train}")
+    base, train = synth.routed_draws(n_base=args.routed_n, n_train=args.routed_train)
+    n, d = base.shape
+    dev = torch.device("cuda:0")
+    Xb = torch.from_numpy(base).to(dev)
+    Xt = torch.from_numpy(train).to(dev)
+    del base, train
+    ws = rsc.Workspace(dev)
+    build = {}
+
+    def clock(name, fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        build[name] = round(time.perf_counter() - t0, 3)
+        log(f"[bench] routed form: {name} {build[name]} s")
+        return out
+
+    init = torch.from_numpy(synth.init_rows(n, P, seed=5)).to(dev)
+    C, assign, off, perm, relocated = clock(
+        "kmeans_s", lambda: rsc.partition_kmeans(Xb, P, init, args.routed_iters, workspace=ws))
+    tidx, _ = clock("labels_exact_knn_s", lambda: rsc.knn(Xb, k, Q=Xt, workspace=ws))
+    labels = rsc.partition_labels(tidx, assign)
+    del tidx
+    router = rsc.Router(d, 256, P, seed=1)
+    losses = clock("train_s", lambda: router.train(Xt, labels, epochs=args.routed_epochs, batch=4096, lr=1e-3,
+                                                   workspace=ws))
+    del labels, Xt
+    torch.cuda.empty_cache()
+
+    cap = 2 * n * (k - 1)
+    idx = torch.empty((n, k), dtype=torch.int32, device=dev)
+    dist = torch.empty((n, k), dtype=torch.float32, device=dev)
+    csr = (torch.empty(n + 1, dtype=torch.int64, device=dev), torch.empty(cap, dtype=torch.int32, device=dev),
+           torch.empty(cap, dtype=torch.float32, device=dev))
+    rws = rsc.Workspace(dev)
+
+    def step():
+        _, _, route, st = rsc.knn_routed(router, Xb, k, off, perm, probes=probes, mass_threshold=thr,
+                                         out=(idx, dist), workspace=rws)
+        g = rsc.connectivities(idx, dist, workspace=ws, out=csr)
+        return st, g
+
+    step()
+    torch.cuda.synchronize()
+    rsc.profile_reset()
+    rsc.profile_enable(True)
+    t0 = time.perf_counter()
+    for i in range(args.form_steps):
+        st, g = step()
+        log(f"[bench] routed form: step {i + 1}/{args.form_steps}")
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.form_steps
+    rsc.profile_enable(False)
+    kern = {}
+    for name in ["router_infer", "probed_prep", "screen_routed", "rerank_probed", "prep_pack", "screen_fp32",
+                 "rerank", "screen_escalate", "rescan"]:
+        tot, cnt = rsc.profile_get(name)
+        if cnt:
+            kern[name] = round(tot / args.form_steps, 3)
+
+    # recall@15 on sampled rows, judged by the exact path
+    rows = torch.from_numpy(synth.sample_rows(n, args.routed_sample, seed=55)).to(dev)
+    ex_idx, _ = rsc.knn(Xb, k, Q=Xb[rows].contiguous(), workspace=ws)
+
+    def recall(found):
+        a = found[rows][:, 1:].cpu().numpy()
+        b = ex_idx[:, 1:].cpu().numpy()
+        return float(np.mean([len(set(x.tolist()) & set(y.tolist())) for x, y in zip(a, b)]) / (k - 1))
+
+    rec = recall(idx)
+    # the method without the router: nearest centroids, same probe count, no fallback
+    nc_parts, _ = rsc.knn(C, probes, Q=Xb, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nc_idx, _, _, st_nc = rsc.knn_probed(Xb, k, off, perm, nc_parts, workspace=rws)
+    torch.cuda.synchronize()
+    ms_nc = (time.perf_counter() - t0) * 1e3
+    rec_nc = recall(nc_idx)
+    router.close()
+    return {"workload": f"base n={n}, d=50, k=15, 500-cluster Zipf(1.1) mixture (centres seed 5, base seed 50), "
+                        f"router trained on {args.routed_train} held-out cells (seed 51)",
+            "cells_per_s": round(n / (ms / 1e3), 1), "ms_per_step": round(ms, 2), "kernel_ms_per_step": kern,
+            "recall@15": round(rec, 5), "meets_recall_0.99": rec >= 0.99, "recall_sample_rows": args.routed_sample,
+            "parts": P, "probes": probes, "mass_threshold": thr, "stats": st, "nnz": int(g.nnz),
+            "index_build_s": build, "kmeans_iters": args.routed_iters, "kmeans_relocated": relocated,
+            "train_epochs": args.routed_epochs, "train_loss_per_epoch": [round(v, 4) for v in losses],
+            "nearest_centroid_probing": {"recall@15": round(rec_nc, 5), "knn_ms": round(ms_nc, 2),
+                                         "mean_probed_rows": round(st_nc["mean_probed_rows"], 1)}}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -273,6 +381,15 @@ def main() -> int:
     ap.add_argument("--traffic-probe", action="store_true", help="run the PMC calibration program and exit")
     ap.add_argument("--no-forms", action="store_true", help="skip the 2M-cell precision forms")
     ap.add_argument("--form-steps", type=int, default=3)
+    ap.add_argument("--no-routed", action="store_true", help="skip the learned-router form")
+    ap.add_argument("--only-routed", action="store_true", help="run the learned-router form alone (no JSON line)")
+    ap.add_argument("--routed-n", type=int, default=5_000_000)
+    ap.add_argument("--routed-train", type=int, default=1_000_000)
+    ap.add_argument("--routed-iters", type=int, default=10, help="k-means iterations")
+    ap.add_argument("--routed-epochs", type=int, default=4)
+    ap.add_argument("--routed-probes", type=int, default=32)
+    ap.add_argument("--routed-threshold", type=float, default=0.9)
+    ap.add_argument("--routed-sample", type=int, default=4000, help="rows whose recall is judged")
     args = ap.parse_args()
     if args.traffic_probe:
         return traffic_probe()
@@ -292,6 +409,9 @@ def main() -> int:
         print("no GPU visible", file=sys.stderr)
         return 1
     rsc.load()
+    if args.only_routed:
+        print(json.dumps({"routed": routed_form(args, rsc)}), flush=True)
+        return 0
 
     w = WORKLOADS[args.workload]
     k = args.k
@@ -360,6 +480,9 @@ def main() -> int:
         forms = precision_forms(args, rsc)
         torch.cuda.empty_cache()
         forms["batched_fp32"] = batched_form(args, rsc)
+        if not args.no_routed:
+            torch.cuda.empty_cache()
+            forms["routed"] = routed_form(args, rsc)
 
     cpu = None
     if not args.no_cpu_baseline:

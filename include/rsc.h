@@ -214,6 +214,180 @@ int rsc_connectivities(const int32_t *idx, const float *dist, int64_t n, int32_t
                        void *workspace, size_t workspace_bytes, void *stream);
 
 /* ---------------------------------------------------------------------- */
+/* Routed form: coarse partitions, learned router, probed search           */
+/* ---------------------------------------------------------------------- */
+/*
+ * The routed form answers a query from a few coarse partitions of the cells
+ * instead of all of them (the paper's approximate-neighbour alternative,
+ * Methods, "Dimensionality reduction and graph analysis", where cuVS serves
+ * the neighbour search): a small network predicts which partitions hold a
+ * cell's neighbours, the cell is compared exactly with the cells of its most
+ * probable partitions, and cells the network is unsure of fall back to
+ * exact brute force.
+ */
+
+/* Workspace bytes for rsc_partition_kmeans. */
+size_t rsc_partition_kmeans_workspace_bytes(int64_t n, int32_t d, int32_t parts);
+
+/*
+ * Lloyd's k-means into `parts` partitions.
+ *   X          device n x d float32 (1 <= d <= 128, parts <= n <= 2^31-2).
+ *   init_rows  device int32 `parts` row ids: initial centroids are those rows.
+ *   iters      iterations (>= 0).  Each assigns every row to its nearest
+ *              centroid (float64 distance from direct differences, lower
+ *              centroid index on ties) and moves every centroid to the mean
+ *              of its rows (exact integer sum of the rows in fixed point,
+ *              divided by the count in float64, rounded to float32).  A
+ *              centroid left without rows takes the row farthest from its own
+ *              centroid (largest distance, lower row index on ties), one row
+ *              per empty centroid, in ascending centroid order.
+ *   centroids  device parts x d float32 (output).
+ *   assign     device int32 n (output): nearest centroid of each row for the
+ *              final centroids (one more assignment pass after the last
+ *              iteration).
+ *   offsets    device int64 parts+1, perm device int32 n (outputs, may be
+ *              NULL): inverted lists of `assign`: the rows of partition p are
+ *              perm[offsets[p] .. offsets[p+1]) (order within a partition
+ *              unspecified).
+ *   relocated  HOST int64 (may be NULL): empty-centroid relocations made.
+ * Synchronises `stream` once per iteration (to look for empty centroids).
+ */
+int rsc_partition_kmeans(const float *X, int64_t n, int32_t d, int32_t parts, const int32_t *init_rows,
+                         int32_t iters, float *centroids, int32_t *assign, int64_t *offsets, int32_t *perm,
+                         int64_t *relocated, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Label gather: labels[i*k + j] = assign[idx[i*k + j]] for an n x k kNN
+ * result `idx` (device int32); labels device int32 n x k.  Entries of idx
+ * outside [0, n_assign) give label -1. */
+int rsc_partition_labels(const int32_t *idx, int64_t n, int32_t k, const int32_t *assign, int64_t n_assign,
+                         int32_t *labels, void *stream);
+
+/*
+ * The router: a d -> hidden -> hidden -> parts perceptron (ReLU, softmax over
+ * partitions) held by an opaque handle that owns its device memory (float32
+ * master weights, Adam moments and bfloat16 copies).  Forward and backward
+ * products run in bfloat16 on the matrix cores with float32 accumulation.
+ * Weight layout (rsc_router_gradients, files): W1 [hidden x d], b1 [hidden],
+ * W2 [hidden x hidden], b2, W3 [parts x hidden], b3 [parts], row-major,
+ * concatenated (n_params floats).
+ */
+typedef struct rsc_router rsc_router;
+
+/* Create a router with uniform(+-sqrt(6/(fan_in+fan_out))) weights drawn from
+ * a counter-based SplitMix64 stream of `seed`, zero biases.  1 <= d <= 256;
+ * hidden and parts multiples of 64, parts <= 4096.  Synchronises the device. */
+int rsc_router_create(rsc_router **out, int32_t d, int32_t hidden, int32_t parts, uint64_t seed);
+/* Free a router (NULL is ignored). */
+void rsc_router_destroy(rsc_router *router);
+/* Shape and progress of a router (host outputs, each may be NULL). */
+int rsc_router_info(const rsc_router *router, int32_t *d, int32_t *hidden, int32_t *parts, int64_t *n_params,
+                    int64_t *steps);
+
+/* Workspace bytes for rsc_router_train with this batch and row count. */
+size_t rsc_router_train_workspace_bytes(const rsc_router *router, int32_t batch, int64_t n);
+/*
+ * Train on n labelled rows for `epochs` passes in row order, one Adam step
+ * (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) per batch of `batch`
+ * rows (a multiple of 64; the last batch may be partial).
+ *   X        device n x d float32.
+ *   labels   device n x m int32 partition ids: the target of row i puts
+ *            weight 1/m on each listed partition (repeats add up; entries
+ *            outside [0, parts) are skipped, their weight dropped); the loss
+ *            is the soft-target cross-entropy averaged over the batch.
+ *   loss_log HOST float32 `epochs` (may be NULL): mean batch loss per epoch
+ *            (losses before each step); when given the call synchronises.
+ */
+int rsc_router_train(rsc_router *router, const float *X, int64_t n, const int32_t *labels, int32_t m,
+                     int32_t epochs, int32_t batch, float lr, float *loss_log, void *workspace,
+                     size_t workspace_bytes, void *stream);
+
+/* Workspace bytes for rsc_router_gradients over n rows. */
+size_t rsc_router_gradients_workspace_bytes(const rsc_router *router, int64_t n);
+/* Gradient of the mean loss over n rows (n <= 65536) at the current weights,
+ * without updating them: grad device float32 n_params (layout above), loss
+ * device float32 1 (may be NULL). */
+int rsc_router_gradients(const rsc_router *router, const float *X, int64_t n, const int32_t *labels, int32_t m,
+                         float *grad, float *loss, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Workspace bytes for rsc_router_logits / rsc_router_probe. */
+size_t rsc_router_infer_workspace_bytes(const rsc_router *router);
+/* Logits of n rows: device n x parts float32. */
+int rsc_router_logits(const rsc_router *router, const float *X, int64_t n, float *logits, void *workspace,
+                      size_t workspace_bytes, void *stream);
+/* The `probes` most probable partitions of each row, by descending logit
+ * (lower index on ties): parts device int32 n x probes; mass device float32 n:
+ * the softmax probability those partitions hold. */
+int rsc_router_probe(const rsc_router *router, const float *X, int64_t n, int32_t probes, int32_t *parts,
+                     float *mass, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Inverted lists of given labels (device int32 n, each in [0, parts)):
+ * offsets device int64 parts+1, perm device int32 n as for
+ * rsc_partition_kmeans.  Synchronises `stream` (labels outside [0, parts)
+ * give RSC_ERR_INVALID_ARG). */
+size_t rsc_partition_lists_workspace_bytes(int32_t parts);
+int rsc_partition_lists(const int32_t *labels, int64_t n, int32_t parts, int64_t *offsets, int32_t *perm,
+                        void *workspace, size_t workspace_bytes, void *stream);
+
+/* Save / load weights and optimizer state (host file; header of shape and
+ * step count, then float32 arrays in the layout above).  Loading requires a
+ * router of the same shape.  Synchronise the device. */
+int rsc_router_save(const rsc_router *router, const char *path);
+int rsc_router_load(rsc_router *router, const char *path);
+
+/* How the rows of a routed or probed search were answered. */
+typedef struct {
+    int64_t routed_rows;      /* answered from their probed partitions */
+    int64_t low_mass_rows;    /* exact search: marked (probed softmax mass below the threshold) */
+    int64_t uncertified_rows; /* exact search: the screen of the probed partitions was not certified */
+    int64_t escalated_rows;   /* exact-search rows screened again, wider */
+    int64_t rescanned_rows;   /* exact-search rows recomputed exhaustively in float64 */
+    double mean_probed_rows;  /* mean candidates per routed row */
+} rsc_routed_stats;
+
+/* Workspace bytes for rsc_knn_probed / rsc_knn_routed. */
+size_t rsc_knn_probed_workspace_bytes(int64_t n, int32_t d, int32_t k, int32_t parts, int32_t probes);
+
+/*
+ * kNN of every row of X restricted to the partitions it probes.
+ *   X            device n x d float32; k, d as for rsc_knn.
+ *   offsets,perm device inverted lists of the partitions (as produced by
+ *                rsc_partition_kmeans: every row in exactly one partition).
+ *   probe_parts  device int32 n x probes partition ids (repeats and -1
+ *                entries ignored), 1 <= probes <= 64.
+ *   exact_rows   device uint8 n or NULL: rows with a non-zero entry are
+ *                answered by exact search over all rows.
+ *   out_idx, out_dist  as for rsc_knn.  A probed row's answer is the exact
+ *                k nearest (float64 distances, lower index on ties) among
+ *                the rows of its probed partitions, self in column 0; fewer
+ *                candidates than k-1 leave index -1 / distance +inf.
+ *                Rows whose screen cannot be certified within their
+ *                partitions are answered by exact search instead.
+ *   out_route    device uint8 n or NULL: 0 probed, 1 exact (marked), 2 exact
+ *                (not certified).
+ *   stats        HOST, may be NULL.
+ * Synchronises `stream` (to size the exact search).
+ */
+int rsc_knn_probed(const float *X, int64_t n, int32_t d, int32_t k, const int64_t *offsets, const int32_t *perm,
+                   int32_t parts, const int32_t *probe_parts, int32_t probes, const uint8_t *exact_rows,
+                   int32_t *out_idx, float *out_dist, uint8_t *out_route, rsc_routed_stats *stats,
+                   void *workspace, size_t workspace_bytes, void *stream);
+
+/* Workspace bytes for rsc_knn_routed. */
+size_t rsc_knn_routed_workspace_bytes(const rsc_router *router, int64_t n, int32_t d, int32_t k, int32_t parts,
+                                      int32_t probes);
+
+/*
+ * The routed form: the router's `probes` most probable partitions per row
+ * (rsc_router_probe), rows whose probed softmax mass is below
+ * `mass_threshold` marked for exact search, then rsc_knn_probed.  The router
+ * must have been created with d and parts equal to these.
+ */
+int rsc_knn_routed(const rsc_router *router, const float *X, int64_t n, int32_t d, int32_t k,
+                   const int64_t *offsets, const int32_t *perm, int32_t parts, int32_t probes, float mass_threshold,
+                   int32_t *out_idx, float *out_dist, uint8_t *out_route, rsc_routed_stats *stats, void *workspace,
+                   size_t workspace_bytes, void *stream);
+
+/* ---------------------------------------------------------------------- */
 /* Kernel timing (off by default)                                          */
 /* ---------------------------------------------------------------------- */
 

@@ -57,7 +57,7 @@ def _load():
             lib.oracle_fuzzy_union.argtypes = [P, P, i64, i32, P, P, P, i64]
             lib.oracle_fuzzy_union.restype = i64
             lib.oracle_max_threads.restype = i32
-            lib.oracle_knn_subset.argtypes = [P, i64, i32, i32, P, P, P, P, P]
+            lib.oracle_knn_subset.argtypes = [P, i64, i32, i32, P, i64, P, P, P, P, P]
             lib.oracle_knn_subset.restype = i32
             _lib = lib
     return _lib
@@ -99,21 +99,25 @@ def knn(R: np.ndarray, k: int, Q: np.ndarray | None = None, self_ids: np.ndarray
     return idx, d2, dist
 
 
-def knn_subset(X: np.ndarray, k: int, cand_off: np.ndarray, cand_ids: np.ndarray):
-    """Exact kNN of every row of ``X`` among its own candidate rows.
+def knn_subset(X: np.ndarray, k: int, cand_off: np.ndarray, cand_ids: np.ndarray, rows: np.ndarray | None = None):
+    """Exact kNN of rows of ``X`` among their own candidate rows.
 
-    Row ``q``'s candidates are ``cand_ids[cand_off[q]:cand_off[q+1]]``; self
+    Query ``i`` is row ``rows[i]`` (row ``i`` when ``rows`` is None); its
+    candidates are ``cand_ids[cand_off[i]:cand_off[i+1]]``; the query's row
     sits in slot 0, empty slots hold index -1.  Returns ``(idx, d2, dist)``.
     """
     X = np.ascontiguousarray(X, dtype=np.float32)
     cand_off = np.ascontiguousarray(cand_off, dtype=np.int64)
     cand_ids = np.ascontiguousarray(cand_ids, dtype=np.int64)
     n, d = X.shape
-    assert cand_off.shape == (n + 1,) and cand_off[0] == 0 and cand_off[-1] == cand_ids.shape[0]
-    idx = np.empty((n, k), dtype=np.int32)
-    d2 = np.empty((n, k), dtype=np.float64)
-    dist = np.empty((n, k), dtype=np.float32)
-    rc = _load().oracle_knn_subset(_p(X), n, d, k, _p(cand_off), _p(cand_ids), _p(idx), _p(d2), _p(dist))
+    qrows = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    nq = n if qrows is None else qrows.shape[0]
+    assert cand_off.shape == (nq + 1,) and cand_off[0] == 0 and cand_off[-1] == cand_ids.shape[0]
+    idx = np.empty((nq, k), dtype=np.int32)
+    d2 = np.empty((nq, k), dtype=np.float64)
+    dist = np.empty((nq, k), dtype=np.float32)
+    rc = _load().oracle_knn_subset(_p(X), n, d, k, _p(qrows), nq, _p(cand_off), _p(cand_ids), _p(idx), _p(d2),
+                                   _p(dist))
     if rc != 0:
         raise ValueError("oracle_knn_subset: invalid arguments")
     return idx, d2, dist

@@ -327,18 +327,25 @@ int64_t oracle_fuzzy_union(const int32_t *idx, const double *a, int64_t n, int k
  * for a query is the exact nearest neighbours among the references of the
  * partitions it probes).
  *
- * Query q is row q of X; its candidates are cand_ids[cand_off[q] ..
- * cand_off[q+1]) (row ids of X, each at most once; q itself may be among
- * them and is ignored).  Slot 0 is q with distance 0; slots 1..k-1 hold the
- * nearest candidates by (d2, index); slots left empty get index -1 and an
- * infinite distance.  Returns 0, or -1 on bad arguments.
+ * Query i is row qrows[i] of X (row i when qrows is NULL; nq queries); its
+ * candidates are cand_ids[cand_off[i] .. cand_off[i+1]) (row ids of X, each
+ * at most once; the query's own row may be among them and is ignored).
+ * Slot 0 is the query's row with distance 0; slots 1..k-1 hold the nearest
+ * candidates by (d2, index); slots left empty get index -1 and an infinite
+ * distance.  Returns 0, or -1 on bad arguments.
  */
-int oracle_knn_subset(const float *X, int64_t n, int d, int k, const int64_t *cand_off,
-                      const int64_t *cand_ids, int32_t *out_idx, double *out_d2, float *out_dist) {
-    if (n < 0 || d < 1 || k < 1) return -1;
+int oracle_knn_subset(const float *X, int64_t n, int d, int k, const int64_t *qrows, int64_t nq,
+                      const int64_t *cand_off, const int64_t *cand_ids, int32_t *out_idx, double *out_d2,
+                      float *out_dist) {
+    if (n < 0 || nq < 0 || d < 1 || k < 1) return -1;
     int fail = 0;
 #pragma omp parallel for schedule(dynamic, 16)
-    for (int64_t q = 0; q < n; ++q) {
+    for (int64_t i = 0; i < nq; ++i) {
+        const int64_t q = qrows ? qrows[i] : i;
+        if (q < 0 || q >= n) {
+            fail = 1;
+            continue;
+        }
         const float *x = X + q * (int64_t)d;
         double *bd = (double *)malloc(sizeof(double) * (size_t)k);
         int64_t *bj = (int64_t *)malloc(sizeof(int64_t) * (size_t)k);
@@ -351,7 +358,7 @@ int oracle_knn_subset(const float *X, int64_t n, int d, int k, const int64_t *ca
         bd[0] = 0.0;
         bj[0] = q;
         int cnt = 1; /* slots [1, cnt) sorted ascending */
-        for (int64_t c = cand_off[q]; c < cand_off[q + 1]; ++c) {
+        for (int64_t c = cand_off[i]; c < cand_off[i + 1]; ++c) {
             int64_t j = cand_ids[c];
             if (j < 0 || j >= n) {
                 fail = 1;
@@ -376,7 +383,7 @@ int oracle_knn_subset(const float *X, int64_t n, int d, int k, const int64_t *ca
             bj[p] = j;
         }
         for (int s = 0; s < k; ++s) {
-            int64_t o = q * (int64_t)k + s;
+            int64_t o = i * (int64_t)k + s;
             out_idx[o] = (int32_t)(s < cnt ? bj[s] : -1);
             if (out_d2) out_d2[o] = s < cnt ? bd[s] : INFINITY;
             if (out_dist) out_dist[o] = s < cnt ? (float)sqrt(bd[s]) : INFINITY;

@@ -129,11 +129,12 @@ def probed_candidates(offsets: np.ndarray, perm: np.ndarray, probes: np.ndarray,
 
 
 def routed_knn(X: np.ndarray, k: int, offsets: np.ndarray, perm: np.ndarray, probes: np.ndarray,
-               exact_rows=None):
-    """Exact kNN of every row within its probed partitions (or all rows where
-    ``exact_rows`` is set).  Returns ``(idx, d2, dist)``."""
+               exact_rows=None, rows=None):
+    """Exact kNN of every row (or of ``rows``, whose probe lists and flags are
+    then given per selected row) within its probed partitions, or over all
+    rows where ``exact_rows`` is set.  Returns ``(idx, d2, dist)``."""
     off, ids = probed_candidates(offsets, perm, probes, exact_rows)
-    return knn_subset(X, k, off, ids)
+    return knn_subset(X, k, off, ids, rows=rows)
 
 
 def recall(found: np.ndarray, exact: np.ndarray) -> float:

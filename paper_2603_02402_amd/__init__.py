@@ -7,6 +7,10 @@ torch's current stream.  Functions mirror the C calls:
 * :func:`knn`             -> ``rsc_knn`` / ``rsc_knn_ex``
 * :func:`connectivities`  -> ``rsc_connectivities``
 * :func:`knn_graph`       -> both, the whole neighbourhood-graph step
+* :func:`knn_batched`     -> ``rsc_knn_batched`` (many samples, one launch)
+* :mod:`.routed`          -> partitions, the router network, probed and
+  routed kNN (``rsc_partition_*``, ``rsc_router_*``, ``rsc_knn_probed``,
+  ``rsc_knn_routed``)
 """
 
 from __future__ import annotations
@@ -21,7 +25,8 @@ __all__ = [
     "knn", "knn_graph", "connectivities", "knn_workspace_bytes", "connectivities_workspace_bytes",
     "read_knn_stats", "profile_enable", "profile_reset", "profile_get", "RscError", "Workspace",
     "RSC_FP32", "RSC_BF16", "RSC_FP8_E4M3", "abi_version", "knn_batched", "knn_batched_autotune",
-    "knn_batched_workspace_bytes",
+    "knn_batched_workspace_bytes", "Router", "partition_kmeans", "partition_lists", "partition_labels",
+    "knn_probed", "knn_routed",
 ]
 
 
@@ -244,3 +249,7 @@ def profile_get(name: str):
     cnt = ctypes.c_int64(0)
     check(load().rsc_profile_get(name.encode(), ctypes.byref(ms), ctypes.byref(cnt)))
     return float(ms.value), int(cnt.value)
+
+
+from .routed import (Router, knn_probed, knn_routed, partition_kmeans, partition_labels,  # noqa: E402
+                     partition_lists)

@@ -48,6 +48,15 @@ class KnnStats(ctypes.Structure):
                 ("max_ref_norm", ctypes.c_float)]
 
 
+class RoutedStats(ctypes.Structure):
+    _fields_ = [("routed_rows", ctypes.c_int64), ("low_mass_rows", ctypes.c_int64),
+                ("uncertified_rows", ctypes.c_int64), ("escalated_rows", ctypes.c_int64),
+                ("rescanned_rows", ctypes.c_int64), ("mean_probed_rows", ctypes.c_double)]
+
+
+_U64 = ctypes.c_uint64
+_F = ctypes.c_float
+
 SIGNATURES = {
     "rsc_abi_version": (ctypes.c_int, []),
     "rsc_last_error": (ctypes.c_char_p, []),
@@ -62,6 +71,29 @@ SIGNATURES = {
     "rsc_batch_policy_name": (ctypes.c_char_p, [_I32]),
     "rsc_connectivities_workspace_bytes": (_SZ, [_I64, _I32]),
     "rsc_connectivities": (ctypes.c_int, [_P, _P, _I64, _I32, _P, _P, _P, _I64, _P, _P, _P, _P, _SZ, _P]),
+    "rsc_partition_kmeans_workspace_bytes": (_SZ, [_I64, _I32, _I32]),
+    "rsc_partition_kmeans": (ctypes.c_int, [_P, _I64, _I32, _I32, _P, _I32, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    "rsc_partition_labels": (ctypes.c_int, [_P, _I64, _I32, _P, _I64, _P, _P]),
+    "rsc_partition_lists_workspace_bytes": (_SZ, [_I32]),
+    "rsc_partition_lists": (ctypes.c_int, [_P, _I64, _I32, _P, _P, _P, _SZ, _P]),
+    "rsc_router_create": (ctypes.c_int, [_P, _I32, _I32, _I32, _U64]),
+    "rsc_router_destroy": (None, [_P]),
+    "rsc_router_info": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "rsc_router_train_workspace_bytes": (_SZ, [_P, _I32, _I64]),
+    "rsc_router_train": (ctypes.c_int, [_P, _P, _I64, _P, _I32, _I32, _I32, _F, _P, _P, _SZ, _P]),
+    "rsc_router_gradients_workspace_bytes": (_SZ, [_P, _I64]),
+    "rsc_router_gradients": (ctypes.c_int, [_P, _P, _I64, _P, _I32, _P, _P, _P, _SZ, _P]),
+    "rsc_router_infer_workspace_bytes": (_SZ, [_P]),
+    "rsc_router_logits": (ctypes.c_int, [_P, _P, _I64, _P, _P, _SZ, _P]),
+    "rsc_router_probe": (ctypes.c_int, [_P, _P, _I64, _I32, _P, _P, _P, _SZ, _P]),
+    "rsc_router_save": (ctypes.c_int, [_P, ctypes.c_char_p]),
+    "rsc_router_load": (ctypes.c_int, [_P, ctypes.c_char_p]),
+    "rsc_knn_probed_workspace_bytes": (_SZ, [_I64, _I32, _I32, _I32, _I32]),
+    "rsc_knn_probed": (ctypes.c_int, [_P, _I64, _I32, _I32, _P, _P, _I32, _P, _I32, _P, _P, _P, _P, _P, _P, _SZ,
+                                      _P]),
+    "rsc_knn_routed_workspace_bytes": (_SZ, [_P, _I64, _I32, _I32, _I32, _I32]),
+    "rsc_knn_routed": (ctypes.c_int, [_P, _P, _I64, _I32, _I32, _P, _P, _I32, _I32, _F, _P, _P, _P, _P, _P, _SZ,
+                                      _P]),
     "rsc_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "rsc_profile_reset": (ctypes.c_int, []),
     "rsc_profile_get": (ctypes.c_int, [ctypes.c_char_p, _P, _P]),

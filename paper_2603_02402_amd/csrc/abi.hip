@@ -263,6 +263,216 @@ int rsc_connectivities(const int32_t *idx, const float *dist, int64_t n, int32_t
                      static_cast<hipStream_t>(stream));
 }
 
+size_t rsc_partition_kmeans_workspace_bytes(int64_t n, int32_t d, int32_t parts) {
+    if (n > INT32_MAX - 1 || d > 128) return 0;
+    return kmeans_workspace_bytes(n, d, parts);
+}
+
+int rsc_partition_kmeans(const float *X, int64_t n, int32_t d, int32_t parts, const int32_t *init_rows,
+                         int32_t iters, float *centroids, int32_t *assign, int64_t *offsets, int32_t *perm,
+                         int64_t *relocated, void *workspace, size_t workspace_bytes, void *stream) {
+    clear_error();
+    if (!aligned(X, 4) || !aligned(init_rows, 4) || !aligned(centroids, 4) || !aligned(assign, 4) ||
+        !aligned(offsets, 8) || !aligned(perm, 4)) {
+        set_error("misaligned array");
+        return RSC_ERR_INVALID_ARG;
+    }
+    return kmeans_run(X, n, d, parts, init_rows, iters, centroids, assign, offsets, perm, relocated, workspace,
+                      workspace_bytes, static_cast<hipStream_t>(stream));
+}
+
+size_t rsc_partition_lists_workspace_bytes(int32_t parts) {
+    return parts < 1 ? 0 : partition_lists_workspace_bytes(parts);
+}
+
+int rsc_partition_lists(const int32_t *labels, int64_t n, int32_t parts, int64_t *offsets, int32_t *perm,
+                        void *workspace, size_t workspace_bytes, void *stream) {
+    clear_error();
+    if (!aligned(labels, 4) || !aligned(offsets, 8) || !aligned(perm, 4) || !aligned(workspace, 256)) {
+        set_error("misaligned array or workspace");
+        return RSC_ERR_INVALID_ARG;
+    }
+    return partition_lists(labels, n, parts, offsets, perm, workspace, workspace_bytes,
+                           static_cast<hipStream_t>(stream));
+}
+
+int rsc_partition_labels(const int32_t *idx, int64_t n, int32_t k, const int32_t *assign, int64_t n_assign,
+                         int32_t *labels, void *stream) {
+    clear_error();
+    if (!aligned(idx, 4) || !aligned(assign, 4) || !aligned(labels, 4)) {
+        set_error("misaligned array");
+        return RSC_ERR_INVALID_ARG;
+    }
+    return partition_labels(idx, n, k, assign, n_assign, labels, static_cast<hipStream_t>(stream));
+}
+
+int rsc_router_create(rsc_router **out, int32_t d, int32_t hidden, int32_t parts, uint64_t seed) {
+    clear_error();
+    return router_create(out, d, hidden, parts, seed);
+}
+
+void rsc_router_destroy(rsc_router *router) { router_destroy(router); }
+
+int rsc_router_info(const rsc_router *router, int32_t *d, int32_t *hidden, int32_t *parts, int64_t *n_params,
+                    int64_t *steps) {
+    clear_error();
+    int dd = 0, hh = 0, pp = 0;
+    const int st = router_info(router, &dd, &hh, &pp, n_params, steps);
+    if (st == RSC_OK) {
+        if (d) *d = dd;
+        if (hidden) *hidden = hh;
+        if (parts) *parts = pp;
+    }
+    return st;
+}
+
+size_t rsc_router_train_workspace_bytes(const rsc_router *router, int32_t batch, int64_t n) {
+    return router_train_workspace(router, batch, n);
+}
+
+int rsc_router_train(rsc_router *router, const float *X, int64_t n, const int32_t *labels, int32_t m,
+                     int32_t epochs, int32_t batch, float lr, float *loss_log, void *workspace,
+                     size_t workspace_bytes, void *stream) {
+    clear_error();
+    if (!aligned(labels, 4) || !aligned(workspace, 256)) {
+        set_error("misaligned labels or workspace");
+        return RSC_ERR_INVALID_ARG;
+    }
+    return router_train(router, X, n, labels, m, epochs, batch, lr, loss_log, workspace, workspace_bytes,
+                        static_cast<hipStream_t>(stream));
+}
+
+size_t rsc_router_gradients_workspace_bytes(const rsc_router *router, int64_t n) {
+    return router_gradients_workspace(router, n);
+}
+
+int rsc_router_gradients(const rsc_router *router, const float *X, int64_t n, const int32_t *labels, int32_t m,
+                         float *grad, float *loss, void *workspace, size_t workspace_bytes, void *stream) {
+    clear_error();
+    if (!aligned(labels, 4) || !aligned(grad, 4) || !aligned(loss, 4) || !aligned(workspace, 256)) {
+        set_error("misaligned array or workspace");
+        return RSC_ERR_INVALID_ARG;
+    }
+    return router_gradients(router, X, n, labels, m, grad, loss, workspace, workspace_bytes,
+                            static_cast<hipStream_t>(stream));
+}
+
+size_t rsc_router_infer_workspace_bytes(const rsc_router *router) { return router_infer_workspace(router); }
+
+int rsc_router_logits(const rsc_router *router, const float *X, int64_t n, float *logits, void *workspace,
+                      size_t workspace_bytes, void *stream) {
+    clear_error();
+    if (!logits || !aligned(logits, 4) || !aligned(workspace, 256)) {
+        set_error("need an aligned logits array and workspace");
+        return RSC_ERR_INVALID_ARG;
+    }
+    return router_infer(router, X, n, nullptr, logits, 0, nullptr, nullptr, workspace, workspace_bytes,
+                        static_cast<hipStream_t>(stream));
+}
+
+int rsc_router_probe(const rsc_router *router, const float *X, int64_t n, int32_t probes, int32_t *parts,
+                     float *mass, void *workspace, size_t workspace_bytes, void *stream) {
+    clear_error();
+    if (!aligned(parts, 4) || !aligned(mass, 4) || !aligned(workspace, 256)) {
+        set_error("misaligned array or workspace");
+        return RSC_ERR_INVALID_ARG;
+    }
+    return router_infer(router, X, n, nullptr, nullptr, probes, parts, mass, workspace, workspace_bytes,
+                        static_cast<hipStream_t>(stream));
+}
+
+int rsc_router_save(const rsc_router *router, const char *path) {
+    clear_error();
+    return router_save(router, path);
+}
+
+int rsc_router_load(rsc_router *router, const char *path) {
+    clear_error();
+    return router_load(router, path);
+}
+
+size_t rsc_knn_probed_workspace_bytes(int64_t n, int32_t d, int32_t k, int32_t parts, int32_t probes) {
+    if (n > INT32_MAX - 1) return 0;
+    return probed_workspace_bytes(n, d, k, parts, probes);
+}
+
+int rsc_knn_probed(const float *X, int64_t n, int32_t d, int32_t k, const int64_t *offsets, const int32_t *perm,
+                   int32_t parts, const int32_t *probe_parts, int32_t probes, const uint8_t *exact_rows,
+                   int32_t *out_idx, float *out_dist, uint8_t *out_route, rsc_routed_stats *stats,
+                   void *workspace, size_t workspace_bytes, void *stream) {
+    clear_error();
+    if (!aligned(offsets, 8) || !aligned(perm, 4) || !aligned(probe_parts, 4) || !aligned(out_idx, 4)) {
+        set_error("misaligned array");
+        return RSC_ERR_INVALID_ARG;
+    }
+    return probed_run(X, n, d, k, offsets, perm, parts, probe_parts, probes, exact_rows, nullptr, 0.f, out_idx,
+                      out_dist, out_route, stats, workspace, workspace_bytes, static_cast<hipStream_t>(stream));
+}
+
+// Routed workspace: the probed search, then the router's scratch, the probe
+// lists (n x probes int32) and the masses (n float32).
+static size_t routed_layout(const rsc_router *router, int64_t n, int32_t d, int32_t k, int32_t parts,
+                            int32_t probes, void *ws, size_t *off_infer, size_t *off_parts, size_t *off_mass) {
+    const size_t a = probed_workspace_bytes(n, d, k, parts, probes);
+    const size_t b = router_infer_workspace(router);
+    if (a == 0 || b == 0) return 0;
+    Carver cv(ws);
+    cv.take<char>(a);
+    const size_t oi = cv.used;
+    cv.take<char>(b);
+    const size_t op = cv.used;
+    cv.take<int32_t>((size_t)n * probes);
+    const size_t om = cv.used;
+    cv.take<float>((size_t)n);
+    if (off_infer) *off_infer = oi;
+    if (off_parts) *off_parts = op;
+    if (off_mass) *off_mass = om;
+    return cv.used;
+}
+
+size_t rsc_knn_routed_workspace_bytes(const rsc_router *router, int64_t n, int32_t d, int32_t k, int32_t parts,
+                                      int32_t probes) {
+    if (!router || n > INT32_MAX - 1) return 0;
+    return routed_layout(router, n, d, k, parts, probes, nullptr, nullptr, nullptr, nullptr);
+}
+
+int rsc_knn_routed(const rsc_router *router, const float *X, int64_t n, int32_t d, int32_t k,
+                   const int64_t *offsets, const int32_t *perm, int32_t parts, int32_t probes, float mass_threshold,
+                   int32_t *out_idx, float *out_dist, uint8_t *out_route, rsc_routed_stats *stats, void *workspace,
+                   size_t workspace_bytes, void *stream) {
+    clear_error();
+    int rd = 0, rp = 0;
+    if (!router || router_shape(router, &rd, &rp) != RSC_OK || rd != d || rp != parts) {
+        set_error("knn_routed: the router's input width and partition count must equal d and parts");
+        return RSC_ERR_INVALID_ARG;
+    }
+    if (!aligned(offsets, 8) || !aligned(perm, 4) || !aligned(out_idx, 4) || !aligned(workspace, 256)) {
+        set_error("misaligned array or workspace");
+        return RSC_ERR_INVALID_ARG;
+    }
+    if (!(mass_threshold >= 0.f && mass_threshold <= 1.f)) {
+        set_error("knn_routed: mass_threshold must lie in [0, 1]");
+        return RSC_ERR_INVALID_ARG;
+    }
+    size_t oi = 0, op = 0, om = 0;
+    const size_t need = routed_layout(router, n, d, k, parts, probes, nullptr, &oi, &op, &om);
+    if (need == 0) {
+        set_error("knn_routed: unsupported size (need n >= k, d <= 128, k <= 63, parts <= 4096, probes <= 64)");
+        return RSC_ERR_UNSUPPORTED;
+    }
+    int st = check_ws(workspace, workspace_bytes, need);
+    if (st != RSC_OK) return st;
+    char *base = static_cast<char *>(workspace);
+    int32_t *parts_buf = reinterpret_cast<int32_t *>(base + op);
+    float *mass_buf = reinterpret_cast<float *>(base + om);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((st = router_infer(router, X, n, nullptr, nullptr, probes, parts_buf, mass_buf, base + oi, op - oi, s)) !=
+        RSC_OK)
+        return st;
+    return probed_run(X, n, d, k, offsets, perm, parts, parts_buf, probes, nullptr, mass_buf, mass_threshold,
+                      out_idx, out_dist, out_route, stats, workspace, oi, s);
+}
+
 int rsc_profile_enable(int enable) {
     Profiler &p = profiler();
     std::lock_guard<std::mutex> lock(p.mu);

@@ -88,7 +88,7 @@ __global__ __launch_bounds__(256) void k_pack(const float *__restrict__ R, const
                                               int d, int DH, int S4, int folded, int64_t nblk,
                                               f32x4 *__restrict__ Ap, float *__restrict__ Np,
                                               const int32_t *__restrict__ blk_sample, const int64_t *__restrict__ boff,
-                                              const int64_t *__restrict__ soff) {
+                                              const int64_t *__restrict__ soff, const int32_t *__restrict__ row_map) {
     const int64_t total = nblk * S4 * kWave;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
@@ -98,13 +98,18 @@ __global__ __launch_bounds__(256) void k_pack(const float *__restrict__ R, const
         const int64_t b = bs / S4;
         // row of lane (c, h); batched: blocks of sample s start at boff[s] and
         // hold rows soff[s]..soff[s+1]-1 (the last block of a sample is padded)
+        // routed form: packed row 32b + c holds row_map[32b + c] (-1: padding)
         int64_t row = 32 * b + (lane & 31), row_end = nr;
         if (blk_sample) {
             const int smp = blk_sample[b];
             row = soff[smp] + 32 * (b - boff[smp]) + (lane & 31);
             row_end = soff[smp + 1];
         }
-        const bool live = row < row_end;
+        bool live = row < row_end;
+        if (row_map) {
+            row = row_map[32 * b + (lane & 31)];
+            live = row >= 0;
+        }
         const int h = lane >> 5;
         f32x4 v;
         const int off = folded ? 1 : 0;  // the norm occupies step 0 when folded
@@ -469,8 +474,33 @@ int knn_prep_fp32(const KnnPlan &p, const float *R, const KnnBuffers &b, const i
     const unsigned g1 = (unsigned)std::min<int64_t>((tot + 255) / 256, 65536);
     hipLaunchKernelGGL(k_pack, dim3(g1), dim3(256), 0, stream, R, b.nrow, p.nr, p.d, p.dh, s4,
                        norm_folded(p.dh) ? 1 : 0, p.nblk, reinterpret_cast<f32x4 *>(b.packed), b.norms, blk_sample,
-                       boff, soff);
+                       boff, soff, nullptr);
     return launch_status("prep_pack");
+}
+
+int knn_norms(const float *R, int64_t nr, int d, float *nrow, KnnCounters *counters, hipStream_t stream) {
+    hipLaunchKernelGGL(k_init_counters, dim3(1), dim3(64), 0, stream, counters);
+    hipLaunchKernelGGL(k_norms, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, stream, R, nr, d, nrow,
+                       &counters->max_norm_bits);
+    return launch_status("norms");
+}
+
+int knn_pack_mapped(int dh, const float *R, const float *nrow, int64_t nr, int d, int64_t nblk, float *packed,
+                    float *norms, const int32_t *row_map, hipStream_t stream) {
+    const int s4 = packed_s4(dh);
+    ScopedTimer timer("prep_pack", stream);
+    const int64_t tot = nblk * s4 * kWave;
+    const unsigned g1 = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tot + 255) / 256, 65536));
+    hipLaunchKernelGGL(k_pack, dim3(g1), dim3(256), 0, stream, R, nrow, nr, d, dh, s4, norm_folded(dh) ? 1 : 0, nblk,
+                       reinterpret_cast<f32x4 *>(packed), norms, nullptr, nullptr, nullptr, row_map);
+    return launch_status("prep_pack");
+}
+
+size_t knn_packed_floats(int dh, int64_t nblk) { return (size_t)nblk * packed_s4(dh) * kWave * 4; }
+
+int knn_launch_screen(int dh, const scr::ScreenArgs &a, unsigned gx, int half_width, const char *name,
+                      hipStream_t s) {
+    return screen(dh, a, gx, half_width, name, s);
 }
 
 int knn_launch_rerank(const RerankArgs &ra, int64_t slots, const char *name, hipStream_t stream) {
@@ -614,19 +644,29 @@ int knn_run_lowp(const KnnPlan &p, const float *Q, const float *R, int32_t *out_
 }
 
 int knn_run(const KnnPlan &p, const float *Q, const float *R, int32_t *out_idx, float *out_dist, void *ws,
-            hipStream_t stream) {
+            hipStream_t stream, const int32_t *qlist, const int32_t *qcount) {
     KnnBuffers b;
     knn_workspace(p, ws, &b);
-    if (p.precision != RSC_FP32) return knn_run_lowp(p, Q, R, out_idx, out_dist, b, stream);
+    if (p.precision != RSC_FP32) {
+        if (qlist) {
+            set_error("internal: row lists need the FP32 path");
+            return RSC_ERR_UNSUPPORTED;
+        }
+        return knn_run_lowp(p, Q, R, out_idx, out_dist, b, stream);
+    }
     int st;
     if ((st = knn_prep_fp32(p, R, b, nullptr, nullptr, nullptr, stream)) != RSC_OK) return st;
     if (p.nq == 0) return RSC_OK;
 
     const double eps_coef = knn_eps_coefficient(p.d);
 
+    // Slots are rows 0..nq-1, or the first min(*qcount, nq) rows of qlist.
     ScreenArgs sa{};
     sa.Q = Q;
     sa.nq = p.nq;
+    sa.qlist = qlist;
+    sa.qcount = qcount;
+    sa.qcap = (int)p.nq;
     sa.Ap = b.packed;
     sa.Np = b.norms;
     sa.nblk = p.nblk;
@@ -641,6 +681,9 @@ int knn_run(const KnnPlan &p, const float *Q, const float *R, int32_t *out_idx, 
     RerankArgs ra{};
     ra.Q = Q;
     ra.nq = p.nq;
+    ra.qlist = qlist;
+    ra.qcount = qcount;
+    ra.qcap = (int)p.nq;
     ra.R = R;
     ra.d = p.d;
     ra.k = p.k;

@@ -111,8 +111,10 @@ struct RerankArgs {
 int knn_plan(int64_t nq, int64_t nr, int d, int k, const rsc_knn_opts *opts, bool self_mode, KnnPlan *plan);
 // Bytes of workspace for a plan; with ws != nullptr also carves the buffers.
 size_t knn_workspace(const KnnPlan &p, void *ws, KnnBuffers *out);
+// With qlist (device rows) the query slots are the first min(*qcount, p.nq)
+// rows of the list; outputs are written at those rows.
 int knn_run(const KnnPlan &p, const float *Q, const float *R, int32_t *out_idx, float *out_dist, void *ws,
-            hipStream_t stream);
+            hipStream_t stream, const int32_t *qlist = nullptr, const int32_t *qcount = nullptr);
 
 // Pieces of the exact path reused by the batched form (knn.hip).
 double knn_eps_coefficient(int d);
@@ -129,6 +131,16 @@ int knn_launch_rescan(const KnnPlan &p, const float *Q, const float *R, const Kn
 namespace scr {
 struct ScreenArgs;
 }
+// Squared norms of R's rows into nrow and their maximum into counters
+// (counters re-initialised).
+int knn_norms(const float *R, int64_t nr, int d, float *nrow, KnnCounters *counters, hipStream_t stream);
+// FP32 packing of nblk blocks whose packed row 32b + c is row_map[32b + c]
+// of R (-1: padding with an infinite norm).
+int knn_pack_mapped(int dh, const float *R, const float *nrow, int64_t nr, int d, int64_t nblk, float *packed,
+                    float *norms, const int32_t *row_map, hipStream_t stream);
+size_t knn_packed_floats(int dh, int64_t nblk);
+int knn_launch_screen(int dh, const scr::ScreenArgs &a, unsigned gx, int half_width, const char *name,
+                      hipStream_t s);
 // Reduced-precision screens (knn_lowp.hip).
 int lowp_steps(int precision, int d);
 int lowp_qb(int precision, int d);
@@ -145,6 +157,44 @@ int batched_run(const float *X, const int64_t *offsets, int S, int d, int k, int
 int batched_autotune(const float *X, const int64_t *offsets, int S, int d, int k, void *ws, size_t ws_bytes,
                      hipStream_t s, int32_t *chosen, float *times_ms);
 const char *batched_policy_name(int pol);
+
+// ---- routed form (partition.hip, router.hip, routed.hip) -----------------
+
+size_t kmeans_workspace_bytes(int64_t n, int d, int P);
+int kmeans_run(const float *X, int64_t n, int d, int P, const int32_t *init_rows, int iters, float *C,
+               int32_t *assign, int64_t *offsets, int32_t *perm, int64_t *relocated, void *ws, size_t ws_bytes,
+               hipStream_t s);
+size_t partition_lists_workspace_bytes(int P);
+int partition_lists(const int32_t *assign, int64_t n, int P, int64_t *offsets, int32_t *perm, void *ws,
+                    size_t ws_bytes, hipStream_t s);
+int partition_labels(const int32_t *idx, int64_t n, int k, const int32_t *assign, int64_t n_assign, int32_t *labels,
+                     hipStream_t s);
+
+int router_create(rsc_router **out, int d, int hidden, int parts, uint64_t seed);
+void router_destroy(rsc_router *R);
+int router_info(const rsc_router *R, int *d, int *hidden, int *parts, int64_t *n_params, int64_t *step);
+size_t router_train_workspace(const rsc_router *R, int batch, int64_t n);
+int router_train(rsc_router *R, const float *X, int64_t n, const int32_t *labels, int m, int epochs, int batch,
+                 float lr, float *loss_log, void *ws, size_t ws_bytes, hipStream_t s);
+size_t router_gradients_workspace(const rsc_router *R, int64_t n);
+int router_gradients(const rsc_router *R, const float *X, int64_t n, const int32_t *labels, int m, float *grad_out,
+                     float *loss_out, void *ws, size_t ws_bytes, hipStream_t s);
+size_t router_infer_workspace(const rsc_router *R);
+// Logits (logits != nullptr) or the top `probes` partitions and their mass
+// of n rows (rows of X, or X[list[i]]).
+int router_infer(const rsc_router *R, const float *X, int64_t n, const int32_t *list, float *logits, int probes,
+                 int32_t *parts, float *mass, void *ws, size_t ws_bytes, hipStream_t s);
+int router_save(const rsc_router *R, const char *path);
+int router_load(rsc_router *R, const char *path);
+int router_shape(const rsc_router *R, int *d, int *parts);
+
+size_t probed_workspace_bytes(int64_t n, int d, int k, int P, int probes);
+// mass/threshold: rows whose mass is below the threshold go to exact search
+// (instead of, or besides, exact_rows).
+int probed_run(const float *X, int64_t n, int d, int k, const int64_t *offsets, const int32_t *perm, int P,
+               const int32_t *probe_parts, int probes, const uint8_t *exact_rows, const float *mass,
+               float threshold, int32_t *out_idx, float *out_dist, uint8_t *out_route, rsc_routed_stats *stats,
+               void *ws, size_t ws_bytes, hipStream_t s);
 
 // ---- graph stages (graph.hip) --------------------------------------------
 

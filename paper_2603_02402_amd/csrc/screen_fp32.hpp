@@ -42,36 +42,41 @@ __device__ __forceinline__ void load_group(f32x4 (&A)[S4], const f32x4 *wb, int 
 // holds reference row 8(v/4) + 4h + (v%4), so each lane sees half of the
 // references of every block and keeps its own sorted list of the L smallest
 // keys of that half.
-//
-// slot: this lane's output slot (or -1); row: its query row (or -1);
-// blocks [blk0, blk1) of the packed array; p: the range index the lists are
-// filed under; ref_base: reference row of packed row 0 (row of a key =
-// ref_base + 32 blk + 8(v/4) + 4h + (v%4)).  All lanes of the workgroup call
-// this together.
-template <int DH, int L>
-__device__ __forceinline__ void screen_fp32_tile(const ScreenArgs &a, int64_t slot, int64_t row, int64_t blk0,
-                                                 int64_t blk1, int p, int64_t ref_base, float2 *qbuf) {
+
+// Query operand of one lane: -2 x (exact scaling) over the lane's half of
+// the contraction, plus the factor 1 of the folded norm step.
+template <int DH>
+struct Fp32Query {
+    static constexpr bool NF = norm_folded(DH);
+    static constexpr int STEPS = DH + (NF ? 1 : 0);
+    float b[STEPS];
+
+    __device__ __forceinline__ void load(const ScreenArgs &a, int64_t row, int h) {
+        constexpr int OFF = NF ? 1 : 0;  // step 0 carries the norm when folded
+#pragma unroll
+        for (int s = 0; s < DH; ++s) {
+            const int t = h * DH + s;
+            b[OFF + s] = (row >= 0 && t < a.d) ? -2.f * a.Q[row * a.d + t] : 0.f;
+        }
+        if constexpr (NF) b[0] = (row >= 0 && h == 0) ? 1.f : 0.f;
+    }
+};
+
+// Stream packed blocks [blk0, blk1) through the MFMA chain and offer the
+// keys to `top` (row of a key = ref_base + 32 blk + 8(v/4) + 4h + (v%4)).
+// With MASK, lanes whose `active` is false offer nothing (their keys are
+// treated as +inf); the wave still runs every MFMA.  Every lane of the wave
+// calls this together.
+template <int DH, int L, bool MASK = false>
+__device__ __forceinline__ void scan_blocks(const ScreenArgs &a, const Fp32Query<DH> &qop, LaneTopK<L> &top,
+                                            int64_t blk0, int64_t blk1, int64_t ref_base, float2 *q,
+                                            bool active = true) {
     constexpr bool NF = norm_folded(DH);
     constexpr int STEPS = DH + (NF ? 1 : 0);
     constexpr int S4 = packed_s4(DH);
-    const int tid = threadIdx.x;
-    const int lane = tid & (kWave - 1);
+    const int lane = threadIdx.x & (kWave - 1);
     const int h = lane >> 5;
     const f32x4 *Ap = static_cast<const f32x4 *>(a.Ap);
-
-    // Query operand, resident for the whole range; -2 folded in (exact).
-    constexpr int OFF = NF ? 1 : 0;  // step 0 carries the norm when folded
-    float b[STEPS];
-#pragma unroll
-    for (int s = 0; s < DH; ++s) {
-        const int t = h * DH + s;
-        b[OFF + s] = (row >= 0 && t < a.d) ? -2.f * a.Q[row * a.d + t] : 0.f;
-    }
-    if constexpr (NF) b[0] = (row >= 0 && h == 0) ? 1.f : 0.f;
-
-    LaneTopK<L> top;
-    top.init();
-    float2 *q = qbuf + tid;
 
     f32x4 A[S4] = {};
     if (blk0 < blk1) {
@@ -100,7 +105,7 @@ __device__ __forceinline__ void screen_fp32_tile(const ScreenArgs &a, int64_t sl
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int s = 4 * s4 + u;
-                if (s < STEPS) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(A[s4][u], b[s], acc, 0, 0, 0);
+                if (s < STEPS) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(A[s4][u], qop.b[s], acc, 0, 0, 0);
             }
             load_group<STEPS, S4>(A, wb, s4, lane);  // consumed: fetch its successor
             // keep each load right behind the MFMAs that freed its registers
@@ -110,9 +115,29 @@ __device__ __forceinline__ void screen_fp32_tile(const ScreenArgs &a, int64_t sl
 #pragma unroll
             for (int v = 0; v < 16; ++v) acc[v] += nv[v >> 2][v & 3];
         }
+        if constexpr (MASK) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[v] = active ? acc[v] : INFINITY;
+        }
 
         top.offer(acc, (int)(ref_base + blk * 32) + 4 * h, q, 256);
     }
+}
+
+// One tile: slot: this lane's output slot (or -1); row: its query row (or
+// -1); blocks [blk0, blk1) of the packed array; p: the range index the lists
+// are filed under; ref_base: reference row of packed row 0.
+template <int DH, int L>
+__device__ __forceinline__ void screen_fp32_tile(const ScreenArgs &a, int64_t slot, int64_t row, int64_t blk0,
+                                                 int64_t blk1, int p, int64_t ref_base, float2 *qbuf) {
+    const int tid = threadIdx.x;
+    const int h = (tid & (kWave - 1)) >> 5;
+    Fp32Query<DH> qop;
+    qop.load(a, row, h);
+    LaneTopK<L> top;
+    top.init();
+    float2 *q = qbuf + tid;
+    scan_blocks<DH, L>(a, qop, top, blk0, blk1, ref_base, q);
     top.flush(q, 256);
     if (slot >= 0) top.store(a, slot, p, h);
 }

@@ -43,6 +43,11 @@ __all__ = [
     "sample_rows",
     "lattice_1d",
     "random_knn_lists",
+    "routed_draws",
+    "init_rows",
+    "random_probes",
+    "random_mask",
+    "random_labels",
 ]
 
 _CHUNK = 1 << 18  # rows drawn per call; the PCG64 stream is identical to one big draw
@@ -139,6 +144,55 @@ WORKLOADS = {
     "plain_1m": MixtureSpec(n=1_000_000, n_clusters=100, law="zipf", seed=1),
     "precision_2m": MixtureSpec(n=2_000_000, n_clusters=100, law="zipf", seed=2),
 }
+
+# Learned-router form: 500 rank-Zipf clusters; the centres come from one seed,
+# the base cells and the held-out training cells from two more.
+ROUTED = {"n_base": 5_000_000, "n_train": 1_000_000, "n_clusters": 500, "law": "zipf", "centre_seed": 5,
+          "base_seed": 50, "train_seed": 51, "parts": 4096}
+
+
+def routed_draws(n_base: int | None = None, n_train: int | None = None, n_clusters: int | None = None,
+                 d: int = 50):
+    """``(base, train)`` of the routed form: two draws around the same centres."""
+    c = ROUTED["n_clusters"] if n_clusters is None else n_clusters
+    centres = draw_centres(_rng(ROUTED["centre_seed"]), c, d)
+    w = cluster_weights(c, ROUTED["law"])
+    base = mixture_from_centres(_rng(ROUTED["base_seed"]), centres, ROUTED["n_base"] if n_base is None else n_base, w)
+    train = mixture_from_centres(_rng(ROUTED["train_seed"]), centres,
+                                 ROUTED["n_train"] if n_train is None else n_train, w)
+    return base, train
+
+
+def init_rows(n: int, parts: int, seed: int) -> np.ndarray:
+    """Distinct row ids (int32) whose rows seed the partition centroids."""
+    return _rng(seed).choice(n, size=parts, replace=False).astype(np.int32)
+
+
+def random_probes(n: int, parts: int, probes: int, seed: int, own: np.ndarray | None = None,
+                  blank: float = 0.05, repeat: float = 0.05) -> np.ndarray:
+    """Probe lists (int32 ``n x probes``) of random partitions: slot 0 is the
+    row's own partition when ``own`` is given; a fraction of the other slots
+    is left empty (-1) or repeats an earlier slot."""
+    rng = _rng(seed)
+    P = rng.integers(0, parts, size=(n, probes)).astype(np.int32)
+    if own is not None:
+        P[:, 0] = own
+    if probes > 1:
+        u = rng.random((n, probes))
+        src = rng.integers(0, np.arange(1, probes + 1)[None, :].repeat(n, 0))
+        rep = np.take_along_axis(P, src, axis=1)
+        P = np.where((u < repeat) & (np.arange(probes) > 0), rep, P)
+        P = np.where((u > 1 - blank) & (np.arange(probes) > 0), -1, P)
+    return P
+
+
+def random_mask(n: int, fraction: float, seed: int) -> np.ndarray:
+    """A seeded uint8 mask with about ``fraction`` ones."""
+    return (_rng(seed).random(n) < fraction).astype(np.uint8)
+
+
+def random_labels(n: int, parts: int, seed: int) -> np.ndarray:
+    return _rng(seed).integers(0, parts, size=n).astype(np.int32)
 
 
 def workload(name: str, n: int | None = None) -> np.ndarray:

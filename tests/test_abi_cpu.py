@@ -173,3 +173,46 @@ def test_batched_validation(lib):
     assert lib.rsc_knn_batched_workspace_bytes(bad.ctypes.data_as(ctypes.c_void_p), 2, 50, 15) == 0
     assert lib.rsc_batch_policy_name(0) != b""
     assert lib.rsc_batch_policy_name(99) == b""
+
+
+def test_routed_validation(lib):
+    from paper_2603_02402_amd import _lib
+
+    st = _lib.RoutedStats()
+
+    def probed(n=1000, d=50, k=15, parts=64, probes=8, ws_bytes=1 << 40, X=FAKE):
+        return lib.rsc_knn_probed(X, n, d, k, FAKE, FAKE, parts, FAKE, probes, None, FAKE, FAKE, None,
+                                  ctypes.byref(st), ctypes.c_void_p(0x100000), ws_bytes, None)
+
+    assert probed(k=0) == -1
+    assert probed(k=1001) == -1
+    assert probed(parts=8193) == -6 and "8192" in _err(lib)
+    assert probed(probes=65) == -6
+    assert probed(d=129) == -6
+    assert probed(n=2**31) == -5
+    assert probed(X=None) == -1
+    assert probed(ws_bytes=1000) == -7 and "workspace" in _err(lib)
+    assert lib.rsc_knn_probed_workspace_bytes(1000, 50, 15, 64, 8) > 1000 * 8 * 4
+    assert lib.rsc_knn_probed_workspace_bytes(1000, 50, 15, 9000, 8) == 0
+
+    h = ctypes.c_void_p(0)
+    assert lib.rsc_router_create(ctypes.byref(h), 50, 100, 64, 0) == -1 and "multiple of 64" in _err(lib)
+    assert lib.rsc_router_create(ctypes.byref(h), 50, 64, 8192, 0) == -1
+    assert lib.rsc_router_create(ctypes.byref(h), 0, 64, 64, 0) == -1
+    assert lib.rsc_router_info(None, None, None, None, None, None) == -1
+    assert lib.rsc_router_train_workspace_bytes(None, 64, 10) == 0
+    assert lib.rsc_knn_routed_workspace_bytes(None, 10, 50, 5, 64, 8) == 0
+    lib.rsc_router_destroy(None)
+
+    def kmeans(n=1000, d=50, parts=64, iters=5, ws_bytes=1 << 40):
+        return lib.rsc_partition_kmeans(FAKE, n, d, parts, FAKE, iters, FAKE, FAKE, None, None, None,
+                                        ctypes.c_void_p(0x100000), ws_bytes, None)
+
+    assert kmeans(parts=1001) == -1
+    assert kmeans(iters=-1) == -1
+    assert kmeans(d=129) == -1
+    assert kmeans(ws_bytes=100) == -7
+    assert lib.rsc_partition_kmeans_workspace_bytes(1000, 50, 64) > 1000 * 4
+    assert lib.rsc_partition_kmeans_workspace_bytes(10, 50, 64) == 0
+    assert lib.rsc_partition_lists(FAKE, 10, 0, FAKE, FAKE, ctypes.c_void_p(0x100000), 1 << 20, None) == -1
+    assert lib.rsc_partition_labels(None, 10, 3, FAKE, 10, FAKE, None) == -1
