@@ -341,7 +341,8 @@ typedef struct {
     int64_t uncertified_rows; /* exact search: the screen of the probed partitions was not certified */
     int64_t escalated_rows;   /* exact-search rows screened again, wider */
     int64_t rescanned_rows;   /* exact-search rows recomputed exhaustively in float64 */
-    double mean_probed_rows;  /* mean candidates per routed row */
+    double mean_probed_rows;  /* mean candidates per probed row (rows of its probed partitions) */
+    double mean_screened_rows; /* mean rows streamed past a probed row (the partitions its tile probes) */
 } rsc_routed_stats;
 
 /* Workspace bytes for rsc_knn_probed / rsc_knn_routed. */

@@ -51,7 +51,8 @@ class KnnStats(ctypes.Structure):
 class RoutedStats(ctypes.Structure):
     _fields_ = [("routed_rows", ctypes.c_int64), ("low_mass_rows", ctypes.c_int64),
                 ("uncertified_rows", ctypes.c_int64), ("escalated_rows", ctypes.c_int64),
-                ("rescanned_rows", ctypes.c_int64), ("mean_probed_rows", ctypes.c_double)]
+                ("rescanned_rows", ctypes.c_int64), ("mean_probed_rows", ctypes.c_double),
+                ("mean_screened_rows", ctypes.c_double)]
 
 
 _U64 = ctypes.c_uint64

@@ -48,7 +48,8 @@ struct RoutedCounters {
     int32_t tile_next;  // persistent-grid work counter
     int32_t bad;        // malformed partitions or probe lists
     int32_t pad[2];
-    unsigned long long probed_cells;  // candidates over all probed rows
+    unsigned long long probed_cells;    // candidates over all probed rows
+    unsigned long long screened_cells;  // rows streamed past each probed query (its tile's union)
 };
 
 struct RoutedBuffers {
@@ -135,6 +136,7 @@ __global__ void k_routed_init(RoutedCounters *rc) {
         rc->tile_next = 0;
         rc->bad = 0;
         rc->probed_cells = 0ull;
+        rc->screened_cells = 0ull;
     }
 }
 
@@ -310,6 +312,53 @@ __global__ __launch_bounds__(256) void k_fill_conf(int64_t n, const uint8_t *__r
     }
 }
 
+// Order the probed queries of each partition by their second and third
+// probes (then by row), so that the 32 queries of a tile probe nearly the
+// same partitions and their union stays small.  One workgroup per
+// partition, bitonic sort in LDS; a partition with more than kSegSort
+// probed queries keeps its fill order.
+constexpr int kSegSort = 4096;
+
+__global__ __launch_bounds__(1024) void k_order_tiles(const int32_t *__restrict__ probe_parts, int np, int P,
+                                                      const int64_t *__restrict__ coff,
+                                                      const int32_t *__restrict__ ccount,
+                                                      int32_t *__restrict__ qperm) {
+    __shared__ int2 e[kSegSort];  // (key, row)
+    const int p = blockIdx.x;
+    const int c = ccount[p];
+    if (c <= kTileQ || c > kSegSort) return;
+    const int64_t base = coff[p];
+    int n2 = kTileQ;
+    while (n2 < c) n2 <<= 1;
+    for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+        if (i < c) {
+            const int32_t row = qperm[base + i];
+            const int32_t *pr = probe_parts + (int64_t)row * np;
+            const int k1 = np > 1 ? pr[1] + 1 : 0, k2 = np > 2 ? pr[2] + 1 : 0;  // -1 entries -> 0
+            e[i] = make_int2(k1 * (P + 1) + k2, row);
+        } else {
+            e[i] = make_int2(INT_MAX, INT_MAX);
+        }
+    }
+    __syncthreads();
+    for (int size = 2; size <= n2; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = threadIdx.x; i < n2 / 2; i += blockDim.x) {
+                const int lo = 2 * stride * (i / stride) + (i % stride), hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const int2 a = e[lo], b = e[hi];
+                const bool gt = a.x > b.x || (a.x == b.x && a.y > b.y);
+                if (gt == up) {
+                    e[lo] = b;
+                    e[hi] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < c; i += blockDim.x) qperm[base + i] = e[i].y;
+}
+
 __global__ __launch_bounds__(256) void k_fill_tiles(int P, const int32_t *__restrict__ ccount,
                                                     const int64_t *__restrict__ coff,
                                                     const int64_t *__restrict__ toff, int2 *__restrict__ tiles) {
@@ -339,6 +388,7 @@ struct RoutedScreenArgs {
     const int32_t *ntiles;
     int32_t *tile_next;
     const int32_t *map;          // packed row -> cell
+    unsigned long long *screened;  // statistics: union rows x tile queries
 };
 
 template <int DH, int L>
@@ -381,22 +431,67 @@ __global__ __launch_bounds__(256, screen_min_waves(DH, L)) void k_screen_routed(
         top.init();
         int ptr = 0;
         int nextp = row >= 0 ? pr[0] : INT_MAX;
-        for (int w = 0; w < nwords; ++w) {
-            uint32_t bits = __builtin_amdgcn_readfirstlane(bm[w]);
-            while (bits) {
-                const int p = w * 32 + __builtin_ctz(bits);
-                bits &= bits - 1;
-                // every probe of this query below p has been consumed, so the
-                // query probed p exactly when its next probe is p
-                const bool active = nextp == p;
-                scan_blocks<DH, L, true>(a, qop, top, ra.pblk[p], ra.pblk[p + 1], 0, q, active);
-                if (active) {
+        int64_t union_blocks = 0;
+        // One continuous stream over the blocks of the union's partitions in
+        // ascending order: the next block (possibly the first of the next
+        // partition) is always in flight while the current one is screened.
+        int w = 0;
+        uint32_t bits = nwords > 0 ? __builtin_amdgcn_readfirstlane(bm[0]) : 0u;
+        auto next_part = [&]() -> int {  // next union partition, or -1
+            while (bits == 0u) {
+                if (++w >= nwords) return -1;
+                bits = __builtin_amdgcn_readfirstlane(bm[w]);
+            }
+            const int p = w * 32 + __builtin_ctz(bits);
+            bits &= bits - 1;
+            return p;
+        };
+        int p = next_part();
+        int64_t b0 = 0, b1 = 0;
+        while (p >= 0) {  // skip empty partitions
+            b0 = ra.pblk[p];
+            b1 = ra.pblk[p + 1];
+            if (b0 < b1) break;
+            if (nextp == p) {
+                ++ptr;
+                nextp = ptr < ra.np ? pr[ptr] : INT_MAX;
+            }
+            p = next_part();
+        }
+        f32x4 A[packed_s4(DH)] = {};
+        if (p >= 0) load_block<DH>(a, A, b0);
+        while (p >= 0) {
+            // every probe of this query below p has been consumed, so the
+            // query probed p exactly when its next probe is p
+            const bool active = nextp == p;
+            if (active) {
+                ++ptr;
+                nextp = ptr < ra.np ? pr[ptr] : INT_MAX;
+            }
+            union_blocks += b1 - b0;
+            // the following non-empty partition and its first block
+            int pn = next_part();
+            int64_t c0 = 0, c1 = 0;
+            while (pn >= 0) {
+                c0 = ra.pblk[pn];
+                c1 = ra.pblk[pn + 1];
+                if (c0 < c1) break;
+                if (nextp == pn) {
                     ++ptr;
                     nextp = ptr < ra.np ? pr[ptr] : INT_MAX;
                 }
+                pn = next_part();
             }
+            for (int64_t blk = b0; blk < b1; ++blk) {
+                const int64_t nxt = blk + 1 < b1 ? blk + 1 : (pn >= 0 ? c0 : blk);
+                screen_block<DH, L, true>(a, qop, top, A, blk, nxt, 0, q, active);
+            }
+            p = pn;
+            b0 = c0;
+            b1 = c1;
         }
         top.flush(q, 256);
+        if (lane == 0) atomicAdd(ra.screened, (unsigned long long)(union_blocks * 32 * tile.y));
         if (slot >= 0) {
             const int64_t base = (slot * 2 + h) * L;
 #pragma unroll
@@ -512,6 +607,8 @@ int probed_run(const float *X, int64_t n, int d, int k, const int64_t *offsets, 
                            &b.rc->ntiles, &b.rc->bad);
         hipLaunchKernelGGL(k_fill_conf, dim3(grid_for(n)), dim3(256), 0, s, n, b.route, b.own, b.coff, b.cursor,
                            b.qperm);
+        hipLaunchKernelGGL(k_order_tiles, dim3(P), dim3(1024), 0, s, probe_parts, probes, P, b.coff, b.ccount,
+                           b.qperm);
         hipLaunchKernelGGL(k_fill_tiles, dim3(grid_for(P)), dim3(256), 0, s, P, b.ccount, b.coff, b.toff, b.tiles);
         if ((st = launch_status("probed lists")) != RSC_OK) return st;
     }
@@ -551,6 +648,7 @@ int probed_run(const float *X, int64_t n, int d, int k, const int64_t *offsets, 
     ra.ntiles = &b.rc->ntiles;
     ra.tile_next = &b.rc->tile_next;
     ra.map = b.map;
+    ra.screened = &b.rc->screened_cells;
     if (hc.ntiles > 0 && (st = launch_routed(dh, ra, half, hc.ntiles, s)) != RSC_OK) return st;
 
     RerankArgs rr{};
@@ -614,6 +712,7 @@ int probed_run(const float *X, int64_t n, int d, int k, const int64_t *offsets, 
         stats->escalated_rows = es.escalated_rows;
         stats->rescanned_rows = es.rescanned_rows;
         stats->mean_probed_rows = hc.nconf > 0 ? (double)hc.probed_cells / (double)hc.nconf : 0.0;
+        stats->mean_screened_rows = hc.nconf > 0 ? (double)hc.screened_cells / (double)hc.nconf : 0.0;
     }
     return RSC_OK;
 }

@@ -116,6 +116,67 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const uint16_t *__restrict__ A,
     }
 }
 
+// The same product with 128 x 128 workgroup tiles: wave (wm, wn) owns a
+// 64 x 64 sub-tile of 2 x 2 MFMA blocks, so each 16-byte operand fragment
+// feeds two MFMAs and the four waves of a workgroup share every row they
+// load (L1).  Needs M and N multiples of 128.
+template <int EPI>
+__global__ __launch_bounds__(256) void k_gemm_nt128(const uint16_t *__restrict__ A, int lda,
+                                                    const uint16_t *__restrict__ B, int ldb, void *__restrict__ C,
+                                                    int ldc, const float *__restrict__ bias,
+                                                    const uint16_t *__restrict__ mask, int K) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c = lane & 31, h = lane >> 5;
+    const int64_t m0 = (int64_t)blockIdx.y * 128 + (wave >> 1) * 64;
+    const int64_t n0 = (int64_t)blockIdx.x * 128 + (wave & 1) * 64;
+    const uint16_t *ap0 = A + (m0 + c) * lda + 8 * h;
+    const uint16_t *ap1 = ap0 + (int64_t)32 * lda;
+    const uint16_t *bp0 = B + (n0 + c) * ldb + 8 * h;
+    const uint16_t *bp1 = bp0 + (int64_t)32 * ldb;
+    f32x16 acc[2][2] = {{f32x16{}, f32x16{}}, {f32x16{}, f32x16{}}};
+    i32x4 a0 = *reinterpret_cast<const i32x4 *>(ap0), a1 = *reinterpret_cast<const i32x4 *>(ap1);
+    i32x4 b0 = *reinterpret_cast<const i32x4 *>(bp0), b1 = *reinterpret_cast<const i32x4 *>(bp1);
+    for (int k0 = 16; k0 <= K; k0 += 16) {
+        i32x4 na0 = a0, na1 = a1, nb0 = b0, nb1 = b1;
+        if (k0 < K) {
+            na0 = *reinterpret_cast<const i32x4 *>(ap0 + k0);
+            na1 = *reinterpret_cast<const i32x4 *>(ap1 + k0);
+            nb0 = *reinterpret_cast<const i32x4 *>(bp0 + k0);
+            nb1 = *reinterpret_cast<const i32x4 *>(bp1 + k0);
+        }
+        const bf16x8 fa0 = __builtin_bit_cast(bf16x8, a0), fa1 = __builtin_bit_cast(bf16x8, a1);
+        const bf16x8 fb0 = __builtin_bit_cast(bf16x8, b0), fb1 = __builtin_bit_cast(bf16x8, b1);
+        acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa0, fb0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa0, fb1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa1, fb0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa1, fb1, acc[1][1], 0, 0, 0);
+        a0 = na0;
+        a1 = na1;
+        b0 = nb0;
+        b1 = nb1;
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int64_t m = m0 + 32 * i + 8 * (v >> 2) + 4 * h + (v & 3);
+                const int64_t n = n0 + 32 * j + c;
+                float x = acc[i][j][v];
+                if constexpr (EPI == kBiasReluBf16 || EPI == kBiasF32) x += bias[n];
+                if constexpr (EPI == kBiasReluBf16) {
+                    static_cast<uint16_t *>(C)[m * ldc + n] = to_bf16(fmaxf(x, 0.f));
+                } else if constexpr (EPI == kMaskBf16) {
+                    static_cast<uint16_t *>(C)[m * ldc + n] = mask[m * ldc + n] != 0 ? to_bf16(x) : (uint16_t)0;
+                } else {
+                    static_cast<float *>(C)[m * ldc + n] = x;
+                }
+            }
+        }
+    }
+}
+
 // C[R x C] -> out[C x R] (BF16), 64 x 64 tiles through LDS.
 __global__ __launch_bounds__(256) void k_transpose_bf16(const uint16_t *__restrict__ in, int rows, int cols,
                                                         uint16_t *__restrict__ out) {
@@ -297,11 +358,15 @@ __global__ __launch_bounds__(256) void k_init_params(float *__restrict__ w, Layo
 
 // Top `probes` partitions per row by logit (ties: lower index) and the
 // softmax mass they hold.  One wave per row: lane l holds columns l + 64 t
-// in registers, keeps its own best, and each round the wave-wide best (by
-// value, then column) is taken and its lane finds its next best.
+// in registers and keeps a sorted list of its 4 best not yet taken; each
+// round the wave-wide best head (by value, then column) is taken and only
+// its lane's list moves.  A lane whose list runs dry rebuilds it from the
+// values that come after the last one it gave up (rare: a lane holds more
+// than 4 of the winners only when they cluster in its columns).
 __global__ __launch_bounds__(256) void k_top_probes(const float *__restrict__ Z, int P, int nb, int probes,
                                                     int32_t *__restrict__ parts, float *__restrict__ mass) {
     constexpr int T = 4096 / kWave;  // registers per lane (P <= 4096)
+    constexpr int LL = 4;            // list length
     const int lane = threadIdx.x & 63;
     const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (r >= nb) return;
@@ -319,24 +384,44 @@ __global__ __launch_bounds__(256) void k_top_probes(const float *__restrict__ Z,
 #pragma unroll
     for (int t = 0; t < T; ++t) se += lane + kWave * t < P ? expf(v[t] - mx) : 0.f;
     for (int o = 32; o > 0; o >>= 1) se += __shfl_xor(se, o, kWave);
-    auto local_best = [&](float &b, int &bt) {
-        b = -INFINITY;
-        bt = -1;
+
+    // (value desc, t asc) order within the lane; t = -1 marks an empty slot
+    float lv[LL];
+    int lt[LL];
+    float fv = INFINITY;  // last value this lane gave up (floor); everything before it is taken
+    int ft = -1;
+    auto rebuild = [&]() {
+#pragma unroll
+        for (int i = 0; i < LL; ++i) {
+            lv[i] = -INFINITY;
+            lt[i] = -1;
+        }
 #pragma unroll
         for (int t = 0; t < T; ++t) {
-            if (v[t] > b) {
-                b = v[t];
-                bt = t;
+            const float x = v[t];
+            const bool after_floor = x < fv || (x == fv && t > ft);
+            const bool real = lane + kWave * t < P;
+            if (real && after_floor && (lt[LL - 1] < 0 || x > lv[LL - 1])) {
+                // insert (t ascending, so equal values keep index order)
+#pragma unroll
+                for (int i = LL - 1; i > 0; --i) {
+                    const bool shift = lt[i - 1] < 0 || x > lv[i - 1];
+                    const bool here = lt[i] < 0 || x > lv[i];
+                    lv[i] = shift ? lv[i - 1] : (here ? x : lv[i]);
+                    lt[i] = shift ? lt[i - 1] : (here ? t : lt[i]);
+                }
+                if (lt[0] < 0 || x > lv[0]) {
+                    lv[0] = x;
+                    lt[0] = t;
+                }
             }
         }
     };
-    float lb;
-    int lt;
-    local_best(lb, lt);
+    rebuild();
     float got = 0.f;
     for (int s = 0; s < probes; ++s) {
-        float best = lb;
-        int bi = lt < 0 ? INT32_MAX : lane + kWave * lt;
+        float best = lt[0] >= 0 ? lv[0] : -INFINITY;
+        int bi = lt[0] >= 0 ? lane + kWave * lt[0] : INT32_MAX;
         for (int o = 32; o > 0; o >>= 1) {
             const float ov = __shfl_xor(best, o, kWave);
             const int oi = __shfl_xor(bi, o, kWave);
@@ -350,11 +435,16 @@ __global__ __launch_bounds__(256) void k_top_probes(const float *__restrict__ Z,
             continue;
         }
         if ((bi & 63) == lane) {
-            const int tt = bi >> 6;
+            fv = lv[0];
+            ft = lt[0];
 #pragma unroll
-            for (int t = 0; t < T; ++t)
-                if (t == tt) v[t] = -INFINITY;
-            local_best(lb, lt);
+            for (int i = 0; i < LL - 1; ++i) {
+                lv[i] = lv[i + 1];
+                lt[i] = lt[i + 1];
+            }
+            lv[LL - 1] = -INFINITY;
+            lt[LL - 1] = -1;
+            if (lt[0] < 0) rebuild();
         }
         if (lane == 0) parts[(int64_t)r * probes + s] = bi;
         got += expf(best - mx) / se;
@@ -442,10 +532,17 @@ size_t carve_infer(const rsc_router *R, void *ws, InferBuffers *t) {
     return cv.used;
 }
 
+// C[M x N] = A[M x K] . B[N x K]^T with the fused epilogue; 128-wide tiles
+// when the shape allows them and still gives the chip enough workgroups.
 template <int EPI>
 int gemm(const uint16_t *A, int lda, const uint16_t *B, int ldb, void *C, int ldc, const float *bias,
          const uint16_t *mask, int M, int N, int K, hipStream_t s) {
-    hipLaunchKernelGGL((k_gemm_nt<EPI>), dim3(N / 64, M / 64), dim3(256), 0, s, A, lda, B, ldb, C, ldc, bias, mask, K);
+    if (M % 128 == 0 && N % 128 == 0 && (int64_t)(M / 128) * (N / 128) >= 512)
+        hipLaunchKernelGGL((k_gemm_nt128<EPI>), dim3(N / 128, M / 128), dim3(256), 0, s, A, lda, B, ldb, C, ldc,
+                           bias, mask, K);
+    else
+        hipLaunchKernelGGL((k_gemm_nt<EPI>), dim3(N / 64, M / 64), dim3(256), 0, s, A, lda, B, ldb, C, ldc, bias,
+                           mask, K);
     return launch_status("router gemm");
 }
 
@@ -715,15 +812,15 @@ int router_infer(const rsc_router *R, const float *X, int64_t n, const int32_t *
     ScopedTimer timer("router_infer", s);
     for (int64_t row0 = 0; row0 < n; row0 += kInferChunk) {
         const int nb = (int)std::min<int64_t>(kInferChunk, n - row0);
-        const int B = (nb + 63) / 64 * 64;
+        const int B = (nb + 127) / 128 * 128;  // 128-row tiles for the products
         if ((st = cast_rows(R, X, list, row0, nb, B, t.a0, s)) != RSC_OK) return st;
         float *z = logits ? nullptr : t.z;
         if (logits) {
-            // whole 64-row groups straight into the output; the ragged tail via the scratch
-            const int full = nb / 64 * 64;
+            // whole 128-row groups straight into the output; the ragged tail via the scratch
+            const int full = nb / 128 * 128;
             if (full > 0 && (st = forward(R, t.a0, t.h1, t.h2, logits + row0 * R->P, full, s)) != RSC_OK) return st;
             if (full < nb) {
-                if ((st = forward(R, t.a0 + (size_t)full * R->dp, t.h1, t.h2, t.z, 64, s)) != RSC_OK) return st;
+                if ((st = forward(R, t.a0 + (size_t)full * R->dp, t.h1, t.h2, t.z, 128, s)) != RSC_OK) return st;
                 if ((st = hip_status(hipMemcpyAsync(logits + (row0 + full) * R->P, t.z,
                                                     (size_t)(nb - full) * R->P * 4, hipMemcpyDeviceToDevice, s),
                                      "copy logits")) != RSC_OK)

@@ -62,65 +62,75 @@ struct Fp32Query {
     }
 };
 
-// Stream packed blocks [blk0, blk1) through the MFMA chain and offer the
-// keys to `top` (row of a key = ref_base + 32 blk + 8(v/4) + 4h + (v%4)).
-// With MASK, lanes whose `active` is false offer nothing (their keys are
-// treated as +inf); the wave still runs every MFMA.  Every lane of the wave
-// calls this together.
-template <int DH, int L, bool MASK = false>
-__device__ __forceinline__ void scan_blocks(const ScreenArgs &a, const Fp32Query<DH> &qop, LaneTopK<L> &top,
-                                            int64_t blk0, int64_t blk1, int64_t ref_base, float2 *q,
-                                            bool active = true) {
+// Issue the loads of packed block `blk` into A (in group order).
+template <int DH>
+__device__ __forceinline__ void load_block(const ScreenArgs &a, f32x4 (&A)[packed_s4(DH)], int64_t blk) {
+    constexpr int STEPS = DH + (norm_folded(DH) ? 1 : 0);
+    constexpr int S4 = packed_s4(DH);
+    const int lane = threadIdx.x & (kWave - 1);
+    const f32x4 *wb0 = static_cast<const f32x4 *>(a.Ap) + blk * (S4 * kWave);
+#pragma unroll
+    for (int s4 = 0; s4 < S4; ++s4) {
+        load_group<STEPS, S4>(A, wb0, s4, lane);
+        __builtin_amdgcn_sched_barrier(0);  // issue in group order, as the block step does
+    }
+}
+
+// One block of the chain: A holds block `blk`; its float4 groups are
+// replaced by those of block `nxt` as soon as the MFMAs have consumed them
+// (nxt may be blk itself at the end of a stream: always in bounds, so the
+// loads need no branch and stay in flight across the MFMAs).  The keys are
+// offered to `top` as rows ref_base + 32 blk + 8(v/4) + 4h + (v%4); with
+// MASK, a lane whose `active` is false offers nothing.
+template <int DH, int L, bool MASK>
+__device__ __forceinline__ void screen_block(const ScreenArgs &a, const Fp32Query<DH> &qop, LaneTopK<L> &top,
+                                             f32x4 (&A)[packed_s4(DH)], int64_t blk, int64_t nxt, int64_t ref_base,
+                                             float2 *q, bool active) {
     constexpr bool NF = norm_folded(DH);
     constexpr int STEPS = DH + (NF ? 1 : 0);
     constexpr int S4 = packed_s4(DH);
     const int lane = threadIdx.x & (kWave - 1);
     const int h = lane >> 5;
-    const f32x4 *Ap = static_cast<const f32x4 *>(a.Ap);
-
-    f32x4 A[S4] = {};
-    if (blk0 < blk1) {
-        const f32x4 *wb0 = Ap + blk0 * (S4 * kWave);
+    f32x4 nv[4];
+    if constexpr (!NF) {
+        const f32x4 *ns = reinterpret_cast<const f32x4 *>(a.Np + blk * 32 + h * 16);
 #pragma unroll
-        for (int s4 = 0; s4 < S4; ++s4) {
-            load_group<STEPS, S4>(A, wb0, s4, lane);
-            __builtin_amdgcn_sched_barrier(0);  // issue in group order, as the loop does
-        }
+        for (int g = 0; g < 4; ++g) nv[g] = ns[g];
     }
+    const f32x4 *wb = static_cast<const f32x4 *>(a.Ap) + nxt * (S4 * kWave);
+    f32x16 acc = f32x16{};
+#pragma unroll
+    for (int s4 = 0; s4 < S4; ++s4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int s = 4 * s4 + u;
+            if (s < STEPS) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(A[s4][u], qop.b[s], acc, 0, 0, 0);
+        }
+        load_group<STEPS, S4>(A, wb, s4, lane);  // consumed: fetch its successor
+        // keep each load right behind the MFMAs that freed its registers
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if constexpr (!NF) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[v] += nv[v >> 2][v & 3];
+    }
+    if constexpr (MASK) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[v] = active ? acc[v] : INFINITY;
+    }
+    top.offer(acc, (int)(ref_base + blk * 32) + 4 * h, q, 256);
+}
 
+// Stream packed blocks [blk0, blk1) through the MFMA chain and offer the
+// keys to `top`.  Every lane of the wave calls this together.
+template <int DH, int L>
+__device__ __forceinline__ void scan_blocks(const ScreenArgs &a, const Fp32Query<DH> &qop, LaneTopK<L> &top,
+                                            int64_t blk0, int64_t blk1, int64_t ref_base, float2 *q) {
+    f32x4 A[packed_s4(DH)] = {};
+    if (blk0 < blk1) load_block<DH>(a, A, blk0);
     for (int64_t blk = blk0; blk < blk1; ++blk) {
-        f32x4 nv[4];
-        if constexpr (!NF) {
-            const f32x4 *ns = reinterpret_cast<const f32x4 *>(a.Np + blk * 32 + h * 16);
-#pragma unroll
-            for (int g = 0; g < 4; ++g) nv[g] = ns[g];
-        }
-        // Next block (the last block re-reads itself: always in bounds,
-        // so the loads need no branch and stay in flight across the MFMAs).
         const int64_t nxt = blk + 1 < blk1 ? blk + 1 : blk;
-        const f32x4 *wb = Ap + nxt * (S4 * kWave);
-        f32x16 acc = f32x16{};
-#pragma unroll
-        for (int s4 = 0; s4 < S4; ++s4) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int s = 4 * s4 + u;
-                if (s < STEPS) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(A[s4][u], qop.b[s], acc, 0, 0, 0);
-            }
-            load_group<STEPS, S4>(A, wb, s4, lane);  // consumed: fetch its successor
-            // keep each load right behind the MFMAs that freed its registers
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        if constexpr (!NF) {
-#pragma unroll
-            for (int v = 0; v < 16; ++v) acc[v] += nv[v >> 2][v & 3];
-        }
-        if constexpr (MASK) {
-#pragma unroll
-            for (int v = 0; v < 16; ++v) acc[v] = active ? acc[v] : INFINITY;
-        }
-
-        top.offer(acc, (int)(ref_base + blk * 32) + 4 * h, q, 256);
+        screen_block<DH, L, false>(a, qop, top, A, blk, nxt, ref_base, q, true);
     }
 }
 

@@ -177,7 +177,7 @@ class Router:
 
 
 def _stats_dict(s: RoutedStats) -> dict:
-    return {f: (float(getattr(s, f)) if f == "mean_probed_rows" else int(getattr(s, f))) for f, _ in s._fields_}
+    return {f: (float(getattr(s, f)) if f.startswith("mean_") else int(getattr(s, f))) for f, _ in s._fields_}
 
 
 def _out(n, k, device, out):
