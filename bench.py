@@ -411,7 +411,8 @@ def main() -> int:
     ap.add_argument("--no-forms", action="store_true", help="skip the 2M-cell precision forms")
     ap.add_argument("--form-steps", type=int, default=3)
     ap.add_argument("--no-routed", action="store_true", help="skip the learned-router form")
-    ap.add_argument("--only-routed", action="store_true", help="run the learned-router form alone (no JSON line)")
+    ap.add_argument("--only", choices=["precision", "batched", "routed"],
+                    help="run one form alone and print its record (no benchmark line)")
     ap.add_argument("--routed-n", type=int, default=5_000_000)
     ap.add_argument("--routed-train", type=int, default=1_000_000)
     ap.add_argument("--routed-iters", type=int, default=10, help="k-means iterations")
@@ -437,8 +438,9 @@ def main() -> int:
         print("no GPU visible", file=sys.stderr)
         return 1
     rsc.load()
-    if args.only_routed:
-        print(json.dumps({"routed": routed_form(args, rsc)}), flush=True)
+    if args.only:
+        fn = {"precision": precision_forms, "batched": batched_form, "routed": routed_form}[args.only]
+        print(json.dumps({args.only: fn(args, rsc)}), flush=True)
         return 0
 
     w = WORKLOADS[args.workload]

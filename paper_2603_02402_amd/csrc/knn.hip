@@ -58,20 +58,31 @@ constexpr int kEscalateSplits = 16;
 constexpr int kEscalateWidth = 64;
 
 // Squared norms of the reference rows (float64 sum, rounded once) and the
-// largest norm.
-__global__ __launch_bounds__(256) void k_norms(const float *__restrict__ R, int64_t nr, int d,
-                                               float *__restrict__ nrow, uint32_t *__restrict__ max_norm_bits) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// largest norm.  One wave per 64 rows: the rows (contiguous in memory) are
+// copied into LDS with coalesced loads, then lane i sums row i.
+constexpr int kNormRows = 64;
+
+__global__ __launch_bounds__(64) void k_norms(const float *__restrict__ R, int64_t nr, int d,
+                                              float *__restrict__ nrow, uint32_t *__restrict__ max_norm_bits) {
+    __shared__ float buf[kNormRows * kMaxD];
+    const int lane = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * kNormRows;
+    const int rows = (int)min<int64_t>(kNormRows, nr - r0);
+    const float *src = R + r0 * d;
+    for (int e = lane; e < rows * d; e += kWave) buf[e] = src[e];
+    __syncthreads();
     float nf = 0.f;
-    if (r < nr) {
-        const float *x = R + r * d;
+    if (lane < rows) {
         double s = 0.0;
-        for (int t = 0; t < d; ++t) s += (double)x[t] * (double)x[t];
+        for (int t = 0; t < d; ++t) {
+            const double x = (double)buf[lane * d + t];
+            s += x * x;
+        }
         nf = (float)s;
-        nrow[r] = nf;
+        nrow[r0 + lane] = nf;
     }
     const float m = wave_max(sqrtf(nf));
-    if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(max_norm_bits, __float_as_uint(m));
+    if (lane == 0) atomicMax(max_norm_bits, __float_as_uint(m));
 }
 
 // Packed reference layout for a contraction half-width DH.  Block b holds
@@ -228,14 +239,27 @@ __device__ __forceinline__ void merge_sorted64(double &rd, int &rj, double d2, i
     }
 }
 
+// Candidate rows are staged through LDS 32 dimensions at a time: for each
+// batch of 64 candidates (one per lane) the wave copies the rows' chunk with
+// coalesced loads (two 128-byte row segments per instruction), then every
+// lane continues its own float64 sum in dimension order from LDS, so the
+// distances are those of exact_d2 bit for bit.
+constexpr int kRerankChunk = 32;
+
 __global__ __launch_bounds__(256) void k_rerank(RerankArgs a) {
+    __shared__ float tile[4][kWave][kRerankChunk + 1];
+    __shared__ float qrow[4][kMaxD];
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t slot = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x >> 6);
+    const int wave = threadIdx.x >> 6;
+    const int64_t slot = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave;
     int64_t nslots = a.nq;
     if (a.qlist) nslots = std::min<int64_t>(std::min<int64_t>(*a.qcount, a.qcap), a.nq);
     if (slot >= nslots) return;
     const int64_t row = a.qlist ? (int64_t)a.qlist[slot] : slot;
     const float *x = a.Q + row * a.d;
+    float(*T)[kRerankChunk + 1] = tile[wave];
+    float *xs = qrow[wave];
+    for (int t = lane; t < a.d; t += kWave) xs[t] = x[t];
 
     // ||x||^2 in float64 (only feeds the certificate's margin)
     double xx = 0.0;
@@ -265,22 +289,43 @@ __global__ __launch_bounds__(256) void k_rerank(RerankArgs a) {
     const int total = a.P * a.S;
     for (int c0 = 0; c0 < total; c0 += kWave) {
         const int ci = c0 + lane;
-        double d2 = INFINITY;
-        int jj = INT_MAX;
+        int j = -1;
+        float key = 0.f;
         if (ci < total) {
             const int p = ci / a.S, e = ci - (ci / a.S) * a.S;
-            const int j = a.cand_idx[cbase + p * a.KP + e];
-            if (j >= 0 && !(a.self_mode && j == row)) {
-                const float *y = a.R + (int64_t)j * a.d;
-                d2 = exact_d2(x, y, a.d);
-                jj = j;
-                double yy = 0.0;
-                for (int t = 0; t < a.d; ++t) yy += (double)y[t] * (double)y[t];
-                const double yn = sqrt(yy);
-                const float key = a.cand_key[cbase + p * a.KP + e];
-                const double err_bound = a.eps_coef * (2.0 * xn * yn + yy) + 1e-300;
-                ratio = fmaxf(ratio, (float)(fabs((double)key - (d2 - xx)) / err_bound));
+            j = a.cand_idx[cbase + p * a.KP + e];
+            key = a.cand_key[cbase + p * a.KP + e];
+        }
+        const bool valid = j >= 0 && !(a.self_mode && j == row);
+        const int jl = valid ? j : 0;  // a row of R that exists, loaded (and ignored) for empty slots
+        double s2 = 0.0, yy = 0.0;
+        for (int k0 = 0; k0 < a.d; k0 += kRerankChunk) {
+            const int w = min(kRerankChunk, a.d - k0);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // earlier reads of the tile are done
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll 4
+            for (int i = 0; i < kWave / 2; ++i) {
+                const int r = 2 * i + (lane >> 5), cc = lane & (kRerankChunk - 1);
+                const int jr = __shfl(jl, r, kWave);
+                if (cc < w) T[r][cc] = a.R[(int64_t)jr * a.d + k0 + cc];
             }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // the tile is written
+            __builtin_amdgcn_wave_barrier();
+            for (int t = 0; t < w; ++t) {
+                const double y = (double)T[lane][t];
+                const double diff = __dsub_rn((double)xs[k0 + t], y);
+                s2 = __dadd_rn(s2, __dmul_rn(diff, diff));
+                yy += y * y;
+            }
+        }
+        double d2 = INFINITY;
+        int jj = INT_MAX;
+        if (valid) {
+            d2 = s2;
+            jj = j;
+            const double yn = sqrt(yy);
+            const double err_bound = a.eps_coef * (2.0 * xn * yn + yy) + 1e-300;
+            ratio = fmaxf(ratio, (float)(fabs((double)key - (d2 - xx)) / err_bound));
         }
         bitonic_sort64(d2, jj, lane);
         if (c0 == 0) {
@@ -468,7 +513,8 @@ int knn_prep_fp32(const KnnPlan &p, const float *R, const KnnBuffers &b, const i
     const int s4 = packed_s4(p.dh);
     ScopedTimer timer("prep_pack", stream);
     hipLaunchKernelGGL(k_init_counters, dim3(1), dim3(64), 0, stream, b.counters);
-    hipLaunchKernelGGL(k_norms, dim3((unsigned)((p.nr + 255) / 256)), dim3(256), 0, stream, R, p.nr, p.d, b.nrow,
+    hipLaunchKernelGGL(k_norms, dim3((unsigned)((p.nr + kNormRows - 1) / kNormRows)), dim3(kNormRows), 0, stream, R,
+                       p.nr, p.d, b.nrow,
                        &b.counters->max_norm_bits);
     const int64_t tot = p.nblk * s4 * kWave;
     const unsigned g1 = (unsigned)std::min<int64_t>((tot + 255) / 256, 65536);
@@ -480,7 +526,8 @@ int knn_prep_fp32(const KnnPlan &p, const float *R, const KnnBuffers &b, const i
 
 int knn_norms(const float *R, int64_t nr, int d, float *nrow, KnnCounters *counters, hipStream_t stream) {
     hipLaunchKernelGGL(k_init_counters, dim3(1), dim3(64), 0, stream, counters);
-    hipLaunchKernelGGL(k_norms, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, stream, R, nr, d, nrow,
+    hipLaunchKernelGGL(k_norms, dim3((unsigned)((nr + kNormRows - 1) / kNormRows)), dim3(kNormRows), 0, stream, R, nr,
+                       d, nrow,
                        &counters->max_norm_bits);
     return launch_status("norms");
 }

@@ -38,7 +38,7 @@ namespace {
 using namespace scr;
 
 struct BatchItem {
-    int64_t q0;        // first query row
+    int64_t q0;        // first query row, or (with a row list) first list entry
     int64_t b0, b1;    // packed reference blocks [b0, b1)
     int64_t ref_base;  // reference row of packed row 0 for this sample
     int32_t nq;        // queries in the tile (<= 128)
@@ -50,6 +50,7 @@ struct BatchArgs {
     const BatchItem *items;
     int n_items;
     int32_t *counter;
+    const int32_t *rows;  // optional: query i of an item is row rows[q0 + i], filed under slot q0 + i
 };
 
 template <int DH, int L>
@@ -66,8 +67,9 @@ __global__ __launch_bounds__(256, screen_min_waves(DH, L)) void k_screen_batched
         if (it >= ba.n_items) break;
         const BatchItem I = ba.items[it];
         const bool live = qi < I.nq;
-        const int64_t row = live ? I.q0 + qi : -1;
-        screen_fp32_tile<DH, L>(ba.base, row, row, I.b0, I.b1, I.p, I.ref_base, qbuf);
+        const int64_t slot = live ? I.q0 + qi : -1;
+        const int64_t row = live ? (ba.rows ? (int64_t)ba.rows[slot] : slot) : -1;
+        screen_fp32_tile<DH, L>(ba.base, slot, row, I.b0, I.b1, I.p, I.ref_base, qbuf);
     }
 }
 
@@ -154,12 +156,18 @@ int build_plan(const int64_t *offsets, int S, int d, int k, const Policy &pol, B
     return RSC_OK;
 }
 
+constexpr int kEscCap = 8192;     // rows of the escalation pass (the rest are rescanned)
+constexpr int kEscRanges = 16;    // reference ranges per sample in the escalation pass
+constexpr int kEscHalf = 32;      // list length per contraction half (64-wide screen)
+
 struct BatchBuffers {
     KnnBuffers kb;
     BatchItem *items;
     int32_t *blk_sample;
     int64_t *boff, *soff;
     int32_t *counter;
+    BatchItem *esc_items;
+    int32_t *esc_rows, *esc_count;
 };
 
 // Workspace: the exact path's buffers for the concatenated problem, then the
@@ -176,6 +184,11 @@ size_t batch_workspace(const BatchPlan &bp, void *ws, BatchBuffers *out) {
     b.boff = cv.take<int64_t>((size_t)bp.S + 1);
     b.soff = cv.take<int64_t>((size_t)bp.S + 1);
     b.counter = cv.take<int32_t>(1);
+    // escalation: at most one partial tile per sample beyond the full ones
+    const size_t esc_items = ((size_t)kEscCap / QG + (size_t)bp.S) * kEscRanges;
+    b.esc_items = cv.take<BatchItem>(esc_items);
+    b.esc_rows = cv.take<int32_t>(kEscCap);
+    b.esc_count = cv.take<int32_t>(1);
     if (out) *out = b;
     return base + cv.used;
 }
@@ -200,17 +213,19 @@ int launch_batched_dh(const BatchArgs &ba, unsigned grid, int half, hipStream_t 
     return launch_status("screen_batched");
 }
 
-int launch_batched(const BatchPlan &bp, const BatchArgs &ba, hipStream_t s) {
-    ScopedTimer timer("screen_batched", s);
+int launch_batched(const BatchPlan &bp, const BatchArgs &ba, hipStream_t s, int half = 0,
+                   const char *name = "screen_batched") {
+    ScopedTimer timer(name, s);
+    if (half == 0) half = bp.kp.half;
     const unsigned grid = (unsigned)std::max(1, std::min<int>(device_slots(bp.kp.dh), ba.n_items));
     switch (bp.kp.dh) {
-        case 4: return launch_batched_dh<4>(ba, grid, bp.kp.half, s);
-        case 8: return launch_batched_dh<8>(ba, grid, bp.kp.half, s);
-        case 16: return launch_batched_dh<16>(ba, grid, bp.kp.half, s);
-        case 25: return launch_batched_dh<25>(ba, grid, bp.kp.half, s);
-        case 32: return launch_batched_dh<32>(ba, grid, bp.kp.half, s);
-        case 48: return launch_batched_dh<48>(ba, grid, bp.kp.half, s);
-        case 64: return launch_batched_dh<64>(ba, grid, bp.kp.half, s);
+        case 4: return launch_batched_dh<4>(ba, grid, half, s);
+        case 8: return launch_batched_dh<8>(ba, grid, half, s);
+        case 16: return launch_batched_dh<16>(ba, grid, half, s);
+        case 25: return launch_batched_dh<25>(ba, grid, half, s);
+        case 32: return launch_batched_dh<32>(ba, grid, half, s);
+        case 48: return launch_batched_dh<48>(ba, grid, half, s);
+        case 64: return launch_batched_dh<64>(ba, grid, half, s);
         default: set_error("internal: no screen kernel for this dimension"); return RSC_ERR_UNSUPPORTED;
     }
 }
@@ -335,6 +350,86 @@ int check_batch_args(const float *X, const int64_t *offsets, int S, int d, int k
     return RSC_OK;
 }
 
+// Rows the first pass could not certify: the first kEscCap of them are
+// screened again 64 wide over up to kEscRanges ranges of their own sample
+// (tiles of one sample, built on the host from the flagged rows) and
+// re-ranked; rows that fail again, and rows beyond the cap, are rescanned
+// exhaustively within their sample.  Synchronises the stream once.
+int escalate(const BatchPlan &bp, const BatchBuffers &b, const float *X, int32_t *out_idx, float *out_dist,
+             const RerankArgs &ra, hipStream_t s) {
+    int32_t flagged = 0;
+    int st = hip_status(hipMemcpyAsync(&flagged, &b.kb.counters->flagged, 4, hipMemcpyDeviceToHost, s),
+                        "read flagged count");
+    if (st == RSC_OK) st = hip_status(hipStreamSynchronize(s), "synchronise");
+    if (st != RSC_OK) return st;
+    const int c = std::min(flagged, kEscCap);
+    if (c > 0) {
+        std::vector<int32_t> rows(c);
+        if ((st = hip_status(hipMemcpyAsync(rows.data(), b.kb.flag1, (size_t)c * 4, hipMemcpyDeviceToHost, s),
+                             "read flagged rows")) != RSC_OK ||
+            (st = hip_status(hipStreamSynchronize(s), "synchronise")) != RSC_OK)
+            return st;
+        std::sort(rows.begin(), rows.end());
+        constexpr int QG = kScreenWaves * 32;
+        std::vector<BatchItem> items;
+        size_t i = 0;
+        while (i < rows.size()) {
+            const int smp = (int)(std::upper_bound(bp.soff.begin(), bp.soff.end(), (int64_t)rows[i]) -
+                                  bp.soff.begin()) - 1;
+            size_t e = i;
+            while (e < rows.size() && e - i < (size_t)QG && rows[e] < bp.soff[smp + 1]) ++e;
+            const int64_t nb = bp.boff[smp + 1] - bp.boff[smp];
+            const int P = (int)std::max<int64_t>(1, std::min<int64_t>(kEscRanges, nb / 8));
+            const int64_t per = (nb + P - 1) / P;
+            for (int p = 0; p < P; ++p) {
+                BatchItem it;
+                it.q0 = (int64_t)i;
+                it.nq = (int32_t)(e - i);
+                it.b0 = bp.boff[smp] + p * per;
+                it.b1 = std::min<int64_t>(bp.boff[smp + 1], it.b0 + per);
+                it.ref_base = bp.soff[smp] - 32 * bp.boff[smp];
+                it.p = p;
+                if (it.b1 > it.b0) items.push_back(it);
+            }
+            i = e;
+        }
+        if ((st = hip_status(hipMemcpyAsync(b.esc_items, items.data(), items.size() * sizeof(BatchItem),
+                                            hipMemcpyHostToDevice, s), "upload escalation items")) != RSC_OK ||
+            (st = hip_status(hipMemcpyAsync(b.esc_rows, rows.data(), (size_t)c * 4, hipMemcpyHostToDevice, s),
+                             "upload escalation rows")) != RSC_OK ||
+            (st = hip_status(hipMemcpyAsync(b.esc_count, &c, 4, hipMemcpyHostToDevice, s), "upload count")) !=
+                RSC_OK)
+            return st;
+        const int64_t ncand = (int64_t)c * kEscRanges * 2 * kEscHalf;
+        const unsigned g = (unsigned)std::min<int64_t>((ncand + 255) / 256, 65536);
+        hipLaunchKernelGGL(k_batch_init, dim3(g), dim3(256), 0, s, b.counter, b.kb.esc_idx, b.kb.esc_key, ncand);
+        if ((st = launch_status("escalation init")) != RSC_OK) return st;
+        BatchArgs ba = batch_args(bp, b, X);
+        ba.base.P = kEscRanges;
+        ba.base.cand_idx = b.kb.esc_idx;
+        ba.base.cand_key = b.kb.esc_key;
+        ba.items = b.esc_items;
+        ba.n_items = (int)items.size();
+        ba.rows = b.esc_rows;
+        if ((st = launch_batched(bp, ba, s, kEscHalf, "screen_escalate")) != RSC_OK) return st;
+        RerankArgs re = ra;
+        re.qlist = b.esc_rows;
+        re.qcount = b.esc_count;
+        re.qcap = c;
+        re.S = kEscHalf;
+        re.KP = kEscHalf;
+        re.P = 2 * kEscRanges;
+        re.cand_idx = b.kb.esc_idx;
+        re.cand_key = b.kb.esc_key;
+        re.flag_out = b.kb.flag2;
+        re.flag_count = &b.kb.counters->flagged2;
+        if ((st = knn_launch_rerank(re, c, "rerank_escalate", s)) != RSC_OK) return st;
+        // the upload of the host vectors must finish before they go out of scope
+        if ((st = hip_status(hipStreamSynchronize(s), "synchronise")) != RSC_OK) return st;
+    }
+    return knn_launch_rescan(bp.kp, X, X, b.kb, c, out_idx, out_dist, b.soff, bp.S, s);
+}
+
 }  // namespace
 
 size_t batched_workspace_bytes(const int64_t *offsets, int S, int d, int k) {
@@ -388,8 +483,7 @@ int batched_run(const float *X, const int64_t *offsets, int S, int d, int k, int
     ra.out_idx = out_idx;
     ra.out_dist = out_dist;
     if ((st = knn_launch_rerank(ra, bp.kp.nq, "rerank", s)) != RSC_OK) return st;
-    // no escalation pass: every uncertified row is rescanned within its sample
-    return knn_launch_rescan(bp.kp, X, X, b.kb, 0, out_idx, out_dist, b.soff, S, s);
+    return escalate(bp, b, X, out_idx, out_dist, ra, s);
 }
 
 int batched_autotune(const float *X, const int64_t *offsets, int S, int d, int k, void *ws, size_t ws_bytes,

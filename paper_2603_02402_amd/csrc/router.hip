@@ -209,14 +209,29 @@ __global__ __launch_bounds__(256) void k_transpose_f32_bf16(const float *__restr
     }
 }
 
-// Column sums of a BF16 matrix (bias gradients), one thread per column.
-__global__ __launch_bounds__(256) void k_colsum_bf16(const uint16_t *__restrict__ in, int rows, int cols,
-                                                     float *__restrict__ out) {
-    const int cc = blockIdx.x * blockDim.x + threadIdx.x;
-    if (cc >= cols) return;
+// Column sums of a BF16 matrix (bias gradients) in two passes with a fixed
+// order: partial[c][j] = sum of rows 256c .. 256c+255 of column j (a wave
+// reads consecutive columns of one row: coalesced), then out[j] = sum over c.
+constexpr int kColChunk = 256;
+
+__global__ __launch_bounds__(256) void k_colsum_partial(const uint16_t *__restrict__ in, int rows, int cols,
+                                                        float *__restrict__ partial) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (j >= cols) return;
+    const int r1 = min(rows, (c + 1) * kColChunk);
     float s = 0.f;
-    for (int r = 0; r < rows; ++r) s += from_bf16(in[(int64_t)r * cols + cc]);
-    out[cc] = s;
+    for (int r = c * kColChunk; r < r1; ++r) s += from_bf16(in[(int64_t)r * cols + j]);
+    partial[(int64_t)c * cols + j] = s;
+}
+
+__global__ __launch_bounds__(256) void k_colsum_final(const float *__restrict__ partial, int chunks, int cols,
+                                                      float *__restrict__ out) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= cols) return;
+    float s = 0.f;
+    for (int c = 0; c < chunks; ++c) s += partial[(int64_t)c * cols + j];
+    out[j] = s;
 }
 
 // Rows [row0, row0 + nb) of X (n x d, float32), or rows list[row0 + i], as a
@@ -488,7 +503,7 @@ constexpr int kInferChunk = 16384;  // rows per inference pass
 
 struct TrainBuffers {
     uint16_t *a0, *h1, *h2, *dz, *dzt, *h2t, *dh2, *dh2t, *h1t, *dh1, *dh1t, *a0t;
-    float *z, *grad, *row_loss, *batch_sum, *epoch_loss;
+    float *z, *grad, *row_loss, *batch_sum, *epoch_loss, *colsum;
 };
 
 size_t carve_train(const rsc_router *R, int B, int64_t nbatches, void *ws, TrainBuffers *t) {
@@ -512,6 +527,7 @@ size_t carve_train(const rsc_router *R, int B, int64_t nbatches, void *ws, Train
     b.row_loss = cv.take<float>((size_t)B);
     b.batch_sum = cv.take<float>((size_t)std::max<int64_t>(nbatches, 1));
     b.epoch_loss = cv.take<float>(kMaxEpochs);
+    b.colsum = cv.take<float>((size_t)((B + kColChunk - 1) / kColChunk) * std::max(P, H));
     if (t) *t = b;
     return cv.used;
 }
@@ -544,6 +560,13 @@ int gemm(const uint16_t *A, int lda, const uint16_t *B, int ldb, void *C, int ld
         hipLaunchKernelGGL((k_gemm_nt<EPI>), dim3(N / 64, M / 64), dim3(256), 0, s, A, lda, B, ldb, C, ldc, bias,
                            mask, K);
     return launch_status("router gemm");
+}
+
+int colsum(const uint16_t *in, int rows, int cols, float *scratch, float *out, hipStream_t s) {
+    const int chunks = (rows + kColChunk - 1) / kColChunk;
+    hipLaunchKernelGGL(k_colsum_partial, dim3((cols + 255) / 256, chunks), dim3(256), 0, s, in, rows, cols, scratch);
+    hipLaunchKernelGGL(k_colsum_final, dim3((cols + 255) / 256), dim3(256), 0, s, scratch, chunks, cols, out);
+    return launch_status("router bias gradient");
 }
 
 int transpose(const uint16_t *in, int rows, int cols, uint16_t *out, hipStream_t s) {
@@ -588,14 +611,14 @@ int backward(const rsc_router *R, const TrainBuffers &t, const int32_t *labels, 
     if ((st = transpose(t.dz, B, P, t.dzt, s)) != RSC_OK) return st;
     if ((st = transpose(t.h2, B, H, t.h2t, s)) != RSC_OK) return st;
     if ((st = gemm<kStoreF32>(t.dzt, B, t.h2t, B, t.grad + L.w3, H, nullptr, nullptr, P, H, B, s)) != RSC_OK) return st;
-    hipLaunchKernelGGL(k_colsum_bf16, dim3((P + 255) / 256), dim3(256), 0, s, t.dz, B, P, t.grad + L.b3);
+    if ((st = colsum(t.dz, B, P, t.colsum, t.grad + L.b3, s)) != RSC_OK) return st;
     // back through W3 and the second ReLU
     if ((st = gemm<kMaskBf16>(t.dz, P, R->w3tb, P, t.dh2, H, nullptr, t.h2, B, H, P, s)) != RSC_OK) return st;
     // W2, b2
     if ((st = transpose(t.dh2, B, H, t.dh2t, s)) != RSC_OK) return st;
     if ((st = transpose(t.h1, B, H, t.h1t, s)) != RSC_OK) return st;
     if ((st = gemm<kStoreF32>(t.dh2t, B, t.h1t, B, t.grad + L.w2, H, nullptr, nullptr, H, H, B, s)) != RSC_OK) return st;
-    hipLaunchKernelGGL(k_colsum_bf16, dim3((H + 255) / 256), dim3(256), 0, s, t.dh2, B, H, t.grad + L.b2);
+    if ((st = colsum(t.dh2, B, H, t.colsum, t.grad + L.b2, s)) != RSC_OK) return st;
     // back through W2 and the first ReLU
     if ((st = gemm<kMaskBf16>(t.dh2, H, R->w2tb, H, t.dh1, H, nullptr, t.h1, B, H, H, s)) != RSC_OK) return st;
     // W1, b1
@@ -603,8 +626,7 @@ int backward(const rsc_router *R, const TrainBuffers &t, const int32_t *labels, 
     if ((st = transpose(t.a0, B, dp, t.a0t, s)) != RSC_OK) return st;
     if ((st = gemm<kStoreF32>(t.dh1t, B, t.a0t, B, t.grad + L.w1, dp, nullptr, nullptr, H, dp, B, s)) != RSC_OK)
         return st;
-    hipLaunchKernelGGL(k_colsum_bf16, dim3((H + 255) / 256), dim3(256), 0, s, t.dh1, B, H, t.grad + L.b1);
-    return launch_status("router bias gradients");
+    return colsum(t.dh1, B, H, t.colsum, t.grad + L.b1, s);
 }
 
 int cast_rows(const rsc_router *R, const float *X, const int32_t *list, int64_t row0, int nb, int B, uint16_t *out,
