@@ -105,6 +105,7 @@ constexpr int kDefaultPolicy = 0;
 struct BatchPlan {
     KnnPlan kp;
     int S = 0;
+    int ranges = 1;  // reference ranges the items use (the candidate lists per query)
     std::vector<int64_t> soff, boff;
     std::vector<int32_t> blk_sample;
     std::vector<BatchItem> items;
@@ -149,6 +150,7 @@ int build_plan(const int64_t *offsets, int S, int d, int k, const Policy &pol, B
             }
         }
     }
+    for (const BatchItem &it : bp.items) bp.ranges = std::max(bp.ranges, (int)it.p + 1);
     if (pol.lpt)
         std::stable_sort(bp.items.begin(), bp.items.end(),
                          [](const BatchItem &a, const BatchItem &b) { return a.b1 - a.b0 > b.b1 - b.b0; });
@@ -257,7 +259,7 @@ BatchArgs batch_args(const BatchPlan &bp, const BatchBuffers &b, const float *X)
     ba.base.Np = b.kb.norms;
     ba.base.nblk = bp.kp.nblk;
     ba.base.d = bp.kp.d;
-    ba.base.P = kMaxSplits;
+    ba.base.P = bp.ranges;
     ba.base.cand_idx = b.kb.cand_idx;
     ba.base.cand_key = b.kb.cand_key;
     ba.items = b.items;
@@ -267,7 +269,7 @@ BatchArgs batch_args(const BatchPlan &bp, const BatchBuffers &b, const float *X)
 }
 
 int screen_only(const BatchPlan &bp, const BatchBuffers &b, const float *X, hipStream_t s) {
-    const int64_t ncand = bp.kp.nq * kMaxSplits * bp.kp.screen;
+    const int64_t ncand = bp.kp.nq * bp.ranges * bp.kp.screen;
     const unsigned g = (unsigned)std::min<int64_t>((ncand + 255) / 256, 65536);
     hipLaunchKernelGGL(k_batch_init, dim3(g), dim3(256), 0, s, b.counter, b.kb.cand_idx, b.kb.cand_key, ncand);
     int st = launch_status("batch init");
@@ -471,7 +473,7 @@ int batched_run(const float *X, const int64_t *offsets, int S, int d, int k, int
     ra.k = k;
     ra.S = bp.kp.half;
     ra.KP = bp.kp.half;
-    ra.P = 2 * kMaxSplits;
+    ra.P = 2 * bp.ranges;
     ra.self_mode = 1;
     ra.certify = 1;
     ra.cand_idx = b.kb.cand_idx;

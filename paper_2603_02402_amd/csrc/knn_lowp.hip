@@ -288,7 +288,11 @@ __global__ __launch_bounds__(256, 3) void k_screen_lowp(ScreenArgs a) {
     constexpr int QCAP = 8;  // 16 KiB of queue per workgroup: three workgroups fit a CU
     constexpr bool kNormInAcc = PREC == RSC_FP8_E4M3;
 
-    __shared__ __attribute__((aligned(16))) char ring[2 * PH * SLOT];
+    // Two ring buffers as two LDS objects: the compiler can then tell that
+    // the asynchronous loads into one never alias the reads of the other and
+    // does not make the reads wait for them.
+    __shared__ __attribute__((aligned(16))) char ring0[PH * SLOT];
+    __shared__ __attribute__((aligned(16))) char ring1[PH * SLOT];
     __shared__ float2 qbuf[QB * QCAP * 256];
 
     const int tid = threadIdx.x;
@@ -302,20 +306,20 @@ __global__ __launch_bounds__(256, 3) void k_screen_lowp(ScreenArgs a) {
     const char *Ab = static_cast<const char *>(a.Ap);
 
     // Issue this wave's share of the loads of phase `ph` into ring buffer `buf`.
-    auto issue = [&](int64_t ph, int buf) {
+    auto issue = [&](int64_t ph, char *buf) {
         const int64_t b0 = blk0 + ph * PH;
         constexpr int NA = PH * Ring::kLoads;
 #pragma unroll
         for (int j = wave; j < NA; j += kScreenWaves) {
             const int pb = j / Ring::kLoads, q = j % Ring::kLoads;
             const int64_t blk = std::min<int64_t>(b0 + pb, blk1 - 1);  // clamp: always in bounds
-            lds_load16(Ab + blk * Ring::kBlockBytes + q * 1024 + lane * 16, ring + (buf * PH + pb) * SLOT + q * 1024);
+            lds_load16(Ab + blk * Ring::kBlockBytes + q * 1024 + lane * 16, buf + pb * SLOT + q * 1024);
         }
         if constexpr (kNormInAcc) {
 #pragma unroll
             for (int pb = wave; pb < PH; pb += kScreenWaves) {
                 const int64_t blk = std::min<int64_t>(b0 + pb, blk1 - 1);
-                if (lane < 8) lds_load16(a.Np + blk * 32 + lane * 4, ring + (buf * PH + pb) * SLOT + Ring::kBlockBytes);
+                if (lane < 8) lds_load16(a.Np + blk * 32 + lane * 4, buf + pb * SLOT + Ring::kBlockBytes);
             }
         }
     };
@@ -368,18 +372,17 @@ __global__ __launch_bounds__(256, 3) void k_screen_lowp(ScreenArgs a) {
         for (int qb = 0; qb < QB; ++qb) top[qb].init();
 
         const int64_t nph = (blk1 - blk0 + PH - 1) / PH;
-        __syncthreads();  // the ring is free (previous query block done with it)
-        if (nph > 0) issue(0, 0);
-        for (int64_t ph = 0; ph < nph; ++ph) {
+        // One phase: wait until its blocks have landed in `cur`, start the
+        // next phase's loads into `nxt`, then screen the blocks of `cur`.
+        auto phase = [&](int64_t ph, const char *cur, char *nxt) {
             __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0): this wave's loads of phase ph landed
             __syncthreads();                      // everyone's landed; phase ph-1 is fully consumed
-            if (ph + 1 < nph) issue(ph + 1, (int)((ph + 1) & 1));
-            const char *base = ring + (int)(ph & 1) * PH * SLOT;
+            if (ph + 1 < nph) issue(ph + 1, nxt);
 #pragma unroll
             for (int r = 0; r < PH; ++r) {
                 const int64_t blk = blk0 + ph * PH + r;
                 if (blk >= blk1) break;
-                const char *sl = base + r * SLOT;
+                const char *sl = cur + r * SLOT;
                 T A[KS];
 #pragma unroll
                 for (int s = 0; s < KS; ++s) {
@@ -401,6 +404,8 @@ __global__ __launch_bounds__(256, 3) void k_screen_lowp(ScreenArgs a) {
                         for (int j = 0; j < 4; ++j) init[4 * g + j] = t[j];
                     }
                 }
+                // all operand reads of the block are in flight before its first MFMA
+                __builtin_amdgcn_sched_barrier(0);
                 f32x16 acc[QB];
 #pragma unroll
                 for (int qb = 0; qb < QB; ++qb) acc[qb] = init;
@@ -413,6 +418,12 @@ __global__ __launch_bounds__(256, 3) void k_screen_lowp(ScreenArgs a) {
 #pragma unroll
                 for (int qb = 0; qb < QB; ++qb) top[qb].offer(acc[qb], ref0, qbuf + qb * QCAP * 256 + tid, 256);
             }
+        };
+        __syncthreads();  // the ring is free (previous query block done with it)
+        if (nph > 0) issue(0, ring0);
+        for (int64_t ph = 0; ph < nph; ph += 2) {
+            phase(ph, ring0, ring1);
+            if (ph + 1 < nph) phase(ph + 1, ring1, ring0);
         }
 #pragma unroll
         for (int qb = 0; qb < QB; ++qb) {
