@@ -57,6 +57,8 @@ def _load():
             lib.oracle_fuzzy_union.argtypes = [P, P, i64, i32, P, P, P, i64]
             lib.oracle_fuzzy_union.restype = i64
             lib.oracle_max_threads.restype = i32
+            lib.oracle_knn_cosine.argtypes = [P, i64, P, P, i64, i32, i32, P, P, P]
+            lib.oracle_knn_cosine.restype = i32
             lib.oracle_knn_subset.argtypes = [P, i64, i32, i32, P, i64, P, P, P, P, P]
             lib.oracle_knn_subset.restype = i32
             _lib = lib
@@ -71,13 +73,16 @@ def max_threads() -> int:
     return int(_load().oracle_max_threads())
 
 
-def knn(R: np.ndarray, k: int, Q: np.ndarray | None = None, self_ids: np.ndarray | None = None):
+def knn(R: np.ndarray, k: int, Q: np.ndarray | None = None, self_ids: np.ndarray | None = None,
+        metric: str = "euclidean"):
     """Exact kNN (float64 brute force, lowest index first on ties).
 
     ``knn(X, k)``: every row of ``X`` against ``X``, self forced into slot 0.
     ``knn(R, k, Q=Q, self_ids=ids)``: queries ``Q`` against ``R``; ``ids``
     (or ``None``) names the reference row that is each query itself.
     Returns ``(idx int32, d2 float64, dist float32)``, each ``nq x k``.
+    ``metric="cosine"``: the cosine distance 1 - cos (float64 in the second
+    array, float32 in the third); rows of zero norm are at distance 1.
     """
     R = np.ascontiguousarray(R, dtype=np.float32)
     if Q is None:
@@ -93,7 +98,10 @@ def knn(R: np.ndarray, k: int, Q: np.ndarray | None = None, self_ids: np.ndarray
     idx = np.empty((nq, k), dtype=np.int32)
     d2 = np.empty((nq, k), dtype=np.float64)
     dist = np.empty((nq, k), dtype=np.float32)
-    rc = _load().oracle_knn(_p(Q), nq, _p(self_ids), _p(R), nr, d, k, _p(idx), _p(d2), _p(dist))
+    if metric not in ("euclidean", "cosine"):
+        raise ValueError(f"unknown metric {metric!r}")
+    fn = _load().oracle_knn if metric == "euclidean" else _load().oracle_knn_cosine
+    rc = fn(_p(Q), nq, _p(self_ids), _p(R), nr, d, k, _p(idx), _p(d2), _p(dist))
     if rc != 0:
         raise ValueError("oracle_knn: invalid arguments")
     return idx, d2, dist
@@ -123,11 +131,11 @@ def knn_subset(X: np.ndarray, k: int, cand_off: np.ndarray, cand_ids: np.ndarray
     return idx, d2, dist
 
 
-def knn_rows(X: np.ndarray, rows: np.ndarray, k: int):
+def knn_rows(X: np.ndarray, rows: np.ndarray, k: int, metric: str = "euclidean"):
     """Exact kNN of the selected rows of ``X`` against all of ``X`` (self in slot 0)."""
     X = np.ascontiguousarray(X, dtype=np.float32)
     rows = np.ascontiguousarray(rows, dtype=np.int64)
-    return knn(X, k, Q=X[rows], self_ids=rows)
+    return knn(X, k, Q=X[rows], self_ids=rows, metric=metric)
 
 
 def pair_d2(X: np.ndarray, ii: np.ndarray, jj: np.ndarray) -> np.ndarray:
@@ -179,8 +187,8 @@ def connectivities(idx: np.ndarray, dist: np.ndarray):
     return indptr, indices, data, rho, sigma
 
 
-def knn_graph(X: np.ndarray, k: int):
+def knn_graph(X: np.ndarray, k: int, metric: str = "euclidean"):
     """The whole step on the CPU: exact kNN, then connectivities."""
-    idx, _, dist = knn(X, k)
+    idx, _, dist = knn(X, k, metric=metric)
     indptr, indices, data, rho, sigma = connectivities(idx, dist)
     return dict(idx=idx, dist=dist, indptr=indptr, indices=indices, data=data, rho=rho, sigma=sigma)

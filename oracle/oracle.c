@@ -393,3 +393,81 @@ int oracle_knn_subset(const float *X, int64_t n, int d, int k, const int64_t *qr
     }
     return fail ? -1 : 0;
 }
+
+/*
+ * Cosine distance of two float32 rows in float64: 1 - x.y / (||x|| ||y||),
+ * the dot product and both squared norms summed in dimension order, each
+ * product and sum rounded on its own.  A row of zero norm has no direction:
+ * its distance to every row is 1 (cosine 0).
+ */
+static double cos_dist(const float *x, const float *y, int d) {
+    double xy = 0.0, xx = 0.0, yy = 0.0;
+    for (int t = 0; t < d; ++t) {
+        double a = (double)x[t], b = (double)y[t];
+        xy = xy + a * b;
+        xx = xx + a * a;
+        yy = yy + b * b;
+    }
+    if (xx == 0.0 || yy == 0.0) return 1.0;
+    return 1.0 - xy / (sqrt(xx) * sqrt(yy));
+}
+
+/*
+ * Exact kNN under the cosine distance, otherwise as oracle_knn (self in slot
+ * 0 when self_ids is given, (distance, index) order, ties to the lower
+ * index).  out_d2 receives the cosine distances in float64, out_dist the
+ * same rounded to float32.
+ */
+int oracle_knn_cosine(const float *Q, int64_t nq, const int64_t *self_ids, const float *R, int64_t nr, int d,
+                      int k, int32_t *out_idx, double *out_d, float *out_dist) {
+    if (nq < 0 || nr < 1 || d < 1 || k < 1 || k > nr) return -1;
+    int fail = 0;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t q = 0; q < nq; ++q) {
+        const float *x = Q + q * (int64_t)d;
+        int64_t self = self_ids ? self_ids[q] : -1;
+        double *bd = (double *)malloc(sizeof(double) * (size_t)k);
+        int64_t *bj = (int64_t *)malloc(sizeof(int64_t) * (size_t)k);
+        if (!bd || !bj) {
+            fail = 1;
+            free(bd);
+            free(bj);
+            continue;
+        }
+        int start = 0;
+        if (self >= 0) {
+            bd[0] = 0.0;
+            bj[0] = self;
+            start = 1;
+        }
+        int cnt = start;
+        for (int64_t j = 0; j < nr; ++j) {
+            if (j == self) continue;
+            double v = cos_dist(x, R + j * (int64_t)d, d);
+            int p;
+            if (cnt < k) {
+                p = cnt++;
+            } else if (k > start && before(v, j, bd[k - 1], bj[k - 1])) {
+                p = k - 1;
+            } else {
+                continue;
+            }
+            while (p > start && before(v, j, bd[p - 1], bj[p - 1])) {
+                bd[p] = bd[p - 1];
+                bj[p] = bj[p - 1];
+                --p;
+            }
+            bd[p] = v;
+            bj[p] = j;
+        }
+        for (int s = 0; s < k; ++s) {
+            int64_t o = q * (int64_t)k + s;
+            out_idx[o] = (int32_t)(s < cnt ? bj[s] : -1);
+            if (out_d) out_d[o] = s < cnt ? bd[s] : INFINITY;
+            if (out_dist) out_dist[o] = s < cnt ? (float)bd[s] : INFINITY;
+        }
+        free(bd);
+        free(bj);
+    }
+    return fail ? -1 : 0;
+}

@@ -474,3 +474,54 @@ def test_bf16_emulation_reduces_to_exact_and_stays_close():
     for a, b in zip(exact, rounded):
         assert np.linalg.norm(a - b) <= 2**-4 * np.linalg.norm(a)
         assert np.linalg.norm(a - b) > 0
+
+
+# ---------------------------------------------------------------------------
+# Cosine metric.
+# ---------------------------------------------------------------------------
+
+def test_cosine_knn_matches_sklearn_and_cdist():
+    from scipy.spatial.distance import cdist
+    from sklearn.neighbors import NearestNeighbors
+
+    from oracle import knn
+
+    rng = np.random.default_rng(21)
+    X = (rng.standard_normal((400, 12)) + rng.normal(0, 3, (1, 12))).astype(np.float32)
+    idx, d, dist = knn(X, 9, metric="cosine")
+    D = cdist(X.astype(np.float64), X.astype(np.float64), metric="cosine")
+    np.fill_diagonal(D, -1.0)  # self first
+    order = np.lexsort((np.broadcast_to(np.arange(400), D.shape), D), axis=1)[:, :9]
+    assert np.array_equal(idx, order)
+    Dk = np.take_along_axis(D, order, axis=1)
+    np.testing.assert_allclose(d[:, 1:], Dk[:, 1:], rtol=0, atol=1e-14)
+    assert (d[:, 0] == 0).all()
+    nn = NearestNeighbors(n_neighbors=9, metric="cosine", algorithm="brute").fit(X.astype(np.float64))
+    sd, si = nn.kneighbors(X.astype(np.float64))
+    assert np.array_equal(np.sort(si[:, 1:], axis=1), np.sort(idx[:, 1:], axis=1))
+    np.testing.assert_allclose(np.sort(sd[:, 1:], axis=1), d[:, 1:], atol=1e-12)
+
+
+def test_cosine_knn_hand_angles_scale_invariance_and_zero_rows():
+    from oracle import knn
+
+    # x = (1, 0): (2, 0) at 0, (1, 1) at 1 - 1/sqrt(2), (0, 1) at 1, (-1, 0) at 2
+    R = np.array([[2, 0], [-1, 0], [0, 1], [1, 1]], dtype=np.float32)
+    idx, d, _ = knn(R, 4, Q=np.array([[1, 0]], dtype=np.float32))
+    idx_c, d_c, _ = knn(R, 4, Q=np.array([[1, 0]], dtype=np.float32), metric="cosine")
+    assert idx_c[0].tolist() == [0, 3, 2, 1]
+    np.testing.assert_allclose(d_c[0], [0.0, 1 - 2 ** -0.5, 1.0, 2.0], atol=1e-15)
+    # scaling rows by powers of two changes nothing (exact in float32)
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((150, 7)).astype(np.float32)
+    S = X * (2.0 ** rng.integers(-6, 7, size=(150, 1))).astype(np.float32)
+    a = knn(X, 6, metric="cosine")
+    b = knn(S, 6, metric="cosine")
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    # a zero row is at distance 1 from every row, and every row from it
+    X[10] = 0.0
+    idx, d, _ = knn(X, 150, metric="cosine")
+    assert idx[10, 0] == 10 and (d[10, 1:] == 1.0).all()
+    assert idx[10, 1:].tolist() == [j for j in range(150) if j != 10]  # all ties: index order
+    pos = np.argwhere(idx[3] == 10)[0, 0]
+    assert d[3, pos] == 1.0
