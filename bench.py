@@ -219,6 +219,47 @@ def precision_forms(args, rsc) -> dict:
     return res
 
 
+def cosine_form(args, rsc, Xt, ws, out) -> dict:
+    """Exact kNN graph under the cosine distance on the plain workload (same
+    cells, buffers and k), timed as a whole graph step."""
+    import torch
+
+    idx, dist, csr = out
+    n, d = Xt.shape
+    k = idx.shape[1]
+    cos = rsc.RSC_COSINE
+    ws.get(max(rsc.knn_workspace_bytes(n, n, d, k, metric=cos), rsc.connectivities_workspace_bytes(n, k)))
+    log("[bench] cosine form: warmup")
+    rsc.knn(Xt, k, out=(idx, dist), workspace=ws, metric=cos)
+    rsc.connectivities(idx, dist, workspace=ws, out=csr)
+    torch.cuda.synchronize()
+    rsc.profile_reset()
+    rsc.profile_enable(True)
+    t0 = time.perf_counter()
+    stats = g = None
+    for i in range(args.form_steps):
+        rsc.knn(Xt, k, out=(idx, dist), workspace=ws, metric=cos)
+        stats = rsc.read_knn_stats(ws)
+        g = rsc.connectivities(idx, dist, workspace=ws, out=csr)
+        log(f"[bench] cosine form: step {i + 1}/{args.form_steps}")
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.form_steps
+    rsc.profile_enable(False)
+    kern = {}
+    for name in ["normalize", "prep_pack", "screen_fp32", "rerank", "screen_escalate", "rerank_escalate", "rescan",
+                 "smooth_knn", "union_count", "union_fill", "row_sort"]:
+        tot, cnt = rsc.profile_get(name)
+        if cnt:
+            kern[name] = round(tot / cnt, 4)
+    scr = kern.get("screen_fp32")
+    return {"workload": "same cells as the plain line (n=1,000,000, d=50, k=15), distance 1 - cos",
+            "form": "exact cosine (FP32 MFMA screen on unit rows, FP64 rerank + certificate)",
+            "cells_per_s": round(n / (ms / 1e3), 1), "ms_per_step": round(ms, 2), "kernel_ms": kern,
+            "screen_frac_of_fp32_peak": round(2 * d * n * n / (scr / 1e3) / 1e12 / PEAK_FP32_TFLOPS, 4) if scr else None,
+            "escalated_rows": stats["escalated_rows"], "rescanned_rows": stats["rescanned_rows"],
+            "max_err_ratio": round(stats["max_err_ratio"], 4), "nnz": int(g.nnz)}
+
+
 def batched_form(args, rsc) -> dict:
     """64 independent samples (log-uniform 2k..200k cells, 10-40 clusters each):
     per-sample exact kNN in one persistent launch + connectivities."""
@@ -411,7 +452,7 @@ def main() -> int:
     ap.add_argument("--no-forms", action="store_true", help="skip the 2M-cell precision forms")
     ap.add_argument("--form-steps", type=int, default=3)
     ap.add_argument("--no-routed", action="store_true", help="skip the learned-router form")
-    ap.add_argument("--only", choices=["precision", "batched", "routed"],
+    ap.add_argument("--only", choices=["cosine", "precision", "batched", "routed"],
                     help="run one form alone and print its record (no benchmark line)")
     ap.add_argument("--routed-n", type=int, default=5_000_000)
     ap.add_argument("--routed-train", type=int, default=1_000_000)
@@ -438,6 +479,18 @@ def main() -> int:
         print("no GPU visible", file=sys.stderr)
         return 1
     rsc.load()
+    if args.only == "cosine":
+        w = WORKLOADS["plain_1m"]
+        Xc = torch.from_numpy(synth.mixture(w["n"], d=50, n_clusters=w["clusters"], law=w["law"],
+                                            seed=w["seed"])).cuda()
+        nc, kc = Xc.shape[0], args.k
+        out = (torch.empty((nc, kc), dtype=torch.int32, device="cuda"),
+               torch.empty((nc, kc), dtype=torch.float32, device="cuda"),
+               (torch.empty(nc + 1, dtype=torch.int64, device="cuda"),
+                torch.empty(2 * nc * (kc - 1), dtype=torch.int32, device="cuda"),
+                torch.empty(2 * nc * (kc - 1), dtype=torch.float32, device="cuda")))
+        print(json.dumps({"cosine": cosine_form(args, rsc, Xc, rsc.Workspace(), out)}), flush=True)
+        return 0
     if args.only:
         fn = {"precision": precision_forms, "batched": batched_form, "routed": routed_form}[args.only]
         print(json.dumps({args.only: fn(args, rsc)}), flush=True)
@@ -504,10 +557,11 @@ def main() -> int:
 
     forms = None
     if not args.no_forms:
+        forms = {"cosine_fp32": cosine_form(args, rsc, Xt, ws, (idx, dist, csr))}
         del Xt, idx, dist, csr
         ws.buf = None
         torch.cuda.empty_cache()
-        forms = precision_forms(args, rsc)
+        forms.update(precision_forms(args, rsc))
         torch.cuda.empty_cache()
         forms["batched_fp32"] = batched_form(args, rsc)
         if not args.no_routed:

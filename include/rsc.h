@@ -74,6 +74,13 @@ const char *rsc_last_error(void);
 
 typedef enum { RSC_FP32 = 0, RSC_BF16 = 1, RSC_FP8_E4M3 = 2 } rsc_precision;
 
+/* Distance of the neighbour search.  RSC_EUCLIDEAN: ||x - y||.
+ * RSC_COSINE: 1 - x.y / (||x|| ||y||) (a row of zero norm is at distance 1
+ * from every row); the screen runs on the unit-normalised rows and the
+ * reported distances are float64 cosine distances of the original rows,
+ * rounded once to float32. */
+typedef enum { RSC_EUCLIDEAN = 0, RSC_COSINE = 1 } rsc_metric;
+
 /*
  * Options of the screening stage.  A zero-initialised struct (or NULL)
  * selects the default: FP32 screen of width 32 (64 for k > 16) followed by
@@ -88,11 +95,13 @@ typedef enum { RSC_FP32 = 0, RSC_BF16 = 1, RSC_FP8_E4M3 = 2 } rsc_precision;
  *              approximate (no certificate): judge them by recall@k.
  *   screen     candidates kept per query: 32 or 64 for RSC_FP32 (must exceed
  *              k), 64 for the reduced-precision forms; 0 = default.
+ *   metric     rsc_metric (0 = Euclidean).  The exactness guarantee of
+ *              RSC_FP32 holds for both metrics.
  */
 typedef struct {
     int32_t precision;
     int32_t screen;
-    int32_t reserved0;
+    int32_t metric;
     int32_t reserved1;
 } rsc_knn_opts;
 

@@ -19,12 +19,13 @@ import ctypes
 from dataclasses import dataclass
 
 from . import _lib
-from ._lib import RSC_BF16, RSC_FP8_E4M3, RSC_FP32, KnnOpts, KnnStats, RscError, check, load
+from ._lib import (RSC_BF16, RSC_COSINE, RSC_EUCLIDEAN, RSC_FP8_E4M3, RSC_FP32, KnnOpts, KnnStats, RscError,
+                   check, load)
 
 __all__ = [
     "knn", "knn_graph", "connectivities", "knn_workspace_bytes", "connectivities_workspace_bytes",
     "read_knn_stats", "profile_enable", "profile_reset", "profile_get", "RscError", "Workspace",
-    "RSC_FP32", "RSC_BF16", "RSC_FP8_E4M3", "abi_version", "knn_batched", "knn_batched_autotune",
+    "RSC_FP32", "RSC_BF16", "RSC_FP8_E4M3", "RSC_EUCLIDEAN", "RSC_COSINE", "abi_version", "knn_batched", "knn_batched_autotune",
     "knn_batched_workspace_bytes", "Router", "partition_kmeans", "partition_lists", "partition_labels",
     "knn_probed", "knn_routed",
 ]
@@ -57,13 +58,13 @@ def abi_version() -> int:
     return int(load().rsc_abi_version())
 
 
-def _opts(precision: int = RSC_FP32, screen: int = 0):
-    return KnnOpts(precision, screen, 0, 0)
+def _opts(precision: int = RSC_FP32, screen: int = 0, metric: int = RSC_EUCLIDEAN):
+    return KnnOpts(precision, screen, metric, 0)
 
 
 def knn_workspace_bytes(n_query: int, n_ref: int, d: int, k: int, precision: int = RSC_FP32,
-                        screen: int = 0) -> int:
-    o = _opts(precision, screen)
+                        screen: int = 0, metric: int = RSC_EUCLIDEAN) -> int:
+    o = _opts(precision, screen, metric)
     return int(load().rsc_knn_workspace_bytes(n_query, n_ref, d, k, ctypes.byref(o)))
 
 
@@ -86,7 +87,8 @@ class Workspace:
         return self.buf
 
 
-def knn(X, k: int, Q=None, precision: int = RSC_FP32, screen: int = 0, out=None, workspace: Workspace | None = None):
+def knn(X, k: int, Q=None, precision: int = RSC_FP32, screen: int = 0, out=None, workspace: Workspace | None = None,
+        metric: int = RSC_EUCLIDEAN):
     """k nearest neighbours.
 
     ``knn(X, k)``: every row of ``X`` (n x d float32) among the rows of ``X``;
@@ -105,7 +107,7 @@ def knn(X, k: int, Q=None, precision: int = RSC_FP32, screen: int = 0, out=None,
     if Q is not None and (Q.dtype != torch.float32 or Q.dim() != 2 or Q.shape[1] != d):
         raise ValueError("Q must be a float32 tensor with X's column count")
     lib = load()
-    o = _opts(precision, screen)
+    o = _opts(precision, screen, metric)
     need = lib.rsc_knn_workspace_bytes(nq, n, d, k, ctypes.byref(o))
     if need == 0:
         # invalid sizes: let the call itself report the reason
@@ -116,7 +118,7 @@ def knn(X, k: int, Q=None, precision: int = RSC_FP32, screen: int = 0, out=None,
         dist = torch.empty((nq, k), dtype=torch.float32, device=X.device)
     else:
         idx, dist = out
-    if Q is None and precision == RSC_FP32 and screen == 0:
+    if Q is None and precision == RSC_FP32 and screen == 0 and metric == RSC_EUCLIDEAN:
         st = lib.rsc_knn(_ptr(X), n, d, k, _ptr(idx), _ptr(dist), _ptr(ws), ws.numel(), _stream())
     elif Q is None:
         st = lib.rsc_knn_opt(_ptr(X), n, d, k, ctypes.byref(o), _ptr(idx), _ptr(dist), _ptr(ws), ws.numel(),
@@ -178,10 +180,10 @@ def connectivities(idx, dist, want_rho_sigma: bool = True, workspace: Workspace 
     return Graph(indptr, indices[:m], data[:m], rho, sigma)
 
 
-def knn_graph(X, k: int, workspace: Workspace | None = None):
+def knn_graph(X, k: int, workspace: Workspace | None = None, metric: int = RSC_EUCLIDEAN):
     """The whole step: ``(idx, dist, Graph)``."""
     ws = workspace or Workspace(X.device)
-    idx, dist = knn(X, k, workspace=ws)
+    idx, dist = knn(X, k, workspace=ws, metric=metric)
     g = connectivities(idx, dist, workspace=ws)
     return idx, dist, g
 

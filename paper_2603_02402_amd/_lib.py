@@ -28,6 +28,7 @@ STATUS_NAMES = {
     -8: "RSC_ERR_BAD_GRAPH",
 }
 RSC_FP32, RSC_BF16, RSC_FP8_E4M3 = 0, 1, 2
+RSC_EUCLIDEAN, RSC_COSINE = 0, 1
 RSC_BATCH_POLICIES = 6
 
 # Every symbol include/rsc.h declares, with (restype, argtypes).
@@ -38,7 +39,7 @@ _SZ = ctypes.c_size_t
 
 
 class KnnOpts(ctypes.Structure):
-    _fields_ = [("precision", ctypes.c_int32), ("screen", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+    _fields_ = [("precision", ctypes.c_int32), ("screen", ctypes.c_int32), ("metric", ctypes.c_int32),
                 ("reserved1", ctypes.c_int32)]
 
 

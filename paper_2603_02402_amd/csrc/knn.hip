@@ -85,6 +85,32 @@ __global__ __launch_bounds__(64) void k_norms(const float *__restrict__ R, int64
     if (lane == 0) atomicMax(max_norm_bits, __float_as_uint(m));
 }
 
+// Unit-normalised rows for the cosine screen: x / ||x|| with the norm summed
+// in float64 and rounded once to float32, then one float32 division per
+// element (each element within 2 units of roundoff of x_t / ||x||); a row of
+// zero norm stays zero.  One wave per 64 rows, staged through LDS so that the
+// loads and stores are coalesced.
+__global__ __launch_bounds__(64) void k_normalize(const float *__restrict__ X, int64_t n, int d,
+                                                  float *__restrict__ out) {
+    __shared__ float buf[kNormRows * kMaxD];
+    const int lane = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * kNormRows;
+    const int rows = (int)min<int64_t>(kNormRows, n - r0);
+    for (int e = lane; e < rows * d; e += kWave) buf[e] = X[r0 * d + e];
+    __syncthreads();
+    if (lane < rows) {
+        double s = 0.0;
+        for (int t = 0; t < d; ++t) {
+            const double x = (double)buf[lane * d + t];
+            s += x * x;
+        }
+        const float nrm = (float)sqrt(s);
+        for (int t = 0; t < d; ++t) buf[lane * d + t] = nrm > 0.f ? buf[lane * d + t] / nrm : 0.f;
+    }
+    __syncthreads();
+    for (int e = lane; e < rows * d; e += kWave) out[r0 * d + e] = buf[e];
+}
+
 // Packed reference layout for a contraction half-width DH.  Block b holds
 // rows 32b..32b+31:
 //   A[b][s4][lane] (float4): element u = step s = 4 s4 + u of lane (c, h).
@@ -267,6 +293,18 @@ __global__ __launch_bounds__(256) void k_rerank(RerankArgs a) {
     xx = wave_sum(xx);
     const double xn = sqrt(xx) * (1.0 + 1e-12);
     const double ymax = (double)__uint_as_float(a.counters->max_norm_bits) * (1.0 + 1e-6);
+    const bool cosine = a.metric == RSC_COSINE;
+    // cosine: the query's squared norm summed in dimension order (as every
+    // pair's distance below and the oracle compute it)
+    double cxx = 0.0;
+    if (cosine) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        for (int t = 0; t < a.d; ++t) {
+            const double v = (double)xs[t];
+            cxx = __dadd_rn(cxx, __dmul_rn(v, v));
+        }
+    }
 
     // Smallest key any full range could have rejected.
     float tau = INFINITY;
@@ -298,7 +336,7 @@ __global__ __launch_bounds__(256) void k_rerank(RerankArgs a) {
         }
         const bool valid = j >= 0 && !(a.self_mode && j == row);
         const int jl = valid ? j : 0;  // a row of R that exists, loaded (and ignored) for empty slots
-        double s2 = 0.0, yy = 0.0;
+        double s2 = 0.0, yy = 0.0, sxy = 0.0;
         for (int k0 = 0; k0 < a.d; k0 += kRerankChunk) {
             const int w = min(kRerankChunk, a.d - k0);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // earlier reads of the tile are done
@@ -311,21 +349,37 @@ __global__ __launch_bounds__(256) void k_rerank(RerankArgs a) {
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // the tile is written
             __builtin_amdgcn_wave_barrier();
-            for (int t = 0; t < w; ++t) {
-                const double y = (double)T[lane][t];
-                const double diff = __dsub_rn((double)xs[k0 + t], y);
-                s2 = __dadd_rn(s2, __dmul_rn(diff, diff));
-                yy += y * y;
+            if (cosine) {
+                for (int t = 0; t < w; ++t) {
+                    const double y = (double)T[lane][t];
+                    sxy = __dadd_rn(sxy, __dmul_rn((double)xs[k0 + t], y));
+                    yy = __dadd_rn(yy, __dmul_rn(y, y));
+                }
+            } else {
+                for (int t = 0; t < w; ++t) {
+                    const double y = (double)T[lane][t];
+                    const double diff = __dsub_rn((double)xs[k0 + t], y);
+                    s2 = __dadd_rn(s2, __dmul_rn(diff, diff));
+                    yy += y * y;
+                }
             }
         }
         double d2 = INFINITY;
         int jj = INT_MAX;
         if (valid) {
-            d2 = s2;
             jj = j;
-            const double yn = sqrt(yy);
-            const double err_bound = a.eps_coef * (2.0 * xn * yn + yy) + 1e-300;
-            ratio = fmaxf(ratio, (float)(fabs((double)key - (d2 - xx)) / err_bound));
+            if (cosine) {
+                // 1 - x.y / (||x|| ||y||); a row of zero norm is at distance 1
+                const bool zero = cxx == 0.0 || yy == 0.0;
+                d2 = zero ? 1.0 : __dsub_rn(1.0, __ddiv_rn(sxy, __dmul_rn(__dsqrt_rn(cxx), __dsqrt_rn(yy))));
+                // the screen ranked 2 D - 1 (unit vectors) up to cosine_eps
+                if (!zero) ratio = fmaxf(ratio, (float)(fabs((double)key - (2.0 * d2 - 1.0)) / a.cosine_eps));
+            } else {
+                d2 = s2;
+                const double yn = sqrt(yy);
+                const double err_bound = a.eps_coef * (2.0 * xn * yn + yy) + 1e-300;
+                ratio = fmaxf(ratio, (float)(fabs((double)key - (d2 - xx)) / err_bound));
+            }
         }
         bitonic_sort64(d2, jj, lane);
         if (c0 == 0) {
@@ -340,7 +394,15 @@ __global__ __launch_bounds__(256) void k_rerank(RerankArgs a) {
 
     const int m = a.self_mode ? a.k - 1 : a.k;  // neighbours to certify
     bool ok = true;
-    if (a.certify && m > 0 && tau < INFINITY) {
+    if (a.certify && m > 0 && tau < INFINITY && cosine) {
+        // Unit vectors: a rejected reference y had a screened key >= tau, and
+        // the key is 2 D_y - 1 up to cosine_eps, so D_y >= (tau + 1 - eps) / 2,
+        // which must exceed D_m.  (A zero row's key may be far from its
+        // D_y = 1 but never above it: the bound still holds for it.)
+        const double dm = __shfl(rd, m - 1, kWave);
+        const double bound = ((double)tau + 1.0 - a.cosine_eps) * 0.5 - 1e-13;
+        ok = dm < bound;
+    } else if (a.certify && m > 0 && tau < INFINITY) {
         // A rejected reference y had a screened key >= tau.  If ||y|| > Y =
         // ||x|| + D_m it lies farther than D_m (triangle inequality); else its
         // float32 key is off by at most eps(Y), so its true key is >= tau -
@@ -361,7 +423,7 @@ __global__ __launch_bounds__(256) void k_rerank(RerankArgs a) {
     }
     if (lane < m) {
         oi[off + lane] = rj == INT_MAX ? -1 : rj;
-        od[off + lane] = (float)sqrt(rd);
+        od[off + lane] = cosine ? (float)rd : (float)sqrt(rd);
     }
     if (!ok && lane == 0) {
         const int pos = atomicAdd(a.flag_count, 1);
@@ -381,7 +443,7 @@ __global__ __launch_bounds__(64) void k_rescan(const float *__restrict__ Q, cons
                                                const int32_t *__restrict__ list2,
                                                const int32_t *__restrict__ count2, int32_t *__restrict__ out_idx,
                                                float *__restrict__ out_dist, KnnCounters *__restrict__ counters,
-                                               const int64_t *__restrict__ soff, int nsamples) {
+                                               const int64_t *__restrict__ soff, int nsamples, int metric) {
     __shared__ double ld[kRescanMax * kWave];
     __shared__ int lj[kRescanMax * kWave];
     const int lane = threadIdx.x;
@@ -408,9 +470,24 @@ __global__ __launch_bounds__(64) void k_rescan(const float *__restrict__ Q, cons
             ld[s * kWave + lane] = INFINITY;
             lj[s * kWave + lane] = INT_MAX;
         }
+        double cxx = 0.0;  // cosine: the query's squared norm, dimensions in order
+        if (metric == RSC_COSINE)
+            for (int t = 0; t < d; ++t) cxx = __dadd_rn(cxx, __dmul_rn((double)x[t], (double)x[t]));
         for (int64_t j = j0 + lane; j < j1; j += kWave) {
             if (self_mode && j == q) continue;
-            const double v = exact_d2(x, R + j * d, d);
+            double v;
+            if (metric == RSC_COSINE) {
+                const float *y = R + j * d;
+                double sxy = 0.0, syy = 0.0;
+                for (int t = 0; t < d; ++t) {
+                    sxy = __dadd_rn(sxy, __dmul_rn((double)x[t], (double)y[t]));
+                    syy = __dadd_rn(syy, __dmul_rn((double)y[t], (double)y[t]));
+                }
+                v = (cxx == 0.0 || syy == 0.0) ? 1.0
+                                               : __dsub_rn(1.0, __ddiv_rn(sxy, __dmul_rn(__dsqrt_rn(cxx), __dsqrt_rn(syy))));
+            } else {
+                v = exact_d2(x, R + j * d, d);
+            }
             if (m > 0 && lex_before(v, (int)j, ld[(m - 1) * kWave + lane], lj[(m - 1) * kWave + lane])) {
                 int p = m - 1;
                 while (p > 0 && lex_before(v, (int)j, ld[(p - 1) * kWave + lane], lj[(p - 1) * kWave + lane])) {
@@ -447,7 +524,7 @@ __global__ __launch_bounds__(64) void k_rescan(const float *__restrict__ Q, cons
             if (lane == owner) ++head;
             if (lane == 0) {
                 oi[off + s] = bj == INT_MAX ? -1 : bj;
-                od[off + s] = (float)sqrt(bd);
+                od[off + s] = metric == RSC_COSINE ? (float)bd : (float)sqrt(bd);
             }
         }
     }
@@ -561,7 +638,7 @@ int knn_launch_rescan(const KnnPlan &p, const float *Q, const float *R, const Kn
     ScopedTimer timer("rescan", stream);
     hipLaunchKernelGGL(k_rescan, dim3(1024), dim3(64), 0, stream, Q, R, p.nr, p.d, p.k, p.self_mode ? 1 : 0, b.flag1,
                        &b.counters->flagged, esc_cap, b.flag2, &b.counters->flagged2, out_idx, out_dist, b.counters,
-                       soff, nsamples);
+                       soff, nsamples, p.metric);
     return launch_status("rescan");
 }
 
@@ -588,6 +665,11 @@ int knn_plan(int64_t nq, int64_t nr, int d, int k, const rsc_knn_opts *opts, boo
     }
     int precision = opts ? opts->precision : RSC_FP32;
     int screen_w = opts ? opts->screen : 0;
+    const int metric = opts ? opts->metric : RSC_EUCLIDEAN;
+    if (metric != RSC_EUCLIDEAN && metric != RSC_COSINE) {
+        set_error("unknown metric");
+        return RSC_ERR_INVALID_ARG;
+    }
     if (precision != RSC_FP32 && precision != RSC_BF16 && precision != RSC_FP8_E4M3) {
         set_error("unknown precision");
         return RSC_ERR_INVALID_ARG;
@@ -615,6 +697,7 @@ int knn_plan(int64_t nq, int64_t nr, int d, int k, const rsc_knn_opts *opts, boo
     plan->self_mode = self_mode;
     plan->nblk = (nr + 31) / 32;
     plan->precision = precision;
+    plan->metric = metric;
     plan->splits = pick_splits(nq, plan->nblk,
                                precision == RSC_FP32 ? kQueriesPerGroup : lowp_queries_per_group(precision, d));
     return RSC_OK;
@@ -643,9 +726,31 @@ size_t knn_workspace(const KnnPlan &p, void *ws, KnnBuffers *out) {
     b.flag2 = cv.take<int32_t>((size_t)std::max<int64_t>(esc_rows, 1));
     b.esc_idx = cv.take<int32_t>((size_t)std::max<int64_t>(esc_rows, 1) * kEscalateSplits * kEscalateWidth);
     b.esc_key = cv.take<float>((size_t)std::max<int64_t>(esc_rows, 1) * kEscalateSplits * kEscalateWidth);
+    if (p.metric == RSC_COSINE) {
+        b.rn = cv.take<float>((size_t)p.nr * p.d);
+        b.qn = p.self_mode ? b.rn : cv.take<float>((size_t)std::max<int64_t>(p.nq, 1) * p.d);
+    }
     if (out) *out = b;
     return cv.used;
 }
+
+// Cosine metric: the screen's inputs are the unit-normalised rows.
+int normalize_inputs(const KnnPlan &p, const float *Q, const float *R, const KnnBuffers &b, hipStream_t stream) {
+    ScopedTimer timer("normalize", stream);
+    hipLaunchKernelGGL(k_normalize, dim3((unsigned)((p.nr + kNormRows - 1) / kNormRows)), dim3(kNormRows), 0, stream,
+                       R, p.nr, p.d, b.rn);
+    if (!p.self_mode && p.nq > 0)
+        hipLaunchKernelGGL(k_normalize, dim3((unsigned)((p.nq + kNormRows - 1) / kNormRows)), dim3(kNormRows), 0,
+                           stream, Q, p.nq, p.d, b.qn);
+    return launch_status("normalize");
+}
+
+// Bound on |screened key - (2 D - 1)| for the cosine screen: the float32
+// key error of unit vectors (eps_coef (2 |x||y| + |y|^2) with norms within
+// 4 units of 1) plus the normalisation: each unit vector is within 2 units of
+// roundoff per element of the exact direction, which moves |y|^2 by at most
+// 4 units and x.y by at most 4 units (doubled in the key), with a margin.
+double cosine_eps(int d) { return 3.0001 * knn_eps_coefficient(d) + 16.0 * std::ldexp(1.0, -24); }
 
 // Reduced-precision form: screen, then rerank without a certificate.
 int knn_run_lowp(const KnnPlan &p, const float *Q, const float *R, int32_t *out_idx, float *out_dist,
@@ -653,10 +758,13 @@ int knn_run_lowp(const KnnPlan &p, const float *Q, const float *R, int32_t *out_
     int st;
     hipLaunchKernelGGL(k_init_counters, dim3(1), dim3(64), 0, stream, b.counters);
     if ((st = launch_status("init_counters")) != RSC_OK) return st;
-    if ((st = lowp_prepare(p, Q, R, b.packed, b.norms, b.scal, b.amax, stream)) != RSC_OK) return st;
+    const bool cosine = p.metric == RSC_COSINE;
+    if (cosine && (st = normalize_inputs(p, Q, R, b, stream)) != RSC_OK) return st;
+    const float *Qs = cosine ? b.qn : Q, *Rs = cosine ? b.rn : R;  // what the screen sees
+    if ((st = lowp_prepare(p, Qs, Rs, b.packed, b.norms, b.scal, b.amax, stream)) != RSC_OK) return st;
     if (p.nq == 0) return RSC_OK;
     ScreenArgs sa{};
-    sa.Q = Q;
+    sa.Q = Qs;
     sa.nq = p.nq;
     sa.Ap = b.packed;
     sa.Np = b.norms;
@@ -679,6 +787,8 @@ int knn_run_lowp(const KnnPlan &p, const float *Q, const float *R, int32_t *out_
     ra.P = 2 * p.splits;
     ra.self_mode = p.self_mode ? 1 : 0;
     ra.certify = 0;
+    ra.metric = p.metric;
+    ra.cosine_eps = 1.0;
     ra.cand_idx = b.cand_idx;
     ra.cand_key = b.cand_key;
     ra.eps_coef = 1.0;
@@ -702,14 +812,17 @@ int knn_run(const KnnPlan &p, const float *Q, const float *R, int32_t *out_idx, 
         return knn_run_lowp(p, Q, R, out_idx, out_dist, b, stream);
     }
     int st;
-    if ((st = knn_prep_fp32(p, R, b, nullptr, nullptr, nullptr, stream)) != RSC_OK) return st;
+    const bool cosine = p.metric == RSC_COSINE;
+    if (cosine && (st = normalize_inputs(p, Q, R, b, stream)) != RSC_OK) return st;
+    const float *Qs = cosine ? b.qn : Q;  // what the screen sees
+    if ((st = knn_prep_fp32(p, cosine ? b.rn : R, b, nullptr, nullptr, nullptr, stream)) != RSC_OK) return st;
     if (p.nq == 0) return RSC_OK;
 
     const double eps_coef = knn_eps_coefficient(p.d);
 
     // Slots are rows 0..nq-1, or the first min(*qcount, nq) rows of qlist.
     ScreenArgs sa{};
-    sa.Q = Q;
+    sa.Q = Qs;
     sa.nq = p.nq;
     sa.qlist = qlist;
     sa.qcount = qcount;
@@ -739,6 +852,8 @@ int knn_run(const KnnPlan &p, const float *Q, const float *R, int32_t *out_idx, 
     ra.P = 2 * p.splits;
     ra.self_mode = p.self_mode ? 1 : 0;
     ra.certify = 1;
+    ra.metric = p.metric;
+    ra.cosine_eps = cosine_eps(p.d);
     ra.cand_idx = b.cand_idx;
     ra.cand_key = b.cand_key;
     ra.eps_coef = eps_coef;

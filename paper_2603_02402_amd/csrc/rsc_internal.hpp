@@ -72,6 +72,7 @@ struct KnnPlan {
     int64_t nblk;          // 32-row reference blocks
     int splits;            // reference ranges of the main screen
     int precision;         // rsc_precision of the screen
+    int metric;            // rsc_metric
 };
 
 struct KnnBuffers {
@@ -84,6 +85,7 @@ struct KnnBuffers {
     int32_t *flag1, *flag2;
     int32_t *esc_idx;
     float *esc_key;
+    float *qn, *rn;   // unit-normalised queries / references (cosine metric)
 };
 
 // Arguments of the float64 rerank (knn.hip).
@@ -97,6 +99,8 @@ struct RerankArgs {
     int d, k, S, KP, P;
     int self_mode;
     int certify;            // 0: approximate screen, never flag rows
+    int metric;             // rsc_metric of the reported distances
+    double cosine_eps;      // cosine: bound on |screened key - (2 D - 1)| for unit vectors
     const int32_t *cand_idx;
     const float *cand_key;
     double eps_coef;
@@ -125,6 +129,7 @@ int knn_prep_fp32(const KnnPlan &p, const float *R, const KnnBuffers &b, const i
 int knn_launch_rerank(const RerankArgs &ra, int64_t slots, const char *name, hipStream_t stream);
 // exhaustive float64 rescan of the rows flagged in b (first certificate only
 // when there was no escalation); soff/nsamples restrict each row to its sample.
+// (uses p.metric for the distances)
 int knn_launch_rescan(const KnnPlan &p, const float *Q, const float *R, const KnnBuffers &b, int esc_cap,
                       int32_t *out_idx, float *out_dist, const int64_t *soff, int nsamples, hipStream_t stream);
 

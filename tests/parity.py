@@ -20,11 +20,25 @@ NEAR_TIE = 1e-5
 REL_TOL = 1e-5
 
 
-def compare_knn(X, rows, idx_g, dist_g, idx_o, dist_o, oracle, k, self_mode=True):
+def cosine_pair_dist(X, ii, jj):
+    """Cosine distances 1 - cos of row pairs (float64; the near-tie check only)."""
+    a = np.asarray(X, dtype=np.float64)[np.asarray(ii)]
+    b = np.asarray(X, dtype=np.float64)[np.asarray(jj)]
+    na, nb = np.sqrt((a * a).sum(1)), np.sqrt((b * b).sum(1))
+    c = np.where((na > 0) & (nb > 0), (a * b).sum(1) / np.maximum(na * nb, 1e-300), 0.0)
+    return 1.0 - c
+
+
+def compare_knn(X, rows, idx_g, dist_g, idx_o, dist_o, oracle, k, self_mode=True, pair_dist=None):
     """Compare GPU rows (already sliced to ``rows``) with oracle rows.
 
-    Returns a dict of counters; raises AssertionError on a real mismatch.
+    ``pair_dist(X, ii, jj)`` gives the distances of row pairs for the near-tie
+    check (default: Euclidean, from the oracle).  Returns a dict of counters;
+    raises AssertionError on a real mismatch.
     """
+    if pair_dist is None:
+        def pair_dist(X_, ii, jj):
+            return np.sqrt(oracle.pair_d2(X_, ii, jj))
     idx_g = np.asarray(idx_g)
     dist_g = np.asarray(dist_g, dtype=np.float64)
     idx_o = np.asarray(idx_o)
@@ -52,8 +66,8 @@ def compare_knn(X, rows, idx_g, dist_g, idx_o, dist_o, oracle, k, self_mode=True
             assert (np.diff(dg) >= 0).all(), f"row {rows[r]}: GPU distances not ascending"
             tie_rows.append(rows[r])
             continue
-        dk = np.sqrt(oracle.pair_d2(X, np.array([rows[r]]), np.array([oi[-1]])))[0]
-        dj = np.sqrt(oracle.pair_d2(X, np.full(len(diff), rows[r]), np.array(diff)))
+        dk = pair_dist(X, np.array([rows[r]]), np.array([oi[-1]]))[0]
+        dj = pair_dist(X, np.full(len(diff), rows[r]), np.array(diff))
         rel = np.abs(dj - dk) / max(dk, 1e-300)
         assert (rel < NEAR_TIE).all(), (
             f"row {rows[r]}: neighbour sets differ beyond a near-tie: gpu={gi.tolist()} oracle={oi.tolist()} "

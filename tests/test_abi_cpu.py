@@ -216,3 +216,16 @@ def test_routed_validation(lib):
     assert lib.rsc_partition_kmeans_workspace_bytes(10, 50, 64) == 0
     assert lib.rsc_partition_lists(FAKE, 10, 0, FAKE, FAKE, ctypes.c_void_p(0x100000), 1 << 20, None) == -1
     assert lib.rsc_partition_labels(None, 10, 3, FAKE, 10, FAKE, None) == -1
+
+
+def test_metric_validation(lib):
+    from paper_2603_02402_amd import _lib
+
+    bad = _lib.KnnOpts(0, 0, 2, 0)
+    assert lib.rsc_knn_ex(FAKE, 10, FAKE, 100, 50, 15, ctypes.byref(bad), FAKE, FAKE, FAKE, 1 << 30, None) == -1
+    assert "metric" in _err(lib)
+    cos = _lib.KnnOpts(0, 0, 1, 0)
+    eu = _lib.KnnOpts(0, 0, 0, 0)
+    # the cosine form keeps the normalised rows in its workspace
+    assert lib.rsc_knn_workspace_bytes(1000, 1000, 50, 15, ctypes.byref(cos)) > \
+        lib.rsc_knn_workspace_bytes(1000, 1000, 50, 15, ctypes.byref(eu)) + 1000 * 50 * 4 - 1
