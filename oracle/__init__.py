@@ -8,7 +8,8 @@ The arithmetic lives in ``oracle.c`` (float64, brute force, compiled with
 ``-ffp-contract=off``); this module only builds it with gcc and marshals
 numpy arrays.  ``mlp.py`` holds the float64 reference of the partition
 router's network, ``partition.py`` the k-means partitions and the routed
-form's candidate sets.
+form's candidate sets, ``edistance.py`` the group-pair distance sums and
+energy distances.
 """
 
 from __future__ import annotations
@@ -61,6 +62,8 @@ def _load():
             lib.oracle_knn_cosine.restype = i32
             lib.oracle_knn_subset.argtypes = [P, i64, i32, i32, P, i64, P, P, P, P, P]
             lib.oracle_knn_subset.restype = i32
+            lib.oracle_edistance_sums.argtypes = [P, i64, i32, P, i64, P, P, i64, P]
+            lib.oracle_edistance_sums.restype = i32
             _lib = lib
     return _lib
 

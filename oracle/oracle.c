@@ -28,6 +28,10 @@
  *                  row-wise access) with ascending unique columns, no
  *                  diagonal, no stored zeros.
  *
+ *   edistance_sums the group-pair sums of Euclidean distances behind the
+ *                  energy distance (Methods, "Perturbation distance
+ *                  computation"); see the function's comment.
+ *
  * Readings where the paper is silent (each listed in the design notes):
  *   - k counts the query itself: k slots, slot 0 = self, k-1 neighbours,
  *     target log2(k).
@@ -470,4 +474,44 @@ int oracle_knn_cosine(const float *Q, int64_t nq, const int64_t *self_ids, const
         free(bj);
     }
     return fail ? -1 : 0;
+}
+
+/*
+ * Group-pair distance sums for the energy distance (Methods, "Perturbation
+ * distance computation").  Cells are grouped through category offsets and a
+ * sorted cell-index array: group g holds the rows cells[offsets[g] ..
+ * offsets[g+1]).  For every listed pair (a, b):
+ *
+ *   a != b   out = sum over i in a, j in b of ||x_i - x_j||
+ *   a == b   out = sum over i < j (positions within the group) of
+ *            ||x_i - x_j||, the upper triangle only; 0 for a group with
+ *            fewer than two cells
+ *
+ * Each distance is the square root of the float64 sum of squared direct
+ * differences; the sums run sequentially in float64, rows of a outer.
+ * Returns 0, or -1 for invalid arguments (a group id out of range, offsets
+ * not ascending, a cell index out of range).
+ */
+int oracle_edistance_sums(const float *X, int64_t n, int d, const int64_t *offsets, int64_t G,
+                          const int32_t *cells, const int32_t *pairs, int64_t npairs, double *out) {
+    if (n < 0 || d < 1 || G < 1 || npairs < 0) return -1;
+    if (offsets[0] != 0) return -1;
+    for (int64_t g = 0; g < G; ++g)
+        if (offsets[g + 1] < offsets[g]) return -1;
+    for (int64_t c = 0; c < offsets[G]; ++c)
+        if (cells[c] < 0 || cells[c] >= n) return -1;
+    for (int64_t p = 0; p < npairs; ++p)
+        if (pairs[2 * p] < 0 || pairs[2 * p] >= G || pairs[2 * p + 1] < 0 || pairs[2 * p + 1] >= G) return -1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t p = 0; p < npairs; ++p) {
+        const int64_t a = pairs[2 * p], b = pairs[2 * p + 1];
+        double s = 0.0;
+        for (int64_t u = offsets[a]; u < offsets[a + 1]; ++u) {
+            const float *x = X + (int64_t)cells[u] * d;
+            const int64_t v0 = a == b ? u + 1 : offsets[b];
+            for (int64_t v = v0; v < offsets[b + 1]; ++v) s = s + sqrt(sq_dist(x, X + (int64_t)cells[v] * d, d));
+        }
+        out[p] = s;
+    }
+    return 0;
 }

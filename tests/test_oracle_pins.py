@@ -525,3 +525,106 @@ def test_cosine_knn_hand_angles_scale_invariance_and_zero_rows():
     assert idx[10, 1:].tolist() == [j for j in range(150) if j != 10]  # all ties: index order
     pos = np.argwhere(idx[3] == 10)[0, 0]
     assert d[3, pos] == 1.0
+
+
+# ---------------------------------------------------------------------------
+# Energy distance between groups of cells (Methods, "Perturbation distance
+# computation").
+# ---------------------------------------------------------------------------
+
+def _ed_groups(sizes, d, seed, shuffle=True):
+    rng = np.random.default_rng(seed)
+    n = int(sum(sizes))
+    X = (rng.standard_normal((n, d)) * rng.uniform(0.5, 2.0, d)).astype(np.float32)
+    labels = np.repeat(np.arange(len(sizes)), sizes)
+    if shuffle:
+        labels = rng.permutation(labels)
+    return X, labels
+
+
+def test_edistance_sums_match_cdist_brute_force():
+    import math
+
+    from scipy.spatial.distance import cdist
+
+    from oracle import edistance as ed
+
+    sizes = [1, 2, 7, 30, 0, 45, 3]
+    X, labels = _ed_groups(sizes, 9, seed=3)
+    off, cells = ed.groups_from_labels(labels, G=len(sizes))
+    # cells of a group need not be ascending: reverse every group's list
+    cells = np.concatenate([cells[off[g]:off[g + 1]][::-1] for g in range(len(sizes))]).astype(np.int32)
+    pairs = ed.all_pairs(len(sizes))
+    s = ed.sums(X, off, cells, pairs)
+    Xd = X.astype(np.float64)
+    for (a, b), v in zip(pairs, s):
+        A = Xd[labels == a]
+        B = Xd[labels == b]
+        if A.size == 0 or B.size == 0:
+            assert v == 0.0
+            continue
+        C = cdist(A, B)
+        ref = math.fsum(np.triu(C, 1).ravel()) if a == b else math.fsum(C.ravel())
+        assert abs(v - ref) <= 1e-12 * max(ref, 1.0), (a, b, v, ref)
+
+
+def test_edistance_matches_scipy_energy_distance_in_one_dimension():
+    from scipy.stats import energy_distance
+
+    from oracle import edistance as ed
+
+    rng = np.random.default_rng(8)
+    u = rng.standard_normal(40).astype(np.float32)
+    v = (rng.standard_normal(25) * 1.5 + 0.7).astype(np.float32)
+    X = np.concatenate([u, v])[:, None]
+    off = np.array([0, 40, 65], dtype=np.int64)
+    cells = np.arange(65, dtype=np.int32)
+    E, D = ed.pairwise(X, off, cells)
+    # scipy's statistic uses all n^2 within pairs (the i = i' zeros included):
+    # its square is 2 d_ab - d_aa (n_a - 1)/n_a - d_bb (n_b - 1)/n_b
+    ev = 2 * D[0, 1] - D[0, 0] * 39 / 40 - D[1, 1] * 24 / 25
+    assert abs(ev - energy_distance(u.astype(np.float64), v.astype(np.float64)) ** 2) <= 1e-12
+    assert E[0, 1] == E[1, 0] and E[0, 0] == 0.0 and E[1, 1] == 0.0
+
+
+def test_edistance_closed_form_on_lattices():
+    from oracle import edistance as ed
+
+    # A = {0, h, ..., (m-1) h} on a line, B = A + L with L >= m h:
+    # within mean h (m + 1) / 3, cross mean L, E = 2 L - 2 h (m + 1) / 3
+    m, h, L = 24, 0.5, 40.0
+    X = np.zeros((2 * m, 4), dtype=np.float32)
+    X[:m, 1] = np.arange(m) * h
+    X[m:, 1] = np.arange(m) * h + L
+    off = np.array([0, m, 2 * m], dtype=np.int64)
+    E, D = ed.pairwise(X, off, np.arange(2 * m, dtype=np.int32))
+    assert D[0, 0] == D[1, 1] == h * (m + 1) / 3
+    assert D[0, 1] == L
+    assert abs(E[0, 1] - (2 * L - 2 * h * (m + 1) / 3)) <= 1e-14 * 2 * L
+
+
+def test_edistance_special_cases_and_invariances():
+    from oracle import edistance as ed
+
+    # two singletons: no within pairs (skipped), E = 2 |x - y|
+    X = np.array([[0, 0], [3, 4]], dtype=np.float32)
+    E, D = ed.pairwise(X, np.array([0, 1, 2], dtype=np.int64), np.array([0, 1], dtype=np.int32))
+    assert D[0, 0] == 0 and D[1, 1] == 0 and E[0, 1] == 10.0
+    # an empty group: its cross means are NaN, its within mean is skipped
+    E, D = ed.pairwise(X, np.array([0, 1, 1, 2], dtype=np.int64), np.array([0, 1], dtype=np.int32))
+    assert np.isnan(D[0, 1]) and np.isnan(E[0, 1]) and D[1, 1] == 0 and E[0, 2] == 10.0
+    # integer coordinates: translation and power-of-two scaling are exact
+    sizes = [5, 9, 14, 2]
+    rng = np.random.default_rng(4)
+    Xi = rng.integers(-20, 20, size=(30, 6)).astype(np.float32)
+    off, cells = ed.groups_from_labels(rng.permutation(np.repeat(np.arange(4), sizes)), G=4)
+    E1, _ = ed.pairwise(Xi, off, cells)
+    E2, _ = ed.pairwise(Xi + np.float32(64), off, cells)
+    E3, _ = ed.pairwise(Xi * np.float32(8), off, cells)
+    np.testing.assert_allclose(E2, E1, rtol=1e-13, atol=1e-12)
+    np.testing.assert_allclose(E3, 8 * E1, rtol=1e-13, atol=1e-12)
+    assert np.array_equal(E1, E1.T) and (np.diag(E1) == 0).all()
+    # one-sided distances are the reference group's row of the pairwise matrix
+    # (a cross sum taken as (ref, g) rather than (g, ref) adds in another order)
+    for ref in range(4):
+        np.testing.assert_allclose(ed.onesided(Xi, off, cells, ref), E1[ref], rtol=1e-13, atol=1e-13)
