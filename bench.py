@@ -260,6 +260,83 @@ def cosine_form(args, rsc, Xt, ws, out) -> dict:
             "max_err_ratio": round(stats["max_err_ratio"], 4), "nnz": int(g.nnz)}
 
 
+PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 matrix
+
+
+def edistance_form(args, rsc) -> dict:
+    """Energy distances of a perturbation screen (1000 groups: 20k control
+    cells, 999 perturbations of 50-350 cells, d = 50): the full G x G matrix
+    and the one-sided distances to the control group."""
+    import torch
+
+    import synth
+
+    X, labels = synth.perturbation_screen()
+    G = synth.EDIST["n_groups"]
+    n, d = X.shape
+    Xt = torch.from_numpy(X).cuda()
+    ws = rsc.Workspace()
+    off, ct = rsc.edistance_groups(torch.from_numpy(labels).cuda(), G, workspace=ws)  # counting sort on the GPU
+    log("[bench] edistance: warmup")
+    rsc.edistance_pairwise(Xt, off, ct, workspace=ws)
+    rsc.edistance_onesided(Xt, off, ct, 0, workspace=ws)
+    torch.cuda.synchronize()
+    steps = max(args.form_steps, 3)
+    rsc.profile_reset()
+    rsc.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        E = rsc.edistance_pairwise(Xt, off, ct, workspace=ws)
+    torch.cuda.synchronize()
+    ms_pw = (time.perf_counter() - t0) * 1e3 / steps
+    tiles_ms = rsc.profile_get("ed_tiles")[0] / steps
+    plan_ms = rsc.profile_get("ed_plan")[0] / steps
+    rsc.profile_reset()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        rsc.edistance_onesided(Xt, off, ct, 0, workspace=ws)
+    torch.cuda.synchronize()
+    ms_os = (time.perf_counter() - t0) * 1e3 / steps
+    os_tiles_ms = rsc.profile_get("ed_tiles")[0] / steps
+    rsc.profile_enable(False)
+    dists = n * (n - 1) / 2
+    flops = 2.0 * d * dists
+    E_h = E.cpu().numpy()
+    cpu = None if args.no_cpu_baseline else edistance_cpu_baseline(X, labels, G)
+    return {"workload": f"perturbation screen: {n} cells, d={d}, {G} groups (control 20,000 cells; 999 "
+                        "perturbations of 50-350 cells, 30% with an effect), seed 9",
+            "pairwise_ms": round(ms_pw, 2), "pairwise_distances_per_s": round(dists / (ms_pw / 1e3), 1),
+            "pairwise_tile_kernel_ms": round(tiles_ms, 2), "plan_ms": round(plan_ms, 3),
+            "tile_kernel_fp64_tflops": round(flops / (tiles_ms / 1e3) / 1e12, 2),
+            "tile_kernel_frac_of_fp64_peak": round(flops / (tiles_ms / 1e3) / 1e12 / PEAK_FP64_TFLOPS, 4),
+            "work_per_call": f"n(n-1)/2 = {dists:.4e} distances, 2 d flops each on the float64 matrix cores",
+            "onesided_ms": round(os_tiles_ms if os_tiles_ms else ms_os, 2), "onesided_call_ms": round(ms_os, 2),
+            "E_range": [round(float(E_h.min()), 6), round(float(E_h.max()), 6)],
+            "cpu_baseline": cpu}
+
+
+def edistance_cpu_baseline(X, labels, G) -> dict:
+    """The oracle (float64 direct differences) on sampled group pairs of the
+    same screen (control against four perturbations, three perturbation pairs,
+    three within-group sums), as distances per second."""
+    import oracle
+    from oracle import edistance as oed
+
+    off, cells = oed.groups_from_labels(labels, G=G)
+    rng = np.random.default_rng(3)
+    gs = rng.choice(np.arange(1, G), size=10, replace=False)
+    pairs = np.array([[0, g] for g in gs[:4]] + [[gs[i], gs[i + 1]] for i in range(4, 10, 2)] +
+                     [[g, g] for g in gs[:3]], dtype=np.int32)
+    cnt = oed.pair_counts(np.diff(off), pairs)
+    t0 = time.perf_counter()
+    oed.sums(X, off, cells, pairs)
+    secs = time.perf_counter() - t0
+    return {"value": round(float(cnt.sum() / secs), 1), "unit": "distances/s",
+            "cores": min(oracle.max_threads(), len(pairs)), "kind": "oracle",
+            "sample": f"{int(cnt.sum())} distances of {len(pairs)} sampled group pairs, one thread per pair "
+                      f"({secs:.2f} s)"}
+
+
 def batched_form(args, rsc) -> dict:
     """64 independent samples (log-uniform 2k..200k cells, 10-40 clusters each):
     per-sample exact kNN in one persistent launch + connectivities."""
@@ -452,7 +529,7 @@ def main() -> int:
     ap.add_argument("--no-forms", action="store_true", help="skip the 2M-cell precision forms")
     ap.add_argument("--form-steps", type=int, default=3)
     ap.add_argument("--no-routed", action="store_true", help="skip the learned-router form")
-    ap.add_argument("--only", choices=["cosine", "precision", "batched", "routed"],
+    ap.add_argument("--only", choices=["cosine", "edistance", "precision", "batched", "routed"],
                     help="run one form alone and print its record (no benchmark line)")
     ap.add_argument("--routed-n", type=int, default=5_000_000)
     ap.add_argument("--routed-train", type=int, default=1_000_000)
@@ -492,7 +569,8 @@ def main() -> int:
         print(json.dumps({"cosine": cosine_form(args, rsc, Xc, rsc.Workspace(), out)}), flush=True)
         return 0
     if args.only:
-        fn = {"precision": precision_forms, "batched": batched_form, "routed": routed_form}[args.only]
+        fn = {"precision": precision_forms, "batched": batched_form, "routed": routed_form,
+              "edistance": edistance_form}[args.only]
         print(json.dumps({args.only: fn(args, rsc)}), flush=True)
         return 0
 
@@ -564,6 +642,8 @@ def main() -> int:
         forms.update(precision_forms(args, rsc))
         torch.cuda.empty_cache()
         forms["batched_fp32"] = batched_form(args, rsc)
+        torch.cuda.empty_cache()
+        forms["edistance_fp64"] = edistance_form(args, rsc)
         if not args.no_routed:
             torch.cuda.empty_cache()
             forms["routed"] = routed_form(args, rsc)

@@ -398,6 +398,91 @@ int rsc_knn_routed(const rsc_router *router, const float *X, int64_t n, int32_t 
                    size_t workspace_bytes, void *stream);
 
 /* ---------------------------------------------------------------------- */
+/* Energy distance between groups of cells                                 */
+/* ---------------------------------------------------------------------- */
+/*
+ * Methods, "Perturbation distance computation": for groups X, Y of cells,
+ *   E(X, Y) = 2 mean ||X_i - Y_j|| - mean ||X_i - X_i'|| - mean ||Y_j - Y_j'||
+ * with the cross mean over all n_X n_Y pairs and each within mean over the
+ * n (n - 1) / 2 pairs of the upper triangle.  A group with fewer than two
+ * cells is skipped: its within mean counts as 0.  A cross mean with an empty
+ * group has no pairs and is NaN.
+ *
+ * Groups use the paper's category-index layout:
+ *   offsets   HOST int64 [G + 1], offsets[0] = 0, non-decreasing; group g
+ *             holds cells[offsets[g] .. offsets[g+1]).  Copied during the
+ *             call (the host array may be reused when it returns).
+ *   cells     DEVICE int32 [offsets[G]], row ids of X in [0, n); an id
+ *             outside that range is read as no cell (the kernels never
+ *             touch memory outside X), so such input gives wrong sums.
+ *   X         DEVICE float32 [n][d], row-major, finite values; any d >= 1.
+ * Distances are float64: dot products on the float64 matrix cores, norms
+ * and square roots in float64; each distance is within
+ * min(sqrt(e), e / dist) + 4 u dist of the exact one, with
+ * e = 2 (d + 4) u (||x||^2 + ||y||^2) and u = 2^-53.
+ * Each pair's sum is accumulated in 64-bit fixed point (scale from an upper
+ * bound of the sum), so results do not depend on scheduling.
+ * G <= 2^20 groups, offsets[G] <= 2^31 cells.  Work is queued on `stream`.
+ * Errors: RSC_ERR_INVALID_ARG (null pointer, bad offsets, group id out of
+ * range), RSC_ERR_WORKSPACE (workspace smaller than the *_workspace_bytes
+ * figure), RSC_ERR_HIP.
+ */
+
+/* Workspace bytes for rsc_edistance_groups (0 for invalid sizes, or when
+ * no device is available to size the sort). */
+size_t rsc_edistance_groups_workspace_bytes(int64_t n, int64_t n_groups);
+
+/*
+ * The category-index layout of integer labels (DEVICE int32 [n], values in
+ * [0, G)): offsets DEVICE int64 [G + 1] and cells DEVICE int32 [n], each
+ * group's rows in ascending order (a stable radix sort of (label, row)).
+ * Synchronises `stream` to report RSC_ERR_INVALID_ARG for a label outside
+ * [0, G); copy offsets to the host for the calls below.
+ */
+int rsc_edistance_groups(const int32_t *labels, int64_t n, int64_t n_groups, int64_t *offsets, int32_t *cells,
+                         void *workspace, size_t workspace_bytes, void *stream);
+
+/* Workspace bytes for rsc_edistance_sums with n_pairs pairs over G groups
+ * holding n_cells = offsets[G] cells of dimension d (0 for invalid sizes).
+ * The workspace holds the grouped rows in group order (n_cells x d float32)
+ * and their norms, so that a tile's rows are contiguous. */
+size_t rsc_edistance_sums_workspace_bytes(int64_t n_groups, int64_t n_pairs, int64_t n_cells, int32_t d);
+
+/*
+ * Sums of distances for a list of group pairs.
+ *   pairs   HOST int32 [n_pairs][2] (a, b); a == b gives the within sum
+ *           over the upper triangle, a != b the sum over all n_a n_b pairs.
+ *   sums    DEVICE float64 [n_pairs].
+ */
+int rsc_edistance_sums(const float *X, int64_t n, int32_t d, const int64_t *offsets, int64_t n_groups,
+                       const int32_t *cells, const int32_t *pairs, int64_t n_pairs, double *sums, void *workspace,
+                       size_t workspace_bytes, void *stream);
+
+/* Workspace bytes for rsc_edistance_pairwise (G (G + 1) / 2 pairs). */
+size_t rsc_edistance_pairwise_workspace_bytes(int64_t n_groups, int64_t n_cells, int32_t d);
+
+/*
+ * All energy distances: E DEVICE float64 [G][G] (symmetric, zero diagonal),
+ * D DEVICE float64 [G][G] mean distances (may be NULL).  E[a][b] is
+ * 2 D[a][b] - (D[a][a] + D[b][b]).
+ */
+int rsc_edistance_pairwise(const float *X, int64_t n, int32_t d, const int64_t *offsets, int64_t n_groups,
+                           const int32_t *cells, double *E, double *D, void *workspace, size_t workspace_bytes,
+                           void *stream);
+
+/* Workspace bytes for rsc_edistance_onesided (2 G - 1 pairs). */
+size_t rsc_edistance_onesided_workspace_bytes(int64_t n_groups, int64_t n_cells, int32_t d);
+
+/*
+ * Methods, "Perturbation distance computation" (one-sided distances): E from
+ * the reference group `ref` to every group, computing only the cross pairs
+ * (ref, g) and the within pairs.  E DEVICE float64 [G], E[ref] = 0.
+ */
+int rsc_edistance_onesided(const float *X, int64_t n, int32_t d, const int64_t *offsets, int64_t n_groups,
+                           const int32_t *cells, int64_t ref, double *E, void *workspace, size_t workspace_bytes,
+                           void *stream);
+
+/* ---------------------------------------------------------------------- */
 /* Kernel timing (off by default)                                          */
 /* ---------------------------------------------------------------------- */
 

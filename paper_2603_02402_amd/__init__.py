@@ -11,6 +11,8 @@ torch's current stream.  Functions mirror the C calls:
 * :mod:`.routed`          -> partitions, the router network, probed and
   routed kNN (``rsc_partition_*``, ``rsc_router_*``, ``rsc_knn_probed``,
   ``rsc_knn_routed``)
+* :mod:`.edistance`       -> energy distances between groups of cells
+  (``rsc_edistance_*``)
 """
 
 from __future__ import annotations
@@ -27,7 +29,7 @@ __all__ = [
     "read_knn_stats", "profile_enable", "profile_reset", "profile_get", "RscError", "Workspace",
     "RSC_FP32", "RSC_BF16", "RSC_FP8_E4M3", "RSC_EUCLIDEAN", "RSC_COSINE", "abi_version", "knn_batched", "knn_batched_autotune",
     "knn_batched_workspace_bytes", "Router", "partition_kmeans", "partition_lists", "partition_labels",
-    "knn_probed", "knn_routed",
+    "knn_probed", "knn_routed", "edistance_groups", "edistance_sums", "edistance_pairwise", "edistance_onesided",
 ]
 
 
@@ -255,3 +257,5 @@ def profile_get(name: str):
 
 from .routed import (Router, knn_probed, knn_routed, partition_kmeans, partition_labels,  # noqa: E402
                      partition_lists)
+from .edistance import (edistance_groups, edistance_onesided, edistance_pairwise,  # noqa: E402
+                        edistance_sums)

@@ -96,6 +96,14 @@ SIGNATURES = {
     "rsc_knn_routed_workspace_bytes": (_SZ, [_P, _I64, _I32, _I32, _I32, _I32]),
     "rsc_knn_routed": (ctypes.c_int, [_P, _P, _I64, _I32, _I32, _P, _P, _I32, _I32, _F, _P, _P, _P, _P, _P, _SZ,
                                       _P]),
+    "rsc_edistance_groups_workspace_bytes": (_SZ, [_I64, _I64]),
+    "rsc_edistance_groups": (ctypes.c_int, [_P, _I64, _I64, _P, _P, _P, _SZ, _P]),
+    "rsc_edistance_sums_workspace_bytes": (_SZ, [_I64, _I64, _I64, _I32]),
+    "rsc_edistance_sums": (ctypes.c_int, [_P, _I64, _I32, _P, _I64, _P, _P, _I64, _P, _P, _SZ, _P]),
+    "rsc_edistance_pairwise_workspace_bytes": (_SZ, [_I64, _I64, _I32]),
+    "rsc_edistance_pairwise": (ctypes.c_int, [_P, _I64, _I32, _P, _I64, _P, _P, _P, _P, _SZ, _P]),
+    "rsc_edistance_onesided_workspace_bytes": (_SZ, [_I64, _I64, _I32]),
+    "rsc_edistance_onesided": (ctypes.c_int, [_P, _I64, _I32, _P, _I64, _P, _I64, _P, _P, _SZ, _P]),
     "rsc_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "rsc_profile_reset": (ctypes.c_int, []),
     "rsc_profile_get": (ctypes.c_int, [ctypes.c_char_p, _P, _P]),

@@ -473,6 +473,69 @@ int rsc_knn_routed(const rsc_router *router, const float *X, int64_t n, int32_t 
                       out_idx, out_dist, out_route, stats, workspace, oi, s);
 }
 
+size_t rsc_edistance_groups_workspace_bytes(int64_t n, int64_t n_groups) {
+    return edistance_groups_workspace_bytes(n, n_groups);
+}
+
+int rsc_edistance_groups(const int32_t *labels, int64_t n, int64_t n_groups, int64_t *offsets, int32_t *cells,
+                         void *workspace, size_t workspace_bytes, void *stream) {
+    clear_error();
+    if (!aligned(labels, 4) || !aligned(offsets, 8) || !aligned(cells, 4) || !aligned(workspace, 256)) {
+        set_error("misaligned array or workspace");
+        return RSC_ERR_INVALID_ARG;
+    }
+    return edistance_groups(labels, n, n_groups, offsets, cells, workspace, workspace_bytes,
+                            static_cast<hipStream_t>(stream));
+}
+
+size_t rsc_edistance_sums_workspace_bytes(int64_t n_groups, int64_t n_pairs, int64_t n_cells, int32_t d) {
+    return edistance_sums_workspace_bytes(n_groups, n_pairs, n_cells, d);
+}
+
+int rsc_edistance_sums(const float *X, int64_t n, int32_t d, const int64_t *offsets, int64_t n_groups,
+                       const int32_t *cells, const int32_t *pairs, int64_t n_pairs, double *sums, void *workspace,
+                       size_t workspace_bytes, void *stream) {
+    clear_error();
+    if (!aligned(X, 4) || !aligned(cells, 4) || !aligned(sums, 8) || !aligned(workspace, 256)) {
+        set_error("misaligned array or workspace");
+        return RSC_ERR_INVALID_ARG;
+    }
+    return edistance_sums(X, n, d, offsets, n_groups, cells, pairs, n_pairs, sums, workspace, workspace_bytes,
+                          static_cast<hipStream_t>(stream));
+}
+
+size_t rsc_edistance_pairwise_workspace_bytes(int64_t n_groups, int64_t n_cells, int32_t d) {
+    return edistance_pairwise_workspace_bytes(n_groups, n_cells, d);
+}
+
+int rsc_edistance_pairwise(const float *X, int64_t n, int32_t d, const int64_t *offsets, int64_t n_groups,
+                           const int32_t *cells, double *E, double *D, void *workspace, size_t workspace_bytes,
+                           void *stream) {
+    clear_error();
+    if (!aligned(X, 4) || !aligned(cells, 4) || !aligned(E, 8) || !aligned(D, 8) || !aligned(workspace, 256)) {
+        set_error("misaligned array or workspace");
+        return RSC_ERR_INVALID_ARG;
+    }
+    return edistance_pairwise(X, n, d, offsets, n_groups, cells, E, D, workspace, workspace_bytes,
+                              static_cast<hipStream_t>(stream));
+}
+
+size_t rsc_edistance_onesided_workspace_bytes(int64_t n_groups, int64_t n_cells, int32_t d) {
+    return edistance_onesided_workspace_bytes(n_groups, n_cells, d);
+}
+
+int rsc_edistance_onesided(const float *X, int64_t n, int32_t d, const int64_t *offsets, int64_t n_groups,
+                           const int32_t *cells, int64_t ref, double *E, void *workspace, size_t workspace_bytes,
+                           void *stream) {
+    clear_error();
+    if (!aligned(X, 4) || !aligned(cells, 4) || !aligned(E, 8) || !aligned(workspace, 256)) {
+        set_error("misaligned array or workspace");
+        return RSC_ERR_INVALID_ARG;
+    }
+    return edistance_onesided(X, n, d, offsets, n_groups, cells, ref, E, workspace, workspace_bytes,
+                              static_cast<hipStream_t>(stream));
+}
+
 int rsc_profile_enable(int enable) {
     Profiler &p = profiler();
     std::lock_guard<std::mutex> lock(p.mu);

@@ -201,6 +201,21 @@ int probed_run(const float *X, int64_t n, int d, int k, const int64_t *offsets, 
                float threshold, int32_t *out_idx, float *out_dist, uint8_t *out_route, rsc_routed_stats *stats,
                void *ws, size_t ws_bytes, hipStream_t s);
 
+// ---- energy distance (edistance.hip) -------------------------------------
+
+size_t edistance_sums_workspace_bytes(int64_t G, int64_t npairs, int64_t ncells, int d);
+size_t edistance_pairwise_workspace_bytes(int64_t G, int64_t ncells, int d);
+size_t edistance_onesided_workspace_bytes(int64_t G, int64_t ncells, int d);
+size_t edistance_groups_workspace_bytes(int64_t n, int64_t G);
+int edistance_groups(const int32_t *labels, int64_t n, int64_t G, int64_t *offsets, int32_t *cells, void *ws,
+                     size_t ws_bytes, hipStream_t s);
+int edistance_sums(const float *X, int64_t n, int d, const int64_t *offsets, int64_t G, const int32_t *cells,
+                   const int32_t *pairs, int64_t npairs, double *sums, void *ws, size_t ws_bytes, hipStream_t s);
+int edistance_pairwise(const float *X, int64_t n, int d, const int64_t *offsets, int64_t G, const int32_t *cells,
+                       double *E, double *D, void *ws, size_t ws_bytes, hipStream_t s);
+int edistance_onesided(const float *X, int64_t n, int d, const int64_t *offsets, int64_t G, const int32_t *cells,
+                       int64_t ref, double *E, void *ws, size_t ws_bytes, hipStream_t s);
+
 // ---- graph stages (graph.hip) --------------------------------------------
 
 size_t graph_workspace_bytes(int64_t n, int k);

@@ -48,6 +48,8 @@ __all__ = [
     "random_probes",
     "random_mask",
     "random_labels",
+    "EDIST",
+    "perturbation_screen",
 ]
 
 _CHUNK = 1 << 18  # rows drawn per call; the PCG64 stream is identical to one big draw
@@ -259,3 +261,36 @@ def random_knn_lists(n: int, k: int, seed: int, hub_fraction: float = 0.01):
     dist = np.cumsum(gaps, axis=1)
     dist[:, 1:] += 0.5
     return idx.astype(np.int32), dist.astype(np.float32)
+
+
+# Energy-distance workload: a perturbation screen.  One large control group
+# and many perturbation groups whose sizes are log-uniform; every cell is
+# drawn from the same PCA-like noise N(0, diag(1/i)); perturbation g shifts
+# its cells by an effect vector that is 0 for 70% of the groups (no
+# phenotype) and N(0, s^2 diag(1/i)) with s log-uniform in [0.2, 2] for the
+# rest.  Labels are shuffled so that a group's cells are scattered over X.
+EDIST = {"n_groups": 1000, "control": 20_000, "lo": 50, "hi": 350, "seed": 9}
+
+
+def perturbation_screen(n_groups: int | None = None, control: int | None = None, lo: int | None = None,
+                        hi: int | None = None, d: int = 50, seed: int | None = None):
+    """``(X float32 n x d, labels int32 n)``; group 0 is the control group."""
+    G = EDIST["n_groups"] if n_groups is None else n_groups
+    c0 = EDIST["control"] if control is None else control
+    lo = EDIST["lo"] if lo is None else lo
+    hi = EDIST["hi"] if hi is None else hi
+    rng = _rng(EDIST["seed"] if seed is None else seed)
+    sizes = np.exp(rng.uniform(np.log(lo), np.log(hi + 1), size=G - 1)).astype(np.int64)
+    sizes = np.concatenate([[c0], sizes])
+    lam = _noise_scale(d)
+    effect = np.zeros((G, d))
+    hit = rng.random(G) < 0.3
+    hit[0] = False
+    s = np.exp(rng.uniform(np.log(0.2), np.log(2.0), size=G))
+    effect[hit] = rng.standard_normal((int(hit.sum()), d)) * lam * s[hit, None]
+    labels = rng.permutation(np.repeat(np.arange(G, dtype=np.int32), sizes))
+    X = np.empty((labels.size, d), dtype=np.float32)
+    for r0 in range(0, labels.size, _CHUNK):
+        lab = labels[r0:r0 + _CHUNK]
+        X[r0:r0 + lab.size] = (effect[lab] + rng.standard_normal((lab.size, d)) * lam).astype(np.float32)
+    return X, labels

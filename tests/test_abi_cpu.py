@@ -229,3 +229,36 @@ def test_metric_validation(lib):
     # the cosine form keeps the normalised rows in its workspace
     assert lib.rsc_knn_workspace_bytes(1000, 1000, 50, 15, ctypes.byref(cos)) > \
         lib.rsc_knn_workspace_bytes(1000, 1000, 50, 15, ctypes.byref(eu)) + 1000 * 50 * 4 - 1
+
+
+def test_edistance_validation(lib):
+    import numpy as np
+
+    def call(offsets, G, pairs, n_pairs, ws_bytes=1 << 30, d=50):
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        pr = np.ascontiguousarray(pairs, dtype=np.int32)
+        return lib.rsc_edistance_sums(FAKE, 1000, d, off.ctypes.data_as(ctypes.c_void_p), G, FAKE,
+                                      pr.ctypes.data_as(ctypes.c_void_p), n_pairs, FAKE, FAKE, ws_bytes, None)
+
+    good_pairs = [[0, 1], [1, 1]]
+    assert call([1, 5, 9], 2, good_pairs, 2) == -1 and "offsets[0]" in _err(lib)
+    assert call([0, 5, 3], 2, good_pairs, 2) == -1 and "non-decreasing" in _err(lib)
+    assert call([0, 5, 9], 2, [[0, 2], [1, 1]], 2) == -1 and "out of range" in _err(lib)
+    assert call([0, 5, 9], 2, [[-1, 0], [1, 1]], 2) == -1
+    assert call([0, 5, 9], 0, good_pairs, 2) == -1
+    assert call([0, 5, 9], 2, good_pairs, 2, d=0) == -1
+    assert call([0, 5, 9], 2, good_pairs, 2, ws_bytes=16) == -7 and "workspace" in _err(lib)
+    assert lib.rsc_edistance_sums_workspace_bytes(0, 5, 100, 50) == 0
+    assert lib.rsc_edistance_sums_workspace_bytes(3, 5, 100, 0) == 0
+    assert lib.rsc_edistance_pairwise_workspace_bytes(1000, 10**5, 50) > \
+        lib.rsc_edistance_onesided_workspace_bytes(1000, 10**5, 50) > 10**5 * 50 * 4
+    off = np.array([0, 5, 9], dtype=np.int64)
+    assert lib.rsc_edistance_onesided(FAKE, 1000, 50, off.ctypes.data_as(ctypes.c_void_p), 2, FAKE, 2, FAKE, FAKE,
+                                      1 << 30, None) == -1 and "reference" in _err(lib)
+
+
+def test_edistance_groups_validation(lib):
+    assert lib.rsc_edistance_groups(None, 10, 3, FAKE, FAKE, FAKE, 1 << 20, None) == -1
+    assert lib.rsc_edistance_groups(FAKE, 0, 3, FAKE, FAKE, FAKE, 1 << 20, None) == -1
+    assert lib.rsc_edistance_groups(FAKE, 10, 0, FAKE, FAKE, FAKE, 1 << 20, None) == -1
+    assert "edistance_groups" in _err(lib)
