@@ -455,18 +455,22 @@ __global__ __launch_bounds__(kEdThreads, 4) void k_ed_matrix(EdArgs a, const int
             for (int u = 0; u < 8; ++u) rs[u] = Ag[wr * 32 + (u >> 2) * 16 + 4 * (u & 3) + lk] - g0r;
 #pragma unroll
             for (int u = 0; u < 2; ++u) cs[u] = Bg[wc * 32 + u * 16 + lr] - g0c;
-            for (int sr = 0; sr < nsr; ++sr)
-                for (int sc = 0; sc < nsc; ++sc) {
-                    double sum = 0.0;
+            // per row group: the lane's two column partials (its columns 16 bj + lr),
+            // then one select per column and bin before the wave sum
+            for (int sr = 0; sr < nsr; ++sr) {
+                double p0 = 0.0, p1 = 0.0;
 #pragma unroll
-                    for (int e = 0; e < 16; ++e) {
-                        const int blk = e >> 2, q = e & 3;
-                        const bool in = rs[(blk >> 1) * 4 + q] == sr && cs[blk & 1] == sc;
-                        sum += in ? dv[e] : 0.0;
-                    }
+                for (int e = 0; e < 16; ++e) {
+                    const int blk = e >> 2, q = e & 3;
+                    const double v = rs[(blk >> 1) * 4 + q] == sr ? dv[e] : 0.0;
+                    if (blk & 1) p1 += v; else p0 += v;
+                }
+                for (int sc = 0; sc < nsc; ++sc) {
+                    double sum = (cs[0] == sc ? p0 : 0.0) + (cs[1] == sc ? p1 : 0.0);
                     for (int o = kWave / 2; o > 0; o >>= 1) sum += __shfl_xor(sum, o, kWave);
                     if (lane == 0) red[wave][sr * kBins + sc] = sum;
                 }
+            }
             __syncthreads();
             if (tid < nsr * nsc) {
                 const int sr = tid / nsc, sc = tid % nsc;
