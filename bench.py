@@ -337,6 +337,54 @@ def edistance_cpu_baseline(X, labels, G) -> dict:
                       f"({secs:.2f} s)"}
 
 
+def large_k_form(args, rsc) -> dict:
+    """Exact kNN graph at larger k on the plain 1M workload (same cells): the
+    main screen splits the references into about k / 32 ranges and the
+    float64 top-m spans up to 4 registers per lane."""
+    import torch
+
+    import synth
+
+    w = WORKLOADS["plain_1m"]
+    X = synth.mixture(w["n"], d=50, n_clusters=w["clusters"], law=w["law"], seed=w["seed"])
+    n, d = X.shape
+    Xt = torch.from_numpy(X).cuda()
+    del X
+    res = {"workload": "same cells as the plain line (n=1,000,000, d=50), exact FP32-screened path"}
+    for k in (30, 64, 100):
+        ws = rsc.Workspace()
+        ws.get(max(rsc.knn_workspace_bytes(n, n, d, k), rsc.connectivities_workspace_bytes(n, k)))
+        out = (torch.empty((n, k), dtype=torch.int32, device="cuda"), torch.empty((n, k), dtype=torch.float32, device="cuda"))
+        cap = 2 * n * (k - 1)
+        csr = (torch.empty(n + 1, dtype=torch.int64, device="cuda"), torch.empty(cap, dtype=torch.int32, device="cuda"),
+               torch.empty(cap, dtype=torch.float32, device="cuda"))
+        log(f"[bench] large k: k={k}")
+        rsc.knn(Xt, k, out=out, workspace=ws)
+        rsc.connectivities(out[0], out[1], workspace=ws, out=csr)
+        torch.cuda.synchronize()
+        rsc.profile_reset()
+        rsc.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(args.form_steps):
+            rsc.knn(Xt, k, out=out, workspace=ws)
+            st = rsc.read_knn_stats(ws)
+            g = rsc.connectivities(out[0], out[1], workspace=ws, out=csr)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.form_steps
+        rsc.profile_enable(False)
+        kern = {}
+        for name in ["screen_fp32", "rerank", "screen_escalate", "rerank_escalate", "rescan"]:
+            tot, cnt = rsc.profile_get(name)
+            if cnt:
+                kern[name] = round(tot / cnt, 3)
+        res[f"k{k}"] = {"cells_per_s": round(n / (ms / 1e3), 1), "ms_per_step": round(ms, 2), "kernel_ms": kern,
+                        "escalated_rows": st["escalated_rows"], "rescanned_rows": st["rescanned_rows"],
+                        "nnz": int(g.nnz)}
+        del out, csr, ws, g
+        torch.cuda.empty_cache()
+    return res
+
+
 def batched_form(args, rsc) -> dict:
     """64 independent samples (log-uniform 2k..200k cells, 10-40 clusters each):
     per-sample exact kNN in one persistent launch + connectivities."""
@@ -529,7 +577,7 @@ def main() -> int:
     ap.add_argument("--no-forms", action="store_true", help="skip the 2M-cell precision forms")
     ap.add_argument("--form-steps", type=int, default=3)
     ap.add_argument("--no-routed", action="store_true", help="skip the learned-router form")
-    ap.add_argument("--only", choices=["cosine", "edistance", "precision", "batched", "routed"],
+    ap.add_argument("--only", choices=["cosine", "edistance", "large_k", "precision", "batched", "routed"],
                     help="run one form alone and print its record (no benchmark line)")
     ap.add_argument("--routed-n", type=int, default=5_000_000)
     ap.add_argument("--routed-train", type=int, default=1_000_000)
@@ -570,7 +618,7 @@ def main() -> int:
         return 0
     if args.only:
         fn = {"precision": precision_forms, "batched": batched_form, "routed": routed_form,
-              "edistance": edistance_form}[args.only]
+              "edistance": edistance_form, "large_k": large_k_form}[args.only]
         print(json.dumps({args.only: fn(args, rsc)}), flush=True)
         return 0
 

@@ -93,8 +93,11 @@ typedef enum { RSC_EUCLIDEAN = 0, RSC_COSINE = 1 } rsc_metric;
  *              The reduced-precision forms keep the 64 smallest screened keys
  *              per query and re-rank them with float64 distances; they are
  *              approximate (no certificate): judge them by recall@k.
- *   screen     candidates kept per query: 32 or 64 for RSC_FP32 (must exceed
- *              k), 64 for the reduced-precision forms; 0 = default.
+ *   screen     candidates kept per query and reference range: 32 or 64 for
+ *              RSC_FP32 (must exceed k when k < 64; 64 for larger k, where
+ *              the references are split into about k / 32 ranges so that
+ *              every range's list keeps spare room), 64 for the
+ *              reduced-precision forms; 0 = default.
  *   metric     rsc_metric (0 = Euclidean).  The exactness guarantee of
  *              RSC_FP32 holds for both metrics.
  */
@@ -119,7 +122,9 @@ size_t rsc_knn_workspace_bytes(int64_t n_query, int64_t n_ref, int32_t d, int32_
 /*
  * k nearest neighbours of every row of X among the rows of X.
  *   X         device, n x d float32 embedding (cells x components).
- *   n, d, k   1 <= k <= n <= 2^31-1, 1 <= d <= 128, k <= 63.
+ *   n, d, k   1 <= k <= n <= 2^31-1; the exact (FP32-screened) path takes
+ *             1 <= d <= 256 and k <= 255, the reduced-precision screens
+ *             d <= 128 and k <= 63.
  *   out_idx   device, n x k int32: row i lists i itself in column 0, then
  *             the k-1 nearest other rows ordered by (distance, index).
  *   out_dist  device, n x k float32 Euclidean distances (column 0 is 0),
@@ -142,7 +147,7 @@ int rsc_knn_opt(const float *X, int64_t n, int32_t d, int32_t k, const rsc_knn_o
  * Rectangular form: k nearest rows of R for every row of Q (no self
  * column: all k slots come from R, ordered by (distance, index)).
  *   Q  device n_query x d float32;  R  device n_ref x d float32.
- *   1 <= k <= n_ref, k <= 63.  opts may be NULL.
+ *   1 <= k <= n_ref; d and k limits as for rsc_knn.  opts may be NULL.
  */
 int rsc_knn_ex(const float *Q, int64_t n_query, const float *R, int64_t n_ref, int32_t d, int32_t k,
                const rsc_knn_opts *opts, int32_t *out_idx, float *out_dist, void *workspace, size_t workspace_bytes,
@@ -200,8 +205,9 @@ size_t rsc_connectivities_workspace_bytes(int64_t n, int32_t k);
 
 /*
  * Connectivities of a kNN result in the layout rsc_knn produces.
- *   idx, dist   device n x k (int32, float32); column 0 is the row itself
- *               and is ignored; columns 1..k-1 are distinct rows != i.
+ *   idx, dist   device n x k (int32, float32), 1 <= k <= 256; column 0 is
+ *               the row itself and is ignored; columns 1..k-1 are distinct
+ *               rows != i.
  *   rho, sigma  device float64 n, or NULL: per row, rho = smallest strictly
  *               positive neighbour distance (0 if none), sigma solves
  *               sum_{j=1..k-1} exp(-max(0, d_ij - rho)/sigma) = log2 k

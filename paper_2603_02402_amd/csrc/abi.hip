@@ -239,8 +239,8 @@ int rsc_connectivities(const int32_t *idx, const float *dist, int64_t n, int32_t
         set_error("n above 2^31-2 cannot be indexed by int32");
         return RSC_ERR_OVERFLOW;
     }
-    if (k > 65) {
-        set_error("k > 65 is not supported by this build");
+    if (k > 256) {
+        set_error("k > 256 is not supported by this build");
         return RSC_ERR_UNSUPPORTED;
     }
     if (!idx || !dist || !indptr || !nnz || (k > 1 && (!indices || !data))) {

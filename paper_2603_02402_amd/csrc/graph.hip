@@ -140,6 +140,67 @@ __global__ __launch_bounds__(256) void k_smooth(const float *__restrict__ dist, 
     if (sigma_out) sigma_out[i] = sigma;
 }
 
+// The same computation for rows with more than 64 neighbour slots: the
+// distances are read from memory (in slot order, as above) instead of being
+// held in registers.
+__device__ __forceinline__ double membership_sum_mem(const float *dr, int m, double rho, double sigma) {
+    double s = 0.0;
+    for (int j = 0; j < m; ++j) {
+        double g = (double)dr[j] - rho;
+        if (g < 0.0) g = 0.0;
+        s = __dadd_rn(s, exp(-g / sigma));
+    }
+    return s;
+}
+
+__global__ __launch_bounds__(256) void k_smooth_wide(const float *__restrict__ dist, int64_t n, int k,
+                                                     double *__restrict__ a, double *__restrict__ rho_out,
+                                                     double *__restrict__ sigma_out, GraphResult *__restrict__ res) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int m = k - 1;
+    const float *dr = dist + i * k + 1;
+    double rho = 0.0;
+    for (int j = 0; j < m; ++j) {
+        const double v = (double)dr[j];
+        if (v > 0.0 && (rho == 0.0 || v < rho)) rho = v;
+    }
+    int at_rho = 0;
+    for (int j = 0; j < m; ++j)
+        if ((double)dr[j] <= rho) ++at_rho;
+    const double target = log2((double)k);
+    double sigma;
+    double *ai = a + i * m;
+    if ((double)at_rho >= target) {
+        sigma = 0.0;
+        for (int j = 0; j < m; ++j) ai[j] = (double)dr[j] <= rho ? 1.0 : 0.0;
+        atomicAdd(&res->degenerate, 1);
+    } else {
+        sigma = 1.0;
+        double lo = 0.0, hi = INFINITY;
+        for (int it = 0; it < 200; ++it) {
+            const double f = membership_sum_mem(dr, m, rho, sigma);
+            if (fabs(f - target) <= 1e-12 * target) break;
+            if (f > target)
+                hi = sigma;
+            else
+                lo = sigma;
+            if (isinf(hi))
+                sigma = sigma * 2.0;
+            else
+                sigma = (lo + hi) / 2.0;
+            if (!isinf(hi) && hi - lo <= ldexp(hi, -52)) break;
+        }
+        for (int j = 0; j < m; ++j) {
+            double g = (double)dr[j] - rho;
+            if (g < 0.0) g = 0.0;
+            ai[j] = exp(-g / sigma);
+        }
+    }
+    if (rho_out) rho_out[i] = rho;
+    if (sigma_out) sigma_out[i] = sigma;
+}
+
 // Union weight of each directed edge and the row lengths.
 __global__ __launch_bounds__(256) void k_union_count(const int32_t *__restrict__ idx, const double *__restrict__ a,
                                                      int64_t n, int k, float *__restrict__ wf,
@@ -380,8 +441,10 @@ int graph_run(const int32_t *idx, const float *dist, int64_t n, int k, int64_t *
             hipLaunchKernelGGL((k_smooth<16>), dim3(g), dim3(256), 0, stream, dist, n, k, w.a, rho, sigma, w.res);
         else if (m <= 32)
             hipLaunchKernelGGL((k_smooth<32>), dim3(g), dim3(256), 0, stream, dist, n, k, w.a, rho, sigma, w.res);
-        else
+        else if (m <= 64)
             hipLaunchKernelGGL((k_smooth<64>), dim3(g), dim3(256), 0, stream, dist, n, k, w.a, rho, sigma, w.res);
+        else
+            hipLaunchKernelGGL(k_smooth_wide, dim3(g), dim3(256), 0, stream, dist, n, k, w.a, rho, sigma, w.res);
         if ((st = launch_status("smooth_knn")) != RSC_OK) return st;
     } else {
         // k == 1: no neighbours; rho = sigma = 0 (no positive root exists)

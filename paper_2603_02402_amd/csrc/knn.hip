@@ -50,24 +50,29 @@ namespace {
 
 using namespace scr;
 
-constexpr int kMaxD = 128;
-constexpr int kMaxK = 63;
-constexpr int kRescanMax = 64;      // list capacity of the exhaustive rescan
+constexpr int kMaxD = 256;       // exact FP32 path (reduced-precision screens: 128)
+constexpr int kMaxK = 255;       // exact FP32 path (reduced-precision screens: 63)
+constexpr int kMaxDLowp = 128;
+constexpr int kMaxKLowp = 63;
 constexpr int kEscalateCap = 8192;  // rows handled by the escalation screen
 constexpr int kEscalateSplits = 16;
 constexpr int kEscalateWidth = 64;
 
 // Squared norms of the reference rows (float64 sum, rounded once) and the
-// largest norm.  One wave per 64 rows: the rows (contiguous in memory) are
-// copied into LDS with coalesced loads, then lane i sums row i.
+// largest norm.  One wave per block of norm_rows(d) rows (64 for d <= 128):
+// the rows (contiguous in memory) are copied into LDS with coalesced loads,
+// then lane i sums row i.
 constexpr int kNormRows = 64;
+constexpr int kNormBuf = kNormRows * 128;  // floats staged per block
+__host__ __device__ inline int norm_rows(int d) { return d <= 128 ? kNormRows : kNormBuf / d; }
 
 __global__ __launch_bounds__(64) void k_norms(const float *__restrict__ R, int64_t nr, int d,
                                               float *__restrict__ nrow, uint32_t *__restrict__ max_norm_bits) {
-    __shared__ float buf[kNormRows * kMaxD];
+    __shared__ float buf[kNormBuf];
     const int lane = threadIdx.x;
-    const int64_t r0 = (int64_t)blockIdx.x * kNormRows;
-    const int rows = (int)min<int64_t>(kNormRows, nr - r0);
+    const int nrb = norm_rows(d);
+    const int64_t r0 = (int64_t)blockIdx.x * nrb;
+    const int rows = (int)min<int64_t>(nrb, nr - r0);
     const float *src = R + r0 * d;
     for (int e = lane; e < rows * d; e += kWave) buf[e] = src[e];
     __syncthreads();
@@ -92,10 +97,11 @@ __global__ __launch_bounds__(64) void k_norms(const float *__restrict__ R, int64
 // loads and stores are coalesced.
 __global__ __launch_bounds__(64) void k_normalize(const float *__restrict__ X, int64_t n, int d,
                                                   float *__restrict__ out) {
-    __shared__ float buf[kNormRows * kMaxD];
+    __shared__ float buf[kNormBuf];
     const int lane = threadIdx.x;
-    const int64_t r0 = (int64_t)blockIdx.x * kNormRows;
-    const int rows = (int)min<int64_t>(kNormRows, n - r0);
+    const int nrb = norm_rows(d);
+    const int64_t r0 = (int64_t)blockIdx.x * nrb;
+    const int rows = (int)min<int64_t>(nrb, n - r0);
     for (int e = lane; e < rows * d; e += kWave) buf[e] = X[r0 * d + e];
     __syncthreads();
     if (lane < rows) {
@@ -242,28 +248,73 @@ __device__ __forceinline__ void bitonic_sort64(double &d2, int &jj, int lane) {
     }
 }
 
-// Merge a sorted 64-list (d2, jj) into the running sorted list (rd, rj): keep
-// the 64 smallest, sorted.
-__device__ __forceinline__ void merge_sorted64(double &rd, int &rj, double d2, int jj, int lane) {
-    const double od = __shfl(d2, kWave - 1 - lane, kWave);
-    const int oj = __shfl(jj, kWave - 1 - lane, kWave);
-    if (lex_before(od, oj, rd, rj)) {
-        rd = od;
-        rj = oj;
-    }
-    // (rd, rj) is now bitonic; sort it ascending
+// Sort a bitonic 64-sequence (d2, jj) ascending in (d, j) order.
+__device__ __forceinline__ void bitonic_clean64(double &d2, int &jj, int lane) {
 #pragma unroll
     for (int stride = kWave >> 1; stride > 0; stride >>= 1) {
-        const double xd = __shfl_xor(rd, stride, kWave);
-        const int xj = __shfl_xor(rj, stride, kWave);
+        const double xd = __shfl_xor(d2, stride, kWave);
+        const int xj = __shfl_xor(jj, stride, kWave);
         const bool lower = (lane & stride) == 0;
-        const bool other_first = lex_before(xd, xj, rd, rj);
+        const bool other_first = lex_before(xd, xj, d2, jj);
         if (lower == other_first) {
-            rd = xd;
-            rj = xj;
+            d2 = xd;
+            jj = xj;
         }
     }
 }
+
+// The m smallest (d, j) seen so far, m <= 64 R, sorted across the wave:
+// position p = 64 r + lane lives in register r of that lane (+inf / INT_MAX
+// where fewer were seen).  A sorted 64-chunk is merged register by register:
+// the 64 smallest of (register r, carry) stay in r, the rest carry on.
+template <int R>
+struct TopM {
+    double d[R];
+    int j[R];
+
+    __device__ __forceinline__ void init() {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            d[r] = INFINITY;
+            j[r] = INT_MAX;
+        }
+    }
+    // (d, j) at position p (p wave-uniform)
+    __device__ __forceinline__ void at(int p, double &pd, int &pj) const {
+        double rd = d[0];
+        int rj = j[0];
+#pragma unroll
+        for (int r = 1; r < R; ++r)
+            if (p >> 6 == r) {
+                rd = d[r];
+                rj = j[r];
+            }
+        pd = __shfl(rd, p & (kWave - 1), kWave);
+        pj = __shfl(rj, p & (kWave - 1), kWave);
+    }
+    // merge a sorted chunk (cd, cj), lane i = i-th smallest
+    __device__ __forceinline__ void merge(double cd, int cj, int lane) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double od = __shfl(cd, kWave - 1 - lane, kWave);
+            const int oj = __shfl(cj, kWave - 1 - lane, kWave);
+            const bool take = lex_before(od, oj, d[r], j[r]);
+            const double hd = take ? d[r] : od;
+            const int hj = take ? j[r] : oj;
+            if (take) {
+                d[r] = od;
+                j[r] = oj;
+            }
+            bitonic_clean64(d[r], j[r], lane);
+            if (r + 1 < R) {
+                cd = hd;
+                cj = hj;
+                if (__ballot(cd < INFINITY) == 0ull) break;  // nothing left to carry
+                bitonic_clean64(cd, cj, lane);
+            }
+        }
+    }
+};
 
 // Candidate rows are staged through LDS 32 dimensions at a time: for each
 // batch of 64 candidates (one per lane) the wave copies the rows' chunk with
@@ -272,6 +323,7 @@ __device__ __forceinline__ void merge_sorted64(double &rd, int &rj, double d2, i
 // distances are those of exact_d2 bit for bit.
 constexpr int kRerankChunk = 32;
 
+template <int R>
 __global__ __launch_bounds__(256) void k_rerank(RerankArgs a) {
     __shared__ float tile[4][kWave][kRerankChunk + 1];
     __shared__ float qrow[4][kMaxD];
@@ -321,8 +373,8 @@ __global__ __launch_bounds__(256) void k_rerank(RerankArgs a) {
         if (full) tau = fminf(tau, root);
     }
 
-    double rd = INFINITY;
-    int rj = INT_MAX;
+    TopM<R> top;
+    top.init();
     float ratio = 0.f;
     const int total = a.P * a.S;
     for (int c0 = 0; c0 < total; c0 += kWave) {
@@ -382,12 +434,7 @@ __global__ __launch_bounds__(256) void k_rerank(RerankArgs a) {
             }
         }
         bitonic_sort64(d2, jj, lane);
-        if (c0 == 0) {
-            rd = d2;
-            rj = jj;
-        } else {
-            merge_sorted64(rd, rj, d2, jj, lane);
-        }
+        top.merge(d2, jj, lane);
     }
     ratio = wave_max(ratio);
     if (lane == 0 && ratio > 0.f) atomicMax(&a.counters->max_ratio_bits, __float_as_uint(ratio));
@@ -399,7 +446,9 @@ __global__ __launch_bounds__(256) void k_rerank(RerankArgs a) {
         // the key is 2 D_y - 1 up to cosine_eps, so D_y >= (tau + 1 - eps) / 2,
         // which must exceed D_m.  (A zero row's key may be far from its
         // D_y = 1 but never above it: the bound still holds for it.)
-        const double dm = __shfl(rd, m - 1, kWave);
+        double dm;
+        int jm;
+        top.at(m - 1, dm, jm);
         const double bound = ((double)tau + 1.0 - a.cosine_eps) * 0.5 - 1e-13;
         ok = dm < bound;
     } else if (a.certify && m > 0 && tau < INFINITY) {
@@ -407,7 +456,9 @@ __global__ __launch_bounds__(256) void k_rerank(RerankArgs a) {
         // ||x|| + D_m it lies farther than D_m (triangle inequality); else its
         // float32 key is off by at most eps(Y), so its true key is >= tau -
         // eps(Y), which must exceed D_m^2 - ||x||^2.
-        const double dm = __shfl(rd, m - 1, kWave);
+        double dm;
+        int jm;
+        top.at(m - 1, dm, jm);
         const double Y = fmin(ymax, (xn + sqrt(dm)) * (1.0 + 1e-9));
         const double eps = a.eps_coef * (2.0 * xn * Y + Y * Y);
         const double bound = (double)tau + xx - eps - 1e-12 * (fabs((double)tau) + xx);
@@ -421,9 +472,13 @@ __global__ __launch_bounds__(256) void k_rerank(RerankArgs a) {
         oi[0] = (int32_t)row;
         od[0] = 0.f;
     }
-    if (lane < m) {
-        oi[off + lane] = rj == INT_MAX ? -1 : rj;
-        od[off + lane] = cosine ? (float)rd : (float)sqrt(rd);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int pos = r * kWave + lane;
+        if (pos < m) {
+            oi[off + pos] = top.j[r] == INT_MAX ? -1 : top.j[r];
+            od[off + pos] = cosine ? (float)top.d[r] : (float)sqrt(top.d[r]);
+        }
     }
     if (!ok && lane == 0) {
         const int pos = atomicAdd(a.flag_count, 1);
@@ -433,19 +488,19 @@ __global__ __launch_bounds__(256) void k_rerank(RerankArgs a) {
 
 // ---------------------------------------------------------------------------
 // Exhaustive float64 scan of the rows no screen could certify: rows
-// list2[0..count2) and list1[cap..count1).  One wave per row; each lane keeps
-// a sorted list of its m best in LDS; the lists are merged by m rounds of a
-// wave-wide lexicographic minimum.
+// list2[0..count2) and list1[cap..count1).  One wave per row: each step the
+// 64 lanes compute the distances of 64 consecutive references; a step with
+// a distance before the current m-th is sorted and merged into the row's
+// wave-wide top-m (TopM).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_rescan(const float *__restrict__ Q, const float *__restrict__ R, int64_t nr,
+template <int R>
+__global__ __launch_bounds__(64) void k_rescan(const float *__restrict__ Q, const float *__restrict__ Rf, int64_t nr,
                                                int d, int k, int self_mode, const int32_t *__restrict__ list1,
                                                const int32_t *__restrict__ count1, int cap1,
                                                const int32_t *__restrict__ list2,
                                                const int32_t *__restrict__ count2, int32_t *__restrict__ out_idx,
                                                float *__restrict__ out_dist, KnnCounters *__restrict__ counters,
                                                const int64_t *__restrict__ soff, int nsamples, int metric) {
-    __shared__ double ld[kRescanMax * kWave];
-    __shared__ int lj[kRescanMax * kWave];
     const int lane = threadIdx.x;
     const int m = self_mode ? k - 1 : k;
     const int c2 = *count2;
@@ -466,40 +521,39 @@ __global__ __launch_bounds__(64) void k_rescan(const float *__restrict__ Q, cons
             j0 = soff[lo];
             j1 = soff[lo + 1];
         }
-        for (int s = 0; s < m; ++s) {
-            ld[s * kWave + lane] = INFINITY;
-            lj[s * kWave + lane] = INT_MAX;
-        }
         double cxx = 0.0;  // cosine: the query's squared norm, dimensions in order
         if (metric == RSC_COSINE)
             for (int t = 0; t < d; ++t) cxx = __dadd_rn(cxx, __dmul_rn((double)x[t], (double)x[t]));
-        for (int64_t j = j0 + lane; j < j1; j += kWave) {
-            if (self_mode && j == q) continue;
-            double v;
-            if (metric == RSC_COSINE) {
-                const float *y = R + j * d;
-                double sxy = 0.0, syy = 0.0;
-                for (int t = 0; t < d; ++t) {
-                    sxy = __dadd_rn(sxy, __dmul_rn((double)x[t], (double)y[t]));
-                    syy = __dadd_rn(syy, __dmul_rn((double)y[t], (double)y[t]));
+        TopM<R> top;
+        top.init();
+        for (int64_t jb = j0; jb < j1; jb += kWave) {
+            const int64_t j = jb + lane;
+            double v = INFINITY;
+            int jj = INT_MAX;
+            if (j < j1 && !(self_mode && j == q)) {
+                const float *y = Rf + j * d;
+                if (metric == RSC_COSINE) {
+                    double sxy = 0.0, syy = 0.0;
+                    for (int t = 0; t < d; ++t) {
+                        sxy = __dadd_rn(sxy, __dmul_rn((double)x[t], (double)y[t]));
+                        syy = __dadd_rn(syy, __dmul_rn((double)y[t], (double)y[t]));
+                    }
+                    v = (cxx == 0.0 || syy == 0.0)
+                            ? 1.0
+                            : __dsub_rn(1.0, __ddiv_rn(sxy, __dmul_rn(__dsqrt_rn(cxx), __dsqrt_rn(syy))));
+                } else {
+                    v = exact_d2(x, y, d);
                 }
-                v = (cxx == 0.0 || syy == 0.0) ? 1.0
-                                               : __dsub_rn(1.0, __ddiv_rn(sxy, __dmul_rn(__dsqrt_rn(cxx), __dsqrt_rn(syy))));
-            } else {
-                v = exact_d2(x, R + j * d, d);
+                jj = (int)j;
             }
-            if (m > 0 && lex_before(v, (int)j, ld[(m - 1) * kWave + lane], lj[(m - 1) * kWave + lane])) {
-                int p = m - 1;
-                while (p > 0 && lex_before(v, (int)j, ld[(p - 1) * kWave + lane], lj[(p - 1) * kWave + lane])) {
-                    ld[p * kWave + lane] = ld[(p - 1) * kWave + lane];
-                    lj[p * kWave + lane] = lj[(p - 1) * kWave + lane];
-                    --p;
-                }
-                ld[p * kWave + lane] = v;
-                lj[p * kWave + lane] = (int)j;
-            }
+            if (m < 1) continue;
+            double md;
+            int mj;
+            top.at(m - 1, md, mj);
+            if (__ballot(lex_before(v, jj, md, mj)) == 0ull) continue;
+            bitonic_sort64(v, jj, lane);
+            top.merge(v, jj, lane);
         }
-        int head = 0;
         int32_t *oi = out_idx + q * k;
         float *od = out_dist + q * k;
         const int off = self_mode ? 1 : 0;
@@ -507,28 +561,19 @@ __global__ __launch_bounds__(64) void k_rescan(const float *__restrict__ Q, cons
             oi[0] = (int32_t)q;
             od[0] = 0.f;
         }
-        for (int s = 0; s < m; ++s) {
-            double bd = head < m ? ld[head * kWave + lane] : INFINITY;
-            int bj = head < m ? lj[head * kWave + lane] : INT_MAX;
-            int owner = lane;
-            for (int o = 32; o > 0; o >>= 1) {
-                const double od2 = __shfl_xor(bd, o, kWave);
-                const int oj = __shfl_xor(bj, o, kWave);
-                const int oo = __shfl_xor(owner, o, kWave);
-                if (lex_before(od2, oj, bd, bj)) {
-                    bd = od2;
-                    bj = oj;
-                    owner = oo;
-                }
-            }
-            if (lane == owner) ++head;
-            if (lane == 0) {
-                oi[off + s] = bj == INT_MAX ? -1 : bj;
-                od[off + s] = metric == RSC_COSINE ? (float)bd : (float)sqrt(bd);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int pos = r * kWave + lane;
+            if (pos < m) {
+                oi[off + pos] = top.j[r] == INT_MAX ? -1 : top.j[r];
+                od[off + pos] = metric == RSC_COSINE ? (float)top.d[r] : (float)sqrt(top.d[r]);
             }
         }
     }
 }
+
+// Registers per lane of the running top-m list.
+int topm_regs(int m) { return m <= 64 ? 1 : m <= 128 ? 2 : 4; }
 
 template <int DH, int L>
 int launch_screen(const ScreenArgs &a, unsigned gx, const char *name, hipStream_t stream) {
@@ -547,6 +592,8 @@ int dispatch_screen(int dh, const ScreenArgs &a, unsigned gx, const char *name, 
         case 32: return launch_screen<32, L>(a, gx, name, s);
         case 48: return launch_screen<48, L>(a, gx, name, s);
         case 64: return launch_screen<64, L>(a, gx, name, s);
+        case 96: return launch_screen<96, L>(a, gx, name, s);
+        case 128: return launch_screen<128, L>(a, gx, name, s);
         default: set_error("internal: no screen kernel for this dimension"); return RSC_ERR_UNSUPPORTED;
     }
 }
@@ -561,7 +608,7 @@ constexpr int kQueriesPerGroup = kScreenWaves * 32;
 
 int pick_dh(int d) {
     const int half = (d + 1) / 2;
-    const int opts[] = {4, 8, 16, 25, 32, 48, 64};
+    const int opts[] = {4, 8, 16, 25, 32, 48, 64, 96, 128};
     for (int o : opts)
         if (half <= o) return o;
     return -1;
@@ -590,7 +637,7 @@ int knn_prep_fp32(const KnnPlan &p, const float *R, const KnnBuffers &b, const i
     const int s4 = packed_s4(p.dh);
     ScopedTimer timer("prep_pack", stream);
     hipLaunchKernelGGL(k_init_counters, dim3(1), dim3(64), 0, stream, b.counters);
-    hipLaunchKernelGGL(k_norms, dim3((unsigned)((p.nr + kNormRows - 1) / kNormRows)), dim3(kNormRows), 0, stream, R,
+    hipLaunchKernelGGL(k_norms, dim3((unsigned)((p.nr + norm_rows(p.d) - 1) / norm_rows(p.d))), dim3(kNormRows), 0, stream, R,
                        p.nr, p.d, b.nrow,
                        &b.counters->max_norm_bits);
     const int64_t tot = p.nblk * s4 * kWave;
@@ -603,7 +650,7 @@ int knn_prep_fp32(const KnnPlan &p, const float *R, const KnnBuffers &b, const i
 
 int knn_norms(const float *R, int64_t nr, int d, float *nrow, KnnCounters *counters, hipStream_t stream) {
     hipLaunchKernelGGL(k_init_counters, dim3(1), dim3(64), 0, stream, counters);
-    hipLaunchKernelGGL(k_norms, dim3((unsigned)((nr + kNormRows - 1) / kNormRows)), dim3(kNormRows), 0, stream, R, nr,
+    hipLaunchKernelGGL(k_norms, dim3((unsigned)((nr + norm_rows(d) - 1) / norm_rows(d))), dim3(kNormRows), 0, stream, R, nr,
                        d, nrow,
                        &counters->max_norm_bits);
     return launch_status("norms");
@@ -629,16 +676,28 @@ int knn_launch_screen(int dh, const scr::ScreenArgs &a, unsigned gx, int half_wi
 
 int knn_launch_rerank(const RerankArgs &ra, int64_t slots, const char *name, hipStream_t stream) {
     ScopedTimer timer(name, stream);
-    hipLaunchKernelGGL(k_rerank, dim3((unsigned)((slots + 3) / 4)), dim3(256), 0, stream, ra);
+    const dim3 grid((unsigned)((slots + 3) / 4));
+    switch (topm_regs(ra.self_mode ? ra.k - 1 : ra.k)) {
+        case 1: hipLaunchKernelGGL(k_rerank<1>, grid, dim3(256), 0, stream, ra); break;
+        case 2: hipLaunchKernelGGL(k_rerank<2>, grid, dim3(256), 0, stream, ra); break;
+        default: hipLaunchKernelGGL(k_rerank<4>, grid, dim3(256), 0, stream, ra); break;
+    }
     return launch_status(name);
 }
 
 int knn_launch_rescan(const KnnPlan &p, const float *Q, const float *R, const KnnBuffers &b, int esc_cap,
                       int32_t *out_idx, float *out_dist, const int64_t *soff, int nsamples, hipStream_t stream) {
     ScopedTimer timer("rescan", stream);
-    hipLaunchKernelGGL(k_rescan, dim3(1024), dim3(64), 0, stream, Q, R, p.nr, p.d, p.k, p.self_mode ? 1 : 0, b.flag1,
-                       &b.counters->flagged, esc_cap, b.flag2, &b.counters->flagged2, out_idx, out_dist, b.counters,
-                       soff, nsamples, p.metric);
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(1024), dim3(64), 0, stream, Q, R, p.nr, p.d, p.k, p.self_mode ? 1 : 0, b.flag1,
+                           &b.counters->flagged, esc_cap, b.flag2, &b.counters->flagged2, out_idx, out_dist,
+                           b.counters, soff, nsamples, p.metric);
+    };
+    switch (topm_regs(p.self_mode ? p.k - 1 : p.k)) {
+        case 1: go(k_rescan<1>); break;
+        case 2: go(k_rescan<2>); break;
+        default: go(k_rescan<4>); break;
+    }
     return launch_status("rescan");
 }
 
@@ -656,14 +715,18 @@ int knn_plan(int64_t nq, int64_t nr, int d, int k, const rsc_knn_opts *opts, boo
         return RSC_ERR_INVALID_ARG;
     }
     if (d > kMaxD) {
-        set_error("d > 128 is not supported by this build");
+        set_error("d > 256 is not supported by this build");
         return RSC_ERR_UNSUPPORTED;
     }
     if (k > kMaxK) {
-        set_error("k > 63 is not supported by this build");
+        set_error("k > 255 is not supported by this build");
         return RSC_ERR_UNSUPPORTED;
     }
     int precision = opts ? opts->precision : RSC_FP32;
+    if (precision != RSC_FP32 && (d > kMaxDLowp || k > kMaxKLowp)) {
+        set_error("reduced-precision screens support d <= 128 and k <= 63");
+        return RSC_ERR_UNSUPPORTED;
+    }
     int screen_w = opts ? opts->screen : 0;
     const int metric = opts ? opts->metric : RSC_EUCLIDEAN;
     if (metric != RSC_EUCLIDEAN && metric != RSC_COSINE) {
@@ -676,8 +739,8 @@ int knn_plan(int64_t nq, int64_t nr, int d, int k, const rsc_knn_opts *opts, boo
     }
     if (precision == RSC_FP32) {
         if (screen_w == 0) screen_w = k <= 16 ? 32 : 64;
-        if (screen_w <= k || (screen_w != 32 && screen_w != 64)) {
-            set_error("screen width must be 32 or 64 and larger than k");
+        if ((screen_w != 32 && screen_w != 64) || (k < 64 && screen_w <= k) || (k >= 64 && screen_w != 64)) {
+            set_error("screen width must be 32 or 64 and larger than k (64 for k >= 64)");
             return RSC_ERR_INVALID_ARG;
         }
     } else {
@@ -700,6 +763,11 @@ int knn_plan(int64_t nq, int64_t nr, int d, int k, const rsc_knn_opts *opts, boo
     plan->metric = metric;
     plan->splits = pick_splits(nq, plan->nblk,
                                precision == RSC_FP32 ? kQueriesPerGroup : lowp_queries_per_group(precision, d));
+    if (precision == RSC_FP32) {
+        // enough (range, half) lists that the m nearest fill each to about half
+        const int m = self_mode ? k - 1 : k;
+        plan->splits = std::min(32, std::max(plan->splits, (m + plan->half - 1) / plan->half));
+    }
     return RSC_OK;
 }
 
@@ -737,10 +805,10 @@ size_t knn_workspace(const KnnPlan &p, void *ws, KnnBuffers *out) {
 // Cosine metric: the screen's inputs are the unit-normalised rows.
 int normalize_inputs(const KnnPlan &p, const float *Q, const float *R, const KnnBuffers &b, hipStream_t stream) {
     ScopedTimer timer("normalize", stream);
-    hipLaunchKernelGGL(k_normalize, dim3((unsigned)((p.nr + kNormRows - 1) / kNormRows)), dim3(kNormRows), 0, stream,
+    hipLaunchKernelGGL(k_normalize, dim3((unsigned)((p.nr + norm_rows(p.d) - 1) / norm_rows(p.d))), dim3(kNormRows), 0, stream,
                        R, p.nr, p.d, b.rn);
     if (!p.self_mode && p.nq > 0)
-        hipLaunchKernelGGL(k_normalize, dim3((unsigned)((p.nq + kNormRows - 1) / kNormRows)), dim3(kNormRows), 0,
+        hipLaunchKernelGGL(k_normalize, dim3((unsigned)((p.nq + norm_rows(p.d) - 1) / norm_rows(p.d))), dim3(kNormRows), 0,
                            stream, Q, p.nq, p.d, b.qn);
     return launch_status("normalize");
 }

@@ -15,7 +15,9 @@ __host__ __device__ constexpr int packed_s4(int DH) { return (DH + (norm_folded(
 
 // Occupancy target (waves per SIMD) that the register budget of a screen
 // instantiation allows without spilling.
-__host__ __device__ constexpr int screen_min_waves(int DH, int L) { return (DH <= 25 && L == 16) ? 3 : 2; }
+__host__ __device__ constexpr int screen_min_waves(int DH, int L) {
+    return (DH <= 25 && L == 16) ? 3 : DH <= 64 ? 2 : 1;
+}
 
 // Load float4 group s4 of a packed block (wave-uniform base wb).  A partial
 // last group (STEPS not a multiple of 4) is fetched with a narrower load so

@@ -77,14 +77,26 @@ def _err(lib):
     return lib.rsc_last_error().decode()
 
 
+def _lib_mod():
+    from paper_2603_02402_amd import _lib
+
+    return _lib
+
+
 def test_knn_validation(lib):
     assert _knn(lib, k=0) == -1
     assert _knn(lib, k=101) == -1
     assert _knn(lib, d=0) == -1
     assert _knn(lib, n=0) == -1
     assert _knn(lib, n=2**31) == -5 and "int32" in _err(lib)
-    assert _knn(lib, d=129) == -6
-    assert _knn(lib, k=64) == -6
+    assert _knn(lib, d=257) == -6 and "256" in _err(lib)
+    assert _knn(lib, k=256, n=1000) == -6 and "255" in _err(lib)
+    # the reduced-precision screens stay at d <= 128, k <= 63
+    bf = _lib_mod().KnnOpts(1, 0, 0, 0)
+    assert lib.rsc_knn_opt(FAKE, 1000, 129, 15, ctypes.byref(bf), FAKE, FAKE, FAKE, 1 << 30, None) == -6
+    assert lib.rsc_knn_opt(FAKE, 1000, 50, 64, ctypes.byref(bf), FAKE, FAKE, FAKE, 1 << 30, None) == -6
+    # large k and d are sized on the exact path
+    assert lib.rsc_knn_workspace_bytes(1000, 1000, 256, 255, None) > 0
     assert _knn(lib, X=None) == -1
     assert _knn(lib, idx=None) == -1
     assert _knn(lib, X=ctypes.c_void_p(0x10002)) == -1 and "aligned" in _err(lib)

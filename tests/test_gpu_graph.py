@@ -140,3 +140,10 @@ def test_graph_deterministic(rsc):
     b = gpu_conn(rsc, idx, dist)
     for x, y in zip(a, b):
         np.testing.assert_array_equal(x.view(np.uint8), y.view(np.uint8))
+
+
+@pytest.mark.parametrize("n,k", [(3000, 66), (2000, 100), (1500, 256)])
+def test_large_k_lists(rsc, oracle_mod, n, k):
+    """Rows with more than 64 neighbour slots (smooth kNN from memory)."""
+    idx, dist = synth.random_knn_lists(n, k, seed=n + k)
+    check_conn_on_lists(rsc, oracle_mod, idx, dist, f"synthetic lists k={k}")

@@ -147,3 +147,53 @@ def test_plain_1m_sampled_parity(rsc, oracle_mod):
     s = np.sort(idx_all, axis=1)
     assert not (s[:, 1:] == s[:, :-1]).any()
     assert ((idx_all >= 0) & (idx_all < X.shape[0])).all()
+
+
+# ---------------------------------------------------------------------------
+# Larger k and d (exact path): the running top-m spans 1, 2 or 4 registers per
+# lane (m <= 64, 128, 256), the main screen splits the references into about
+# k / 32 ranges, and the exhaustive rescan uses the same top-m lists.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,d,k", [
+    (3000, 50, 65), (3000, 50, 66), (2500, 50, 100), (2000, 30, 128), (2000, 30, 129), (1500, 20, 255),
+    (1500, 129, 15), (1200, 200, 40), (1100, 256, 64), (900, 256, 200),
+])
+def test_large_k_and_d(rsc, oracle_mod, n, d, k):
+    X = synth.mixture(n, d=d, n_clusters=6, seed=n + d + k)
+    check_full(rsc, oracle_mod, X, k, f"large k/d n={n} d={d} k={k}")
+
+
+def test_large_k_rescan_on_ties(rsc, oracle_mod):
+    """A lattice (every distance a multiple of the spacing) and injected
+    duplicates with k = 100: rows the screens cannot certify go to the
+    exhaustive float64 scan."""
+    X = synth.lattice_1d(1500, d=20, spacing=0.5)
+    idx_g, dist_g, st = gpu_knn(rsc, X, 100)
+    idx_o, _, dist_o = oracle_mod.knn(X, 100)
+    log(f"[knn parity] lattice k=100: stats {st}")
+    np.testing.assert_array_equal(idx_g, idx_o)
+    np.testing.assert_array_equal(dist_g, dist_o)
+    Y = synth.mixture(2000, d=50, n_clusters=4, seed=31)
+    Y[100:400] = Y[99]  # 301 identical rows: more than k
+    idx_g, dist_g, st = gpu_knn(rsc, Y, 150)
+    idx_o, _, dist_o = oracle_mod.knn(Y, 150)
+    log(f"[knn parity] duplicates k=150: stats {st}")
+    res = compare_knn(Y, np.arange(2000), idx_g, dist_g, idx_o, dist_o, oracle_mod, 150)
+    assert res["exact_rows"] + res["near_tie_rows"] == 2000
+
+
+def test_large_k_rectangular_and_cosine(rsc, oracle_mod):
+    R = synth.mixture(4000, d=64, n_clusters=10, seed=41)
+    Q = synth.mixture(300, d=64, n_clusters=10, seed=42)
+    for k in (64, 128, 200):
+        idx_g, dist_g, _ = gpu_knn(rsc, R, k, Q=Q)
+        idx_o, _, dist_o = oracle_mod.knn(R, k, Q=Q)
+        compare_knn(R, np.arange(len(Q)), idx_g, dist_g, idx_o, dist_o, oracle_mod, k, self_mode=False)
+    from tests.parity import cosine_pair_dist
+
+    X = synth.mixture(2500, d=50, n_clusters=8, seed=43)
+    idx_g, dist_g, _ = gpu_knn(rsc, X, 100, metric=rsc.RSC_COSINE)
+    idx_o, _, dist_o = oracle_mod.knn(X, 100, metric="cosine")
+    res = compare_knn(X, np.arange(2500), idx_g, dist_g, idx_o, dist_o, oracle_mod, 100, pair_dist=cosine_pair_dist)
+    assert res["exact_rows"] + res["near_tie_rows"] == 2500
