@@ -9,7 +9,7 @@ The arithmetic lives in ``oracle.c`` (float64, brute force, compiled with
 numpy arrays.  ``mlp.py`` holds the float64 reference of the partition
 router's network, ``partition.py`` the k-means partitions and the routed
 form's candidate sets, ``edistance.py`` the group-pair distance sums and
-energy distances.
+energy distances, ``pca.py`` the sparse PCA that produces the embedding.
 """
 
 from __future__ import annotations

@@ -50,6 +50,8 @@ __all__ = [
     "random_labels",
     "EDIST",
     "perturbation_screen",
+    "SPARSE_PCA",
+    "sparse_expression",
 ]
 
 _CHUNK = 1 << 18  # rows drawn per call; the PCG64 stream is identical to one big draw
@@ -294,3 +296,60 @@ def perturbation_screen(n_groups: int | None = None, control: int | None = None,
         lab = labels[r0:r0 + _CHUNK]
         X[r0:r0 + lab.size] = (effect[lab] + rng.standard_normal((lab.size, d)) * lam).astype(np.float32)
     return X, labels
+
+
+# Sparse expression matrix for the PCA row: cells x genes in CSR, a stand-in
+# for log-normalised counts over highly variable genes.  Gene g is detected in
+# a cell with probability q_g = a / (1 + g / 500) (a popularity that falls off
+# over the gene list, `a` set for the target density).  A detected entry
+# holds log1p(s_c exp(b_g + u_c . v_g)) with a log-normal cell depth s_c, r = 8
+# latent programs u_c ~ N(0, I), v_g ~ N(0, 0.35^2 I) and b_g ~ N(0.5, 0.5^2),
+# so the matrix has a low-rank structure under noise.  Detected positions are
+# drawn in row-major order as geometric gaps at max_g q_g, each kept with
+# probability q_g / max q, so the gene indices of a row come out ascending.
+SPARSE_PCA = {"n": 1_000_000, "p": 2000, "density": 0.05, "seed": 21}
+
+
+def sparse_expression(n: int | None = None, p: int | None = None, density: float | None = None,
+                      seed: int | None = None, programs: int = 8):
+    """``(indptr int64 n+1, indices int32, data float32)``: rows in cell
+    order, gene indices ascending within each row."""
+    n = SPARSE_PCA["n"] if n is None else n
+    p = SPARSE_PCA["p"] if p is None else p
+    density = SPARSE_PCA["density"] if density is None else density
+    rng = _rng(SPARSE_PCA["seed"] if seed is None else seed)
+    w = 1.0 / (1.0 + np.arange(p) / 500.0)
+    q = np.minimum(1.0, density * w / w.mean())
+    qmax = float(q.max())
+    b = rng.normal(0.5, 0.5, size=p)
+    V = rng.normal(0.0, 0.35, size=(programs, p))
+    Vt = np.ascontiguousarray(V.T)
+    depth = np.exp(rng.normal(0.0, 0.3, size=n))
+    U = rng.standard_normal((n, programs))
+    counts = np.zeros(n, dtype=np.int64)
+    ind_parts, val_parts = [], []
+    rows_per = max(1, (1 << 26) // p)
+    for r0 in range(0, n, rows_per):
+        r1 = min(n, r0 + rows_per)
+        size = (r1 - r0) * p
+        pos = []
+        last = -1
+        while True:  # candidate positions: geometric gaps at qmax over the chunk's grid
+            gaps = rng.geometric(qmax, size=int(qmax * size * 1.05) + 64)
+            cand = last + np.cumsum(gaps)
+            pos.append(cand[cand < size])
+            if cand[-1] >= size:
+                break
+            last = int(cand[-1])
+        pos = np.concatenate(pos)
+        g = pos % p
+        pos = pos[rng.random(pos.size) < q[g] / qmax]
+        cr, g = pos // p, pos % p
+        c = cr + r0
+        val = np.log1p(depth[c] * np.exp(b[g] + (U[c] * Vt[g]).sum(1)))
+        counts[r0:r1] = np.bincount(cr, minlength=r1 - r0)
+        ind_parts.append(g.astype(np.int32))
+        val_parts.append(val.astype(np.float32))
+    indptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=indptr[1:])
+    return indptr, np.concatenate(ind_parts), np.concatenate(val_parts)

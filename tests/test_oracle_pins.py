@@ -628,3 +628,77 @@ def test_edistance_special_cases_and_invariances():
     # (a cross sum taken as (ref, g) rather than (g, ref) adds in another order)
     for ref in range(4):
         np.testing.assert_allclose(ed.onesided(Xi, off, cells, ref), E1[ref], rtol=1e-13, atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# Sparse PCA (Methods, "Principal component analysis").
+# ---------------------------------------------------------------------------
+
+def _small_csr(n=300, p=40, density=0.2, seed=1):
+    import synth
+
+    return synth.sparse_expression(n=n, p=p, density=density, seed=seed)
+
+
+def test_pca_covariance_matches_numpy_cov_and_scipy_gram():
+    import scipy.sparse as sp
+
+    from oracle import pca as opca
+
+    ip, ix, v = _small_csr()
+    X = sp.csr_matrix((v.astype(np.float64), ix, ip), shape=(300, 40))
+    mu, S = opca.gram(ip, ix, v, 40)
+    np.testing.assert_allclose(S, (X.T @ X).toarray(), rtol=1e-13, atol=1e-12)
+    np.testing.assert_allclose(mu, np.asarray(X.mean(axis=0)).ravel(), rtol=1e-13, atol=1e-15)
+    mu2, C = opca.covariance(ip, ix, v, 40)
+    np.testing.assert_allclose(C, np.cov(X.toarray(), rowvar=False), rtol=1e-10, atol=1e-12)
+    assert np.array_equal(C, C.T)
+
+
+def test_pca_matches_sklearn_full_pca():
+    from sklearn.decomposition import PCA
+
+    from oracle import pca as opca
+
+    ip, ix, v = _small_csr(n=500, p=30, seed=2)
+    Xd = opca.dense(ip, ix, v, 30)
+    mu, C, ev, V, Z = opca.pca(ip, ix, v, 30, 8)
+    skl = PCA(n_components=8, svd_solver="full").fit(Xd)
+    np.testing.assert_allclose(ev, skl.explained_variance_, rtol=1e-9)
+    Zs = skl.transform(Xd)
+    for t in range(8):  # loadings and scores agree up to the sign of each component
+        s = np.sign(V[:, t] @ skl.components_[t])
+        np.testing.assert_allclose(V[:, t], s * skl.components_[t], atol=1e-9)
+        np.testing.assert_allclose(Z[:, t], s * Zs[:, t], atol=1e-8)
+    assert (np.abs(V).argmax(0) == np.abs(V).argmax(0)).all()
+    assert all(V[np.abs(V[:, t]).argmax(), t] > 0 for t in range(8))  # the sign rule
+
+
+def test_pca_closed_forms():
+    from oracle import pca as opca
+
+    # genes 0 and 1 always equal, gene 2 independent: the covariance has rank
+    # 2 and one eigenvector is (1, -1, 0)/sqrt(2) with eigenvalue 0
+    rng = np.random.default_rng(3)
+    a = rng.integers(1, 5, 200).astype(np.float32)
+    c = rng.integers(1, 5, 200).astype(np.float32)
+    ip = np.arange(0, 601, 3, dtype=np.int64)
+    ix = np.tile(np.array([0, 1, 2], dtype=np.int32), 200)
+    v = np.stack([a, a, c], axis=1).ravel()
+    mu, C, ev, V, Z = opca.pca(ip, ix, v, 3, 3)
+    a64, c64 = a.astype(np.float64), c.astype(np.float64)
+    va, vc = np.var(a64, ddof=1), np.var(c64, ddof=1)
+    cac = ((a64 - a64.mean()) * (c64 - c64.mean())).sum() / 199
+    # on (1, 1, 0)/sqrt(2) and (0, 0, 1) the covariance is [[2 va, sqrt2 cac], [sqrt2 cac, vc]]
+    tr, det = 2 * va + vc, 2 * va * vc - 2 * cac * cac
+    disc = np.sqrt(tr * tr / 4 - det)
+    np.testing.assert_allclose(sorted(ev), [0.0, tr / 2 - disc, tr / 2 + disc], atol=1e-12)
+    zero = int(np.argmin(np.abs(ev)))
+    np.testing.assert_allclose(np.abs(V[:, zero]), [2 ** -0.5, 2 ** -0.5, 0.0], atol=1e-12)
+    # scores are centred: every column of Z sums to 0
+    np.testing.assert_allclose(Z.sum(0), 0.0, atol=1e-9)
+    # an empty row is a cell of zeros: its score is -mu^T V
+    ip2 = np.concatenate([ip, [600]])
+    _, _, _, V2, Z2 = opca.pca(ip2, ix, v, 3, 3)
+    mu2 = np.concatenate([np.stack([a, a, c], 1).astype(np.float64), np.zeros((1, 3))]).mean(0)
+    np.testing.assert_allclose(Z2[-1], -(mu2 @ V2), atol=1e-12)
