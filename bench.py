@@ -385,6 +385,66 @@ def large_k_form(args, rsc) -> dict:
     return res
 
 
+def pca_form(args, rsc) -> dict:
+    """Sparse PCA of a cells x genes CSR matrix (Methods, Principal component
+    analysis): means, Gram, centring, top-50 eigenpairs, scores."""
+    import torch
+
+    import synth
+
+    n, p, k = args.pca_n, synth.SPARSE_PCA["p"], 50
+    log(f"[bench] pca: generating {n} x {p} CSR")
+    t0 = time.perf_counter()
+    ip, ix, v = synth.sparse_expression(n=n)
+    gen_s = time.perf_counter() - t0
+    nnz = int(ip[-1])
+    ipt, ixt, vt = torch.from_numpy(ip).cuda(), torch.from_numpy(ix).cuda(), torch.from_numpy(v).cuda()
+    ws = rsc.Workspace()
+    log("[bench] pca: warmup")
+    rsc.pca(ipt, ixt, vt, p, k, workspace=ws)
+    torch.cuda.synchronize()
+    steps = max(1, args.form_steps)
+    rsc.profile_reset()
+    rsc.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        mean, evals, V, Z = rsc.pca(ipt, ixt, vt, p, k, workspace=ws)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    rsc.profile_enable(False)
+    kern = {}
+    for name in ["pca_densify", "pca_gram", "pca_center", "pca_eigh", "pca_scores"]:
+        tot, cnt = rsc.profile_get(name)
+        if cnt:
+            kern[name] = round(tot / steps, 3)
+    P = (p + 1 + 63) // 64 * 64
+    gram_flops = 2.0 * n * (P // 64) * (P // 64 + 1) / 2 * 64 * 64  # upper-triangle tiles, all padded columns
+    alg_flops = 1.0 * n * p * (p + 1)  # the upper triangle of X^T X, 2 flops per product
+    g_ms = kern.get("pca_gram")
+    ev = evals.cpu().numpy()
+    cpu = None if args.no_cpu_baseline else pca_cpu_baseline(ip, ix, v, p)
+    return {"workload": f"CSR {n} cells x {p} genes, {nnz} stored entries ({nnz / (n * p):.3f} dense), "
+                        f"k = {k}, latent 8-program model (seed {synth.SPARSE_PCA['seed']})",
+            "ms_per_call": round(ms, 2), "cells_per_s": round(n / (ms / 1e3), 1), "kernel_ms": kern,
+            "gram_fp64_tflops_algorithmic": round(alg_flops / (g_ms / 1e3) / 1e12, 2) if g_ms else None,
+            "gram_fp64_tflops_tiles": round(gram_flops / (g_ms / 1e3) / 1e12, 2) if g_ms else None,
+            "gram_frac_of_fp64_peak": round(gram_flops / (g_ms / 1e3) / 1e12 / PEAK_FP64_TFLOPS, 4) if g_ms else None,
+            "top_evals": [round(float(x), 5) for x in ev[:5]], "generation_s": round(gen_s, 1), "cpu_baseline": cpu}
+
+
+def pca_cpu_baseline(ip, ix, v, p) -> dict:
+    """The oracle's float64 Gram and means on the first cells of the same
+    matrix (cells per second of the covariance step)."""
+    from oracle import pca as opca
+
+    m = 2000
+    t0 = time.perf_counter()
+    opca.covariance(ip[:m + 1], ix, v, p)
+    secs = time.perf_counter() - t0
+    return {"value": round(m / secs, 1), "unit": "cells/s (covariance)", "cores": 1, "kind": "oracle",
+            "sample": f"the first {m} cells ({secs:.2f} s)"}
+
+
 def batched_form(args, rsc) -> dict:
     """64 independent samples (log-uniform 2k..200k cells, 10-40 clusters each):
     per-sample exact kNN in one persistent launch + connectivities."""
@@ -577,7 +637,8 @@ def main() -> int:
     ap.add_argument("--no-forms", action="store_true", help="skip the 2M-cell precision forms")
     ap.add_argument("--form-steps", type=int, default=3)
     ap.add_argument("--no-routed", action="store_true", help="skip the learned-router form")
-    ap.add_argument("--only", choices=["cosine", "edistance", "large_k", "precision", "batched", "routed"],
+    ap.add_argument("--pca-n", type=int, default=1_000_000, help="cells of the sparse-PCA form")
+    ap.add_argument("--only", choices=["cosine", "edistance", "large_k", "pca", "precision", "batched", "routed"],
                     help="run one form alone and print its record (no benchmark line)")
     ap.add_argument("--routed-n", type=int, default=5_000_000)
     ap.add_argument("--routed-train", type=int, default=1_000_000)
@@ -618,7 +679,7 @@ def main() -> int:
         return 0
     if args.only:
         fn = {"precision": precision_forms, "batched": batched_form, "routed": routed_form,
-              "edistance": edistance_form, "large_k": large_k_form}[args.only]
+              "edistance": edistance_form, "large_k": large_k_form, "pca": pca_form}[args.only]
         print(json.dumps({args.only: fn(args, rsc)}), flush=True)
         return 0
 
@@ -692,6 +753,8 @@ def main() -> int:
         forms["batched_fp32"] = batched_form(args, rsc)
         torch.cuda.empty_cache()
         forms["edistance_fp64"] = edistance_form(args, rsc)
+        torch.cuda.empty_cache()
+        forms["sparse_pca"] = pca_form(args, rsc)
         if not args.no_routed:
             torch.cuda.empty_cache()
             forms["routed"] = routed_form(args, rsc)

@@ -489,6 +489,45 @@ int rsc_edistance_onesided(const float *X, int64_t n, int32_t d, const int64_t *
                            void *stream);
 
 /* ---------------------------------------------------------------------- */
+/* Sparse PCA: the embedding the graph is built on                         */
+/* ---------------------------------------------------------------------- */
+/*
+ * Methods, "Principal component analysis": for a cells x genes CSR matrix X
+ * (n x p), mu = X^T 1 / n, S = X^T X (upper triangle accumulated, then
+ * copied), C = (S - n mu mu^T) / (n - 1) without centring X, the top-k
+ * eigenpairs of C, and the scores Z = X V - 1 (mu^T V).
+ *   indptr   DEVICE int64 [n + 1]; indices DEVICE int32 [nnz] (genes in
+ *            [0, p), distinct within a row); data DEVICE float32 [nnz].
+ *   mean     DEVICE float64 [p]; cov DEVICE float64 [p][p] (symmetric;
+ *            may be NULL in rsc_pca).
+ *   evals    DEVICE float64 [k], descending.
+ *   loadings DEVICE float64 [p][k], column t = the t-th eigenvector, signed
+ *            so that its largest-magnitude entry (lowest gene on ties) is
+ *            positive.
+ *   scores   DEVICE float32 [n][k] (sums in float64, rounded once).
+ * 2 <= n, 1 <= p <= 16384, 1 <= k <= min(p, 64).  The Gram matrix is summed
+ * in float64 on the matrix cores (float32 products are exact in float64) over
+ * densified chunks of cells; the eigendecomposition is rocSOLVER's float64
+ * symmetric solver, run on the caller's workspace.  The first call on a
+ * device creates a rocBLAS handle that the library keeps until the process
+ * ends.  Both calls synchronise `stream` (to report a gene index outside
+ * [0, p) as RSC_ERR_INVALID_ARG, and the solver's status).
+ */
+
+/* Workspace bytes for rsc_pca (k >= 1; needs a device to size the solver)
+ * or rsc_pca_covariance (k = 0). */
+size_t rsc_pca_workspace_bytes(int64_t n, int32_t p, int32_t k);
+
+/* mean and covariance only. */
+int rsc_pca_covariance(const int64_t *indptr, const int32_t *indices, const float *data, int64_t n, int32_t p,
+                       double *mean, double *cov, void *workspace, size_t workspace_bytes, void *stream);
+
+/* The whole PCA. */
+int rsc_pca(const int64_t *indptr, const int32_t *indices, const float *data, int64_t n, int32_t p, int32_t k,
+            double *mean, double *cov, double *evals, double *loadings, float *scores, void *workspace,
+            size_t workspace_bytes, void *stream);
+
+/* ---------------------------------------------------------------------- */
 /* Kernel timing (off by default)                                          */
 /* ---------------------------------------------------------------------- */
 

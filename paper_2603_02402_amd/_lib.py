@@ -104,6 +104,9 @@ SIGNATURES = {
     "rsc_edistance_pairwise": (ctypes.c_int, [_P, _I64, _I32, _P, _I64, _P, _P, _P, _P, _SZ, _P]),
     "rsc_edistance_onesided_workspace_bytes": (_SZ, [_I64, _I64, _I32]),
     "rsc_edistance_onesided": (ctypes.c_int, [_P, _I64, _I32, _P, _I64, _P, _I64, _P, _P, _SZ, _P]),
+    "rsc_pca_workspace_bytes": (_SZ, [_I64, _I32, _I32]),
+    "rsc_pca_covariance": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _P, _SZ, _P]),
+    "rsc_pca": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _I32, _P, _P, _P, _P, _P, _P, _SZ, _P]),
     "rsc_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "rsc_profile_reset": (ctypes.c_int, []),
     "rsc_profile_get": (ctypes.c_int, [ctypes.c_char_p, _P, _P]),

@@ -536,6 +536,33 @@ int rsc_edistance_onesided(const float *X, int64_t n, int32_t d, const int64_t *
                               static_cast<hipStream_t>(stream));
 }
 
+size_t rsc_pca_workspace_bytes(int64_t n, int32_t p, int32_t k) { return pca_workspace_bytes(n, p, k); }
+
+int rsc_pca_covariance(const int64_t *indptr, const int32_t *indices, const float *data, int64_t n, int32_t p,
+                       double *mean, double *cov, void *workspace, size_t workspace_bytes, void *stream) {
+    clear_error();
+    if (!aligned(indptr, 8) || !aligned(indices, 4) || !aligned(data, 4) || !aligned(mean, 8) || !aligned(cov, 8) ||
+        !aligned(workspace, 256)) {
+        set_error("misaligned array or workspace");
+        return RSC_ERR_INVALID_ARG;
+    }
+    return pca_covariance(indptr, indices, data, n, p, mean, cov, workspace, workspace_bytes,
+                          static_cast<hipStream_t>(stream));
+}
+
+int rsc_pca(const int64_t *indptr, const int32_t *indices, const float *data, int64_t n, int32_t p, int32_t k,
+            double *mean, double *cov, double *evals, double *loadings, float *scores, void *workspace,
+            size_t workspace_bytes, void *stream) {
+    clear_error();
+    if (!aligned(indptr, 8) || !aligned(indices, 4) || !aligned(data, 4) || !aligned(mean, 8) || !aligned(cov, 8) ||
+        !aligned(evals, 8) || !aligned(loadings, 8) || !aligned(scores, 4) || !aligned(workspace, 256)) {
+        set_error("misaligned array or workspace");
+        return RSC_ERR_INVALID_ARG;
+    }
+    return pca_run(indptr, indices, data, n, p, k, mean, cov, evals, loadings, scores, workspace, workspace_bytes,
+                   static_cast<hipStream_t>(stream));
+}
+
 int rsc_profile_enable(int enable) {
     Profiler &p = profiler();
     std::lock_guard<std::mutex> lock(p.mu);

@@ -216,6 +216,14 @@ int edistance_pairwise(const float *X, int64_t n, int d, const int64_t *offsets,
 int edistance_onesided(const float *X, int64_t n, int d, const int64_t *offsets, int64_t G, const int32_t *cells,
                        int64_t ref, double *E, void *ws, size_t ws_bytes, hipStream_t s);
 
+// ---- sparse PCA (pca.hip) -------------------------------------------------
+
+size_t pca_workspace_bytes(int64_t n, int p, int k);
+int pca_covariance(const int64_t *indptr, const int32_t *indices, const float *data, int64_t n, int p, double *mean,
+                   double *cov, void *ws, size_t ws_bytes, hipStream_t s);
+int pca_run(const int64_t *indptr, const int32_t *indices, const float *data, int64_t n, int p, int k, double *mean,
+            double *cov, double *evals, double *loadings, float *Z, void *ws, size_t ws_bytes, hipStream_t s);
+
 // ---- graph stages (graph.hip) --------------------------------------------
 
 size_t graph_workspace_bytes(int64_t n, int k);
