@@ -129,3 +129,32 @@ def test_pca_deterministic(rsc):
     b = rsc.pca(dev(ip), dev(ix), dev(v), 200, 16)
     for x, y in zip(a, b):
         assert np.array_equal(x.cpu().numpy(), y.cpu().numpy())
+
+
+def test_pca_two_chunks(rsc):
+    """300k cells x 2000 genes: more than one 2 GiB dense chunk (262,144
+    cells at 2048 padded columns), the benchmarked gene count."""
+    from oracle import pca as opca
+
+    n, p, k = 300_000, 2000, 12
+    ip, ix, v = csr(n, p, 0.05, seed=9)
+    log(f"[pca] two chunks: n={n} p={p} nnz={ip[-1]}")
+    mu, ev, V, Z = rsc.pca(dev(ip), dev(ix), dev(v), p, k)
+    mu, ev, V, Z = mu.cpu().numpy(), ev.cpu().numpy(), V.cpu().numpy(), Z.cpu().numpy()
+    log("  oracle (float64)")
+    mu_o, C_o, ev_o, V_o, Z_o = opca.pca(ip, ix, v, p, k)
+    np.testing.assert_allclose(mu, mu_o, rtol=4 * n * U)
+    w_all = np.sort(np.linalg.eigvalsh(C_o))[::-1]
+    tol_ev = 64 * p * U * np.abs(w_all).max() + 4 * n * U * np.abs(C_o).max()
+    log(f"  max |evals - oracle| = {np.abs(ev - ev_o).max():.3e} (tol {tol_ev:.3e})")
+    assert (np.abs(ev - ev_o) <= tol_ev).all()
+    rows = synth.sample_rows(n, 2000, seed=3)
+    l1 = np.array([np.abs(v[ip[c]:ip[c + 1]]).astype(np.float64).sum() for c in rows])
+    scale = l1.max() + np.abs(mu_o).sum()
+    for t in range(k):
+        gap = min(abs(w_all[t] - w_all[t - 1]) if t > 0 else np.inf, abs(w_all[t] - w_all[t + 1]))
+        err_v = np.abs(V[:, t] - V_o[:, t]).max()
+        assert err_v <= 10 * tol_ev / gap, f"component {t}: {err_v:.3e} (gap {gap:.3e})"
+        zb = scale * err_v + 2.0 ** -24 * np.abs(Z_o[rows, t]) + 64 * U * scale
+        assert (np.abs(Z[rows, t] - Z_o[rows, t]) <= zb).all()
+    log(f"  loadings within {np.abs(V - V_o).max():.3e}")
