@@ -324,9 +324,9 @@ def edistance_cpu_baseline(X, labels, G) -> dict:
 
     off, cells = oed.groups_from_labels(labels, G=G)
     rng = np.random.default_rng(3)
-    gs = rng.choice(np.arange(1, G), size=10, replace=False)
-    pairs = np.array([[0, g] for g in gs[:4]] + [[gs[i], gs[i + 1]] for i in range(4, 10, 2)] +
-                     [[g, g] for g in gs[:3]], dtype=np.int32)
+    gs = rng.choice(np.arange(1, G), size=64, replace=False)
+    pairs = np.array([[0, g] for g in gs[:40]] + [[gs[i], gs[i + 1]] for i in range(40, 64, 2)] +
+                     [[g, g] for g in gs[:16]], dtype=np.int32)
     cnt = oed.pair_counts(np.diff(off), pairs)
     t0 = time.perf_counter()
     oed.sums(X, off, cells, pairs)
@@ -437,7 +437,7 @@ def pca_cpu_baseline(ip, ix, v, p) -> dict:
     matrix (cells per second of the covariance step)."""
     from oracle import pca as opca
 
-    m = 2000
+    m = 20000
     t0 = time.perf_counter()
     opca.covariance(ip[:m + 1], ix, v, p)
     secs = time.perf_counter() - t0

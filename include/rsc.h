@@ -90,14 +90,17 @@ typedef enum { RSC_EUCLIDEAN = 0, RSC_COSINE = 1 } rsc_metric;
  *              RSC_BF16      BF16 operands, FP32 accumulation;
  *              RSC_FP8_E4M3  OCP e4m3 operands with per-dimension absmax
  *                            scaling (s_t = max|y_t| / 448), FP32 accumulation.
- *              The reduced-precision forms keep the 64 smallest screened keys
- *              per query and re-rank them with float64 distances; they are
- *              approximate (no certificate): judge them by recall@k.
+ *              The reduced-precision forms keep the `screen` (default 64)
+ *              smallest screened keys per query and re-rank them with float64
+ *              distances; they are approximate (no certificate): judge them
+ *              by recall@k.
  *   screen     candidates kept per query and reference range: 32 or 64 for
  *              RSC_FP32 (must exceed k when k < 64; 64 for larger k, where
  *              the references are split into about k / 32 ranges so that
- *              every range's list keeps spare room), 64 for the
- *              reduced-precision forms; 0 = default.
+ *              every range's list keeps spare room); 64 (default), 128, 256
+ *              or 512 for the reduced-precision forms, which split the
+ *              references into screen / 64 ranges of 64 candidates each;
+ *              0 = default.
  *   metric     rsc_metric (0 = Euclidean).  The exactness guarantee of
  *              RSC_FP32 holds for both metrics.
  */

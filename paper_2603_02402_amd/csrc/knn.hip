@@ -745,11 +745,13 @@ int knn_plan(int64_t nq, int64_t nr, int d, int k, const rsc_knn_opts *opts, boo
         }
     } else {
         if (screen_w == 0) screen_w = 64;
-        if (screen_w != 64) {
-            set_error("reduced-precision screens keep 64 candidates (screen = 0 or 64)");
+        if (screen_w != 64 && screen_w != 128 && screen_w != 256 && screen_w != 512) {
+            set_error("reduced-precision screens keep 64, 128, 256 or 512 candidates per query");
             return RSC_ERR_INVALID_ARG;
         }
     }
+    const int lowp_ranges = precision == RSC_FP32 ? 1 : screen_w / 64;
+    if (precision != RSC_FP32) screen_w = 64;  // per reference range; the ranges multiply it
     plan->nq = nq;
     plan->nr = nr;
     plan->d = d;
@@ -767,6 +769,8 @@ int knn_plan(int64_t nq, int64_t nr, int d, int k, const rsc_knn_opts *opts, boo
         // enough (range, half) lists that the m nearest fill each to about half
         const int m = self_mode ? k - 1 : k;
         plan->splits = std::min(32, std::max(plan->splits, (m + plan->half - 1) / plan->half));
+    } else {
+        plan->splits = std::max(plan->splits, lowp_ranges);
     }
     return RSC_OK;
 }

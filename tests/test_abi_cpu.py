@@ -118,6 +118,9 @@ def test_knn_ex_validation(lib):
     assert call(opts=ctypes.byref(narrow)) == -1 and "screen" in _err(lib)
     wide = _lib.KnnOpts(0, 65, 0, 0)
     assert call(opts=ctypes.byref(wide)) == -1
+    assert call(opts=ctypes.byref(_lib.KnnOpts(2, 100, 0, 0))) == -1 and "512" in _err(lib)
+    assert lib.rsc_knn_workspace_bytes(1000, 1000, 50, 15, ctypes.byref(_lib.KnnOpts(2, 512, 0, 0))) > \
+        lib.rsc_knn_workspace_bytes(1000, 1000, 50, 15, ctypes.byref(_lib.KnnOpts(2, 64, 0, 0)))
 
 
 def test_connectivities_validation(lib):

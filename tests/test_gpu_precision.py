@@ -116,3 +116,23 @@ def test_precision_2m_sampled(rsc, oracle_mod):
         log(f"[precision] {name} 2M sampled recall@15 = {rec:.5f}")
         assert (idx[:, 0] == np.arange(X.shape[0])).all()
         assert rec >= floor
+
+
+def test_wider_screens(rsc, oracle_mod):
+    """More candidates per query (reference split into screen / 64 ranges):
+    the re-ranked lists keep their structure and recall does not drop."""
+    import torch
+
+    X = synth.workload("plain_10k")
+    Xt = torch.from_numpy(X).cuda()
+    idx_o, _, dist_o = oracle_mod.knn(X, 15)
+    for prec in (rsc.RSC_FP8_E4M3, rsc.RSC_BF16):
+        recs = []
+        for S in (64, 128, 256, 512):
+            idx, dist = rsc.knn(Xt, 15, precision=prec, screen=S)
+            torch.cuda.synchronize()
+            idx, dist = idx.cpu().numpy(), dist.cpu().numpy()
+            check_structure(X, idx, dist, 15, oracle_mod)
+            recs.append(tie_aware_recall(dist, dist_o, 15))
+        log(f"[precision] {prec} recall@15 by screen 64/128/256/512: {recs}")
+        assert all(b >= a - 1e-3 for a, b in zip(recs, recs[1:]))
