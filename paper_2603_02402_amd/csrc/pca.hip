@@ -256,7 +256,14 @@ struct PcaLayout {
 };
 
 // One rocBLAS handle per device, created on first use and kept for the
-// process (the solver's own allocations stay with it).
+// process (the solver's own allocations stay with it).  Its stream and
+// workspace are set per call, so calls on one device hold solver_lock()
+// while they use it.
+std::mutex &solver_lock() {
+    static std::mutex m;
+    return m;
+}
+
 rocblas_handle solver_handle() {
     static std::mutex mu;
     static rocblas_handle handles[64] = {};
@@ -270,6 +277,7 @@ rocblas_handle solver_handle() {
 size_t solver_bytes(int p) {
     rocblas_handle h = solver_handle();
     if (!h) return 0;
+    std::lock_guard<std::mutex> lock(solver_lock());
     size_t bytes = 0;
     if (rocblas_start_device_memory_size_query(h) != rocblas_status_success) return 0;
     rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_upper, p, nullptr, p, nullptr, nullptr, nullptr);
@@ -436,6 +444,7 @@ int pca_run(const int64_t *indptr, const int32_t *indices, const float *data, in
     int32_t *info = at<int32_t>(ws, L.o_info);
     {
         ScopedTimer t("pca_eigh", s);
+        std::lock_guard<std::mutex> lock(solver_lock());
         if (rocblas_set_stream(h, s) != rocblas_status_success ||
             rocblas_set_workspace(h, at<char>(ws, L.o_solver), L.bytes - L.o_solver) != rocblas_status_success) {
             set_error("pca: solver setup failed");
