@@ -152,7 +152,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_local(int64_t *__restrict__
     s[threadIdx.x] = x;
     __syncthreads();
     for (int o = 1; o < kScanBlock; o <<= 1) {
-        const int64_t t = threadIdx.x >= o ? s[threadIdx.x - o] : 0;
+        const int64_t t = (int)threadIdx.x >= o ? s[threadIdx.x - o] : 0;
         __syncthreads();
         s[threadIdx.x] += t;
         __syncthreads();
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_totals(int64_t *__restrict_
     part[threadIdx.x] = s;
     __syncthreads();
     for (int o = 1; o < kScanBlock; o <<= 1) {
-        const int64_t t = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
+        const int64_t t = (int)threadIdx.x >= o ? part[threadIdx.x - o] : 0;
         __syncthreads();
         part[threadIdx.x] += t;
         __syncthreads();

@@ -286,8 +286,10 @@ bool g_cache_loaded = false;
 
 std::string batch_key(const int64_t *offsets, int S, int d, int k) {
     int dev = 0, cus = 0;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    // (a failed query leaves 0 in the key: the cache entry is then shared
+    // by devices that could not be told apart, which only costs a retune)
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 0;
     int hist[40] = {0};
     for (int s = 0; s < S; ++s) {
         const int64_t n = offsets[s + 1] - offsets[s];
@@ -522,16 +524,16 @@ int batched_autotune(const float *X, const int64_t *offsets, int S, int d, int k
         if ((st = hip_status(hipEventRecord(e1, s), "event")) != RSC_OK) break;
         if ((st = hip_status(hipEventSynchronize(e1), "event")) != RSC_OK) break;
         float ms = 0.f;
-        hipEventElapsedTime(&ms, e0, e1);
+        if ((st = hip_status(hipEventElapsedTime(&ms, e0, e1), "event time")) != RSC_OK) break;
         if (times_ms) times_ms[pol] = ms;
         if (ms < best_ms) {
             best_ms = ms;
             best = pol;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    const hipError_t d0 = hipEventDestroy(e0), d1 = hipEventDestroy(e1);
     if (st != RSC_OK) return st;
+    if ((st = hip_status(d0 != hipSuccess ? d0 : d1, "event destroy")) != RSC_OK) return st;
     {
         std::lock_guard<std::mutex> lock(g_cache_mu);
         load_cache_file();

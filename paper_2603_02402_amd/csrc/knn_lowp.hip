@@ -243,7 +243,6 @@ struct LowpOp;
 template <>
 struct LowpOp<RSC_BF16> {
     using T = i32x4;
-    static constexpr int kPerStep = 16;
     __device__ static f32x16 mfma(T a, T b, f32x16 c) {
         return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
                                                        c, 0, 0, 0);
@@ -252,7 +251,6 @@ struct LowpOp<RSC_BF16> {
 template <>
 struct LowpOp<RSC_FP8_E4M3> {
     using T = i32x8;
-    static constexpr int kPerStep = 64;
     __device__ static f32x16 mfma(T a, T b, f32x16 c) {
         // format 0 = e4m3 for both operands; block scales 127 = 2^0
         return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 127, 0, 127);

@@ -113,7 +113,7 @@ __global__ __launch_bounds__(256) void k_far_partial(const double *__restrict__ 
     si[threadIdx.x] = bi;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w && farther(sd[threadIdx.x + w], si[threadIdx.x + w], sd[threadIdx.x], si[threadIdx.x])) {
+        if ((int)threadIdx.x < w && farther(sd[threadIdx.x + w], si[threadIdx.x + w], sd[threadIdx.x], si[threadIdx.x])) {
             sd[threadIdx.x] = sd[threadIdx.x + w];
             si[threadIdx.x] = si[threadIdx.x + w];
         }
@@ -143,7 +143,7 @@ __global__ __launch_bounds__(256) void k_far_final(const double *__restrict__ pd
     si[threadIdx.x] = bi;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w && farther(sd[threadIdx.x + w], si[threadIdx.x + w], sd[threadIdx.x], si[threadIdx.x])) {
+        if ((int)threadIdx.x < w && farther(sd[threadIdx.x + w], si[threadIdx.x + w], sd[threadIdx.x], si[threadIdx.x])) {
             sd[threadIdx.x] = sd[threadIdx.x + w];
             si[threadIdx.x] = si[threadIdx.x + w];
         }
@@ -227,7 +227,7 @@ __global__ __launch_bounds__(1024) void k_scan_counts(const int32_t *__restrict_
     part[threadIdx.x] = s;
     __syncthreads();
     for (int o = 1; o < 1024; o <<= 1) {
-        const int64_t v = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
+        const int64_t v = (int)threadIdx.x >= o ? part[threadIdx.x - o] : 0;
         __syncthreads();
         part[threadIdx.x] += v;
         __syncthreads();

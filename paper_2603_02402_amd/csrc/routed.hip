@@ -173,8 +173,8 @@ __global__ __launch_bounds__(1024) void k_scan_parts(int mode, const int64_t *__
     s1[threadIdx.x] = c;
     __syncthreads();
     for (int o = 1; o < 1024; o <<= 1) {
-        const int64_t va = threadIdx.x >= o ? s0[threadIdx.x - o] : 0;
-        const int64_t vc = threadIdx.x >= o ? s1[threadIdx.x - o] : 0;
+        const int64_t va = (int)threadIdx.x >= o ? s0[threadIdx.x - o] : 0;
+        const int64_t vc = (int)threadIdx.x >= o ? s1[threadIdx.x - o] : 0;
         __syncthreads();
         s0[threadIdx.x] += va;
         s1[threadIdx.x] += vc;

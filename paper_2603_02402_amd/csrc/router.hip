@@ -298,7 +298,7 @@ __global__ __launch_bounds__(256) void k_batch_loss(const float *__restrict__ ro
     part[threadIdx.x] = s;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
         __syncthreads();
     }
     if (threadIdx.x == 0) *out = part[0] * scale;
@@ -492,7 +492,7 @@ __global__ __launch_bounds__(256) void k_epoch_loss(const float *__restrict__ ba
     part[threadIdx.x] = acc;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
         __syncthreads();
     }
     if (threadIdx.x == 0) *out = (float)(part[0] * inv_n);
