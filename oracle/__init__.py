@@ -9,7 +9,8 @@ The arithmetic lives in ``oracle.c`` (float64, brute force, compiled with
 numpy arrays.  ``mlp.py`` holds the float64 reference of the partition
 router's network, ``partition.py`` the k-means partitions and the routed
 form's candidate sets, ``edistance.py`` the group-pair distance sums and
-energy distances, ``pca.py`` the sparse PCA that produces the embedding.
+energy distances, ``pca.py`` the sparse PCA that produces the embedding,
+``umap.py`` the UMAP layout of the graph.
 """
 
 from __future__ import annotations
@@ -64,6 +65,11 @@ def _load():
             lib.oracle_knn_subset.restype = i32
             lib.oracle_edistance_sums.argtypes = [P, i64, i32, P, i64, P, P, i64, P]
             lib.oracle_edistance_sums.restype = i32
+            lib.oracle_umap_layout.argtypes = [P, P, P, i64, i32, P, i32, ctypes.c_double, ctypes.c_double,
+                                               ctypes.c_double, ctypes.c_double, i32, ctypes.c_uint64]
+            lib.oracle_umap_layout.restype = i32
+            lib.oracle_splitmix64_next.argtypes = [ctypes.c_uint64]
+            lib.oracle_splitmix64_next.restype = ctypes.c_uint64
             _lib = lib
     return _lib
 

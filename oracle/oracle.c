@@ -515,3 +515,104 @@ int oracle_edistance_sums(const float *X, int64_t n, int d, const int64_t *offse
     }
     return 0;
 }
+
+/*
+ * UMAP layout by stochastic gradient descent over the edges of the fuzzy
+ * graph (the layout step of UMAP, reference [15] of the paper's Technical
+ * architecture section; the paper runs it on the graph this library builds).
+ * One reading of the method, written out plainly:
+ *
+ *   q(d2)      = 1 / (1 + a d2^b), d2 the squared embedding distance
+ *   eps_e      = w_max / w_e epochs between samples of edge e (never
+ *                sampled if w_e < w_max / n_epochs); first due at eps_e
+ *   epoch t    (0 .. n_epochs-1), alpha_t = alpha0 (1 - t / n_epochs):
+ *              every move is computed from the embedding at the start of
+ *              the epoch (Y); vertex i sums the moves of its own edges in
+ *              CSR order, then Y_i += the sum.  For each edge e = (i, j)
+ *              of row i that is due (next_e <= t; then next_e += eps_e):
+ *                attraction: d2 = |Y_i - Y_j|^2, g = -2 a b d2^(b-1) /
+ *                  (a d2^b + 1) if d2 > 0 else 0; move_i += clip(g (Y_i -
+ *                  Y_j)) alpha_t per coordinate;
+ *                `neg` repulsions from vertices k = splitmix64(seed, t, e,
+ *                  p) mod n, p = 0 .. neg-1 (k == i skipped): d2 = |Y_i -
+ *                  Y_k|^2, if d2 > 0: g = 2 gamma b / ((0.001 + d2)(a d2^b
+ *                  + 1)), move_i += clip(g (Y_i - Y_k)) alpha_t, else
+ *                  move_i += 4 alpha_t per coordinate;
+ *   clip(x)    = max(-4, min(4, x)).
+ *
+ * splitmix64: state s = seed + (t * 2^40 + e * 2^4 + p + 1) * 0x9E3779B97F4A7C15
+ * (mod 2^64), then the SplitMix64 finaliser (xor-shift 30, multiply by
+ * 0xBF58476D1CE4E5B9, xor-shift 27, multiply by 0x94D049BB133111EB,
+ * xor-shift 31); k = (out >> 11) mod n.
+ *
+ * Y is n x dim float64, updated in place.  Returns 0, or -1 for invalid
+ * arguments.
+ */
+static uint64_t sm64_mix(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+uint64_t oracle_splitmix64_next(uint64_t state) { return sm64_mix(state + 0x9E3779B97F4A7C15ull); }
+
+static double clip4(double x) { return x > 4.0 ? 4.0 : (x < -4.0 ? -4.0 : x); }
+
+int oracle_umap_layout(const int64_t *indptr, const int32_t *indices, const float *weights, int64_t n, int dim,
+                       double *Y, int n_epochs, double a, double b, double gamma, double alpha0, int neg,
+                       uint64_t seed) {
+    if (n < 1 || dim < 1 || n_epochs < 0 || neg < 0) return -1;
+    int64_t nnz = indptr[n];
+    double wmax = 0.0;
+    for (int64_t e = 0; e < nnz; ++e)
+        if ((double)weights[e] > wmax) wmax = (double)weights[e];
+    double *eps = (double *)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+    double *next = (double *)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+    double *Y0 = (double *)malloc(sizeof(double) * (size_t)n * dim);
+    double *mv = (double *)malloc(sizeof(double) * (size_t)dim);
+    if (!eps || !next || !Y0 || !mv) {
+        free(eps); free(next); free(Y0); free(mv);
+        return -1;
+    }
+    for (int64_t e = 0; e < nnz; ++e) {
+        double w = (double)weights[e];
+        eps[e] = (w > 0.0 && w >= wmax / (double)n_epochs) ? wmax / w : -1.0;
+        next[e] = eps[e];
+    }
+    for (int t = 0; t < n_epochs; ++t) {
+        double alpha = alpha0 * (1.0 - (double)t / (double)n_epochs);
+        memcpy(Y0, Y, sizeof(double) * (size_t)n * dim);
+        for (int64_t i = 0; i < n; ++i) {
+            const double *yi = Y0 + i * dim;
+            for (int c = 0; c < dim; ++c) mv[c] = 0.0;
+            for (int64_t e = indptr[i]; e < indptr[i + 1]; ++e) {
+                if (eps[e] < 0.0 || next[e] > (double)t) continue;
+                next[e] = next[e] + eps[e];
+                const double *yj = Y0 + (int64_t)indices[e] * dim;
+                double d2 = 0.0;
+                for (int c = 0; c < dim; ++c) d2 = d2 + (yi[c] - yj[c]) * (yi[c] - yj[c]);
+                double g = 0.0;
+                if (d2 > 0.0) g = (-2.0 * a * b * pow(d2, b - 1.0)) / (a * pow(d2, b) + 1.0);
+                for (int c = 0; c < dim; ++c) mv[c] = mv[c] + clip4(g * (yi[c] - yj[c])) * alpha;
+                for (int p = 0; p < neg; ++p) {
+                    uint64_t st = seed + ((uint64_t)t * (1ull << 40) + (uint64_t)e * 16ull + (uint64_t)p + 1ull) *
+                                             0x9E3779B97F4A7C15ull;
+                    int64_t k = (int64_t)((sm64_mix(st) >> 11) % (uint64_t)n);
+                    if (k == i) continue;
+                    const double *yk = Y0 + k * dim;
+                    double dk = 0.0;
+                    for (int c = 0; c < dim; ++c) dk = dk + (yi[c] - yk[c]) * (yi[c] - yk[c]);
+                    if (dk > 0.0) {
+                        double gr = (2.0 * gamma * b) / ((0.001 + dk) * (a * pow(dk, b) + 1.0));
+                        for (int c = 0; c < dim; ++c) mv[c] = mv[c] + clip4(gr * (yi[c] - yk[c])) * alpha;
+                    } else {
+                        for (int c = 0; c < dim; ++c) mv[c] = mv[c] + 4.0 * alpha;
+                    }
+                }
+            }
+            for (int c = 0; c < dim; ++c) Y[i * dim + c] = yi[c] + mv[c];
+        }
+    }
+    free(eps); free(next); free(Y0); free(mv);
+    return 0;
+}

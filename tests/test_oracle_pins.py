@@ -702,3 +702,93 @@ def test_pca_closed_forms():
     _, _, _, V2, Z2 = opca.pca(ip2, ix, v, 3, 3)
     mu2 = np.concatenate([np.stack([a, a, c], 1).astype(np.float64), np.zeros((1, 3))]).mean(0)
     np.testing.assert_allclose(Z2[-1], -(mu2 @ V2), atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# UMAP layout (the method's published loss, gradients and sampling; reading
+# in oracle.c).
+# ---------------------------------------------------------------------------
+
+def test_splitmix64_published_value():
+    from oracle import umap as ou
+
+    # SplitMix64's first output from state 0 (the generator's published test value)
+    assert ou.splitmix64_next(0) == 0xE220A8397B1DCDAF
+
+
+def _two_points(w=1.0):
+    ip = np.array([0, 1, 2], dtype=np.int64)
+    ix = np.array([1, 0], dtype=np.int32)
+    return ip, ix, np.array([w, w], dtype=np.float32)
+
+
+def test_umap_attraction_is_the_gradient_of_minus_log_q():
+    from oracle import umap as ou
+
+    a, b = ou.fit_ab(0.5, 1.0)
+    y0 = np.array([[0.3, -0.2], [1.1, 0.4]])
+    Y = ou.layout(*_two_points(), y0, n_epochs=2, a=a, b=b, neg=0)  # epoch 1 samples the edge, alpha 1/2
+
+    def loss(yi):
+        d2 = ((yi - y0[1]) ** 2).sum()
+        return np.log1p(a * d2 ** b)  # -log q
+
+    h = 1e-6
+    grad = np.array([(loss(y0[0] + h * np.eye(2)[c]) - loss(y0[0] - h * np.eye(2)[c])) / (2 * h) for c in range(2)])
+    np.testing.assert_allclose(Y[0] - y0[0], -0.5 * grad, rtol=1e-7)
+    np.testing.assert_allclose(Y[1] - y0[1], 0.5 * grad, rtol=1e-7)  # the mirror move of the other row
+
+
+def test_umap_repulsion_is_the_gradient_of_minus_log_one_minus_q():
+    from oracle import umap as ou
+
+    a, b, gamma = 1.2, 0.9, 1.5
+    y0 = np.array([[0.0, 0.0], [6.0, 8.0], [30.0, 40.0]])  # distances 10 and 50: the 0.001 term is negligible
+    # vertex 0 has one edge (to 1, weight 1); vertex 2 is only ever a negative sample
+    ip = np.array([0, 1, 2, 2], dtype=np.int64)
+    ix = np.array([1, 0], dtype=np.int32)
+    w = np.array([1.0, 1.0], dtype=np.float32)
+    Ya = ou.layout(ip, ix, w, y0, n_epochs=2, a=a, b=b, gamma=gamma, neg=0)
+    Yr = ou.layout(ip, ix, w, y0, n_epochs=2, a=a, b=b, gamma=gamma, neg=1, seed=7)
+    # which vertex the single negative of vertex 0 drew (epoch 1, edge 0, draw 0)
+    st = (7 + ((1 << 40) + 0 * 16 + 0 + 1) * 0x9E3779B97F4A7C15) % (1 << 64)
+    kk = (ou.splitmix64_next((st - 0x9E3779B97F4A7C15) % (1 << 64)) >> 11) % 3
+    rep = Yr[0] - Ya[0]
+    if kk == 0:
+        assert np.all(rep == 0)
+        return
+    yk = y0[kk]
+
+    def loss(yi):
+        d2 = ((yi - yk) ** 2).sum()
+        q = 1.0 / (1.0 + a * d2 ** b)
+        return -gamma * np.log(1.0 - q)
+
+    h = 1e-5
+    grad = np.array([(loss(y0[0] + h * np.eye(2)[c]) - loss(y0[0] - h * np.eye(2)[c])) / (2 * h) for c in range(2)])
+    np.testing.assert_allclose(rep, -0.5 * grad, rtol=1e-4)
+
+
+def test_umap_schedule_translation_and_clipping():
+    from oracle import umap as ou
+
+    a, b = ou.fit_ab(0.5, 1.0)
+    # a weak edge (weight 1/3 of the strongest) moves its rows only at epochs 3, 6, ...
+    # rows: 0 -> {1 (w 1), 2 (w 1/3)}, 1 -> {0 (w 1)}, 2 -> {0 (w 1)}, 3 -> {2 (w 1/3)}
+    ip = np.array([0, 2, 3, 4, 5], dtype=np.int64)
+    ix = np.array([1, 2, 0, 0, 2], dtype=np.int32)
+    w = np.array([1.0, 1.0 / 3, 1.0, 1.0, 1.0 / 3], dtype=np.float32)
+    y0 = np.array([[0.0, 0.0], [2.0, 0.0], [0.0, 3.0], [5.0, 5.0]])
+    moves = []
+    for T in range(1, 8):
+        Y = ou.layout(ip, ix, w, y0, n_epochs=T, a=a, b=b, neg=0)
+        moves.append(Y[3].copy())
+    # row 3 holds only the weak edge (3 -> 2): still at y0 until an epoch t >= 3 has run
+    assert np.array_equal(moves[0], y0[3]) and np.array_equal(moves[2], y0[3]) and not np.array_equal(moves[3], y0[3])
+    # translation by an exact offset moves every result by the same offset
+    Yt = ou.layout(ip, ix, w, y0 + 1024.0, n_epochs=6, a=a, b=b, neg=2, seed=3)
+    Yu = ou.layout(ip, ix, w, y0, n_epochs=6, a=a, b=b, neg=2, seed=3)
+    np.testing.assert_allclose(Yt - 1024.0, Yu, atol=1e-9)
+    # coincident points: the attraction is 0 and no step exceeds 4 alpha per coordinate
+    Yc = ou.layout(*_two_points(), np.zeros((2, 2)), n_epochs=2, a=a, b=b, neg=0)
+    assert np.array_equal(Yc, np.zeros((2, 2)))
