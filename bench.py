@@ -261,6 +261,11 @@ def cosine_form(args, rsc, Xt, ws, out) -> dict:
 
 
 PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 matrix
+# float64 vector instruction rate: 256 CUs x 64 lanes x 2.4 GHz (78.6 TFLOP/s counts an FMA as 2)
+PEAK_FP64_VECTOR_OPS = 39.3
+# float64 add / multiply / fma instructions of one slot of k_umap_terms (the
+# straight-line correctly rounded power plus the move), counted in its assembly
+UMAP_TERM_FP64_OPS = 619
 
 
 def edistance_form(args, rsc) -> dict:
@@ -443,6 +448,104 @@ def pca_cpu_baseline(ip, ix, v, p) -> dict:
     secs = time.perf_counter() - t0
     return {"value": round(m / secs, 1), "unit": "cells/s (covariance)", "cores": 1, "kind": "oracle",
             "sample": f"the first {m} cells ({secs:.2f} s)"}
+
+
+def umap_samples(w: np.ndarray, n_epochs: int) -> int:
+    """Edge samples a layout of n_epochs makes: edge e (eps = w_max / w_e,
+    kept if w_e >= w_max / n_epochs) is due at epochs eps, 2 eps, ... below
+    n_epochs (the float64 accumulation of eps can move a boundary sample:
+    the count is exact up to those)."""
+    w = w.astype(np.float64)
+    wmax = w.max() if w.size else 0.0
+    keep = (w > 0) & (w >= wmax / n_epochs)
+    eps = wmax / w[keep]
+    return int(np.floor((n_epochs - 1) / eps + 1e-9).sum())
+
+
+def umap_form(args, rsc, csr=None) -> dict:
+    """UMAP layout of the 1M-cell kNN graph (the embedding step the paper
+    runs on this graph): 200 epochs of edge-sampled SGD, 5 negatives per
+    sample, 2-D, random initial embedding."""
+    import torch
+
+    import synth
+
+    n_epochs, neg, dim = args.umap_epochs, 5, 2
+    if csr is None:
+        w = WORKLOADS["plain_1m"]
+        log("[bench] umap: building the 1M-cell graph")
+        X = torch.from_numpy(synth.mixture(w["n"], d=50, n_clusters=w["clusters"], law=w["law"],
+                                           seed=w["seed"])).cuda()
+        ws0 = rsc.Workspace()
+        idx, dist = rsc.knn(X, args.k, workspace=ws0)
+        g = rsc.connectivities(idx, dist, workspace=ws0)
+        csr = (g.indptr, g.indices, g.data)
+        del X, idx, dist, ws0
+    indptr, indices, data = csr
+    n = indptr.numel() - 1
+    nnz = int(indptr[-1].item())
+    indices, data = indices[:nnz], data[:nnz]
+    Y0 = torch.from_numpy(synth.umap_init(n, dim, seed=13)).cuda()
+    ws = rsc.Workspace()
+    log("[bench] umap: warmup")
+    rsc.umap_layout((indptr, indices, data), Y0, n_epochs=n_epochs, neg=neg, seed=1, workspace=ws)
+    torch.cuda.synchronize()
+    steps = max(1, args.form_steps)
+    rsc.profile_reset()
+    rsc.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        Y = rsc.umap_layout((indptr, indices, data), Y0, n_epochs=n_epochs, neg=neg, seed=1, workspace=ws)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    rsc.profile_enable(False)
+    kern = {}
+    for name in ["umap_init", "umap_epochs", "umap_due", "umap_terms", "umap_sum"]:
+        tot, cnt = rsc.profile_get(name)
+        if cnt:
+            kern[name] = round(tot / steps, 3)
+    wts = data.cpu().numpy()
+    samples = umap_samples(wts, n_epochs)
+    ep_ms = kern.get("umap_epochs")
+    terms = None
+    if kern.get("umap_terms"):
+        # the term kernel is bound by float64 vector issue (the correctly rounded
+        # power): UMAP_TERM_FP64_OPS float64 instructions per slot, one slot per
+        # (edge sample, draw)
+        slots = samples * (1 + neg)
+        rate = slots * UMAP_TERM_FP64_OPS / (kern["umap_terms"] / 1e3) / 1e12
+        terms = {"bound": "alu", "unit": "T float64 ops/s", "slots": slots, "ops_per_slot": UMAP_TERM_FP64_OPS,
+                 "achieved": round(rate, 2), "peak": PEAK_FP64_VECTOR_OPS, "frac": round(rate / PEAK_FP64_VECTOR_OPS, 4)}
+    finite = bool(torch.isfinite(Y).all().item())
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = umap_cpu_baseline(indptr.cpu().numpy(), indices.cpu().numpy(), wts, Y0.cpu().numpy(), neg, samples,
+                                n_epochs)
+    return {"workload": f"fuzzy kNN graph of the 1M-cell plain workload: {n} vertices, {nnz} stored edges; "
+                        f"{n_epochs} epochs, {neg} negative samples, dim {dim}, random initial layout",
+            "ms_per_call": round(ms, 2), "layouts_per_s": round(1e3 / ms, 3), "kernel_ms": kern,
+            "edge_samples": samples, "pow_evaluations_approx": samples * (1 + neg),
+            "edge_samples_per_s": round(samples / (ep_ms / 1e3), 1) if ep_ms else None,
+            "ms_per_epoch": round(ep_ms / n_epochs, 4) if ep_ms else None, "term_kernel_roofline": terms,
+            "finite": finite, "cpu_baseline": cpu}
+
+
+def umap_cpu_baseline(indptr, indices, w, Y0, neg, samples_full, n_epochs_full) -> dict:
+    """The oracle's layout of the same graph over 3 epochs (epochs 1 and 2
+    sample the edges with w >= w_max / 2), as edge samples per second, and
+    scaled to full layouts per second."""
+    import oracle
+    from oracle import umap as ou
+
+    E = 3
+    s = umap_samples(w, E)
+    t0 = time.perf_counter()
+    ou.layout(indptr, indices, w, Y0, E, 0.5830300203414425, 1.3341669924314914, neg=neg, seed=1)
+    secs = time.perf_counter() - t0
+    rate = s / secs
+    return {"value": round(rate / samples_full, 6), "unit": f"{n_epochs_full}-epoch layouts/s",
+            "edge_samples_per_s": round(rate, 1), "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": f"{E} epochs of the same graph ({s} edge samples, {secs:.1f} s)"}
 
 
 def batched_form(args, rsc) -> dict:
@@ -638,7 +741,9 @@ def main() -> int:
     ap.add_argument("--form-steps", type=int, default=3)
     ap.add_argument("--no-routed", action="store_true", help="skip the learned-router form")
     ap.add_argument("--pca-n", type=int, default=1_000_000, help="cells of the sparse-PCA form")
-    ap.add_argument("--only", choices=["cosine", "edistance", "large_k", "pca", "precision", "batched", "routed"],
+    ap.add_argument("--umap-epochs", type=int, default=200)
+    ap.add_argument("--only", choices=["cosine", "edistance", "large_k", "pca", "precision", "batched", "routed",
+                                       "umap"],
                     help="run one form alone and print its record (no benchmark line)")
     ap.add_argument("--routed-n", type=int, default=5_000_000)
     ap.add_argument("--routed-train", type=int, default=1_000_000)
@@ -679,7 +784,7 @@ def main() -> int:
         return 0
     if args.only:
         fn = {"precision": precision_forms, "batched": batched_form, "routed": routed_form,
-              "edistance": edistance_form, "large_k": large_k_form, "pca": pca_form}[args.only]
+              "edistance": edistance_form, "large_k": large_k_form, "pca": pca_form, "umap": umap_form}[args.only]
         print(json.dumps({args.only: fn(args, rsc)}), flush=True)
         return 0
 
@@ -745,7 +850,13 @@ def main() -> int:
     forms = None
     if not args.no_forms:
         forms = {"cosine_fp32": cosine_form(args, rsc, Xt, ws, (idx, dist, csr))}
-        del Xt, idx, dist, csr
+        # the layout runs on the plain graph: rebuild it into the CSR buffers
+        step()
+        del Xt, idx, dist
+        ws.buf = None
+        torch.cuda.empty_cache()
+        forms["umap_layout"] = umap_form(args, rsc, csr)
+        del csr
         ws.buf = None
         torch.cuda.empty_cache()
         forms.update(precision_forms(args, rsc))

@@ -531,6 +531,46 @@ int rsc_pca(const int64_t *indptr, const int32_t *indices, const float *data, in
             size_t workspace_bytes, void *stream);
 
 /* ---------------------------------------------------------------------- */
+/* UMAP layout of the graph                                                */
+/* ---------------------------------------------------------------------- */
+/*
+ * The layout step of UMAP (the embedding method the paper runs on this
+ * graph, its reference [15]): stochastic gradient descent over the graph's
+ * edges on the cross-entropy between the weights and q(d2) = 1/(1 + a d2^b).
+ * Deterministic reading: edge e (weight w_e) is due every w_max / w_e
+ * epochs (never when w_e < w_max / n_epochs); in epoch t every move is
+ * computed from the embedding at the start of t and vertex i sums the moves
+ * of its own row's due edges in CSR order -- an attraction towards the
+ * neighbour, then `neg` repulsions from vertices drawn by a counter-based
+ * SplitMix64 (state seed + (t 2^40 + e 16 + p + 1) 0x9E3779B97F4A7C15,
+ * k = (mix >> 11) mod n) -- each coordinate clipped to [-4, 4] and scaled by
+ * alpha0 (1 - t / n_epochs); attraction -2 a b (d2^b / d2) / (a d2^b + 1),
+ * repulsion 2 gamma b / ((0.001 + d2)(a d2^b + 1)), with d2^b the correctly
+ * rounded power.  The embedding is kept in float64 and every operation is
+ * rounded as written, so the layout is bitwise reproducible and equals that
+ * of any sequential implementation of these steps.
+ *   indptr, indices, weights  DEVICE CSR of the symmetric graph (the
+ *            rsc_connectivities layout): int64 [n + 1], int32 [nnz], float32
+ *            [nnz] with weights >= 0 (indices and weights may be NULL when
+ *            nnz = 0).
+ *   Y        DEVICE float32 [n][dim], the initial embedding in (finite,
+ *            else RSC_ERR_INVALID_ARG), the layout out; 1 <= dim <= 8.
+ *   a, b     the similarity curve (min_dist 0.5, spread 1: a = 0.58303,
+ *            b = 1.33417, the least-squares fit of UMAP's target curve);
+ *            gamma the repulsion strength (1), alpha0 the initial rate (1),
+ *            neg the negative samples per due edge (5).
+ * Synchronises `stream` once, to report a malformed graph as
+ * RSC_ERR_BAD_GRAPH before any epoch runs.  Supports n < 2^31 and
+ * nnz < 2^32 - 1; the workspace (rsc_umap_workspace_bytes, 0 for an
+ * unsupported shape) holds about nnz (28 + 8 dim (1 + neg)) + 16 n dim bytes:
+ * the move terms of every due edge of an epoch are kept for the ordered sums.
+ */
+size_t rsc_umap_workspace_bytes(int64_t n, int64_t nnz, int32_t dim, int32_t neg);
+int rsc_umap_layout(const int64_t *indptr, const int32_t *indices, const float *weights, int64_t n, int64_t nnz,
+                    int32_t dim, float *Y, int32_t n_epochs, double a, double b, double gamma, double alpha0,
+                    int32_t neg, uint64_t seed, void *workspace, size_t workspace_bytes, void *stream);
+
+/* ---------------------------------------------------------------------- */
 /* Kernel timing (off by default)                                          */
 /* ---------------------------------------------------------------------- */
 

@@ -46,6 +46,7 @@
  * on its own, in the order written.
  */
 #include <math.h>
+#include <quadmath.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -530,15 +531,19 @@ int oracle_edistance_sums(const float *X, int64_t n, int d, const int64_t *offse
  *              the epoch (Y); vertex i sums the moves of its own edges in
  *              CSR order, then Y_i += the sum.  For each edge e = (i, j)
  *              of row i that is due (next_e <= t; then next_e += eps_e):
- *                attraction: d2 = |Y_i - Y_j|^2, g = -2 a b d2^(b-1) /
- *                  (a d2^b + 1) if d2 > 0 else 0; move_i += clip(g (Y_i -
- *                  Y_j)) alpha_t per coordinate;
+ *                attraction: d2 = |Y_i - Y_j|^2, g = -2 a b (d2^b / d2) /
+ *                  (a d2^b + 1) if d2 > 0 else 0 (d2^(b-1) taken as
+ *                  d2^b / d2); move_i += clip(g (Y_i - Y_j)) alpha_t per
+ *                  coordinate;
  *                `neg` repulsions from vertices k = splitmix64(seed, t, e,
  *                  p) mod n, p = 0 .. neg-1 (k == i skipped): d2 = |Y_i -
  *                  Y_k|^2, if d2 > 0: g = 2 gamma b / ((0.001 + d2)(a d2^b
  *                  + 1)), move_i += clip(g (Y_i - Y_k)) alpha_t, else
  *                  move_i += 4 alpha_t per coordinate;
- *   clip(x)    = max(-4, min(4, x)).
+ *   clip(x)    = max(-4, min(4, x));
+ *   d2^b       the power rounded to the nearest double (evaluated in
+ *              quadruple precision, then rounded), so that the result is one
+ *              defined function of the inputs, whatever library computes it.
  *
  * splitmix64: state s = seed + (t * 2^40 + e * 2^4 + p + 1) * 0x9E3779B97F4A7C15
  * (mod 2^64), then the SplitMix64 finaliser (xor-shift 30, multiply by
@@ -558,6 +563,9 @@ uint64_t oracle_splitmix64_next(uint64_t state) { return sm64_mix(state + 0x9E37
 
 static double clip4(double x) { return x > 4.0 ? 4.0 : (x < -4.0 ? -4.0 : x); }
 
+/* x^y rounded to nearest: the quadruple-precision power (about 113 bits) rounded to double */
+static double pow_rn(double x, double y) { return (double)powq((__float128)x, (__float128)y); }
+
 int oracle_umap_layout(const int64_t *indptr, const int32_t *indices, const float *weights, int64_t n, int dim,
                        double *Y, int n_epochs, double a, double b, double gamma, double alpha0, int neg,
                        uint64_t seed) {
@@ -569,9 +577,8 @@ int oracle_umap_layout(const int64_t *indptr, const int32_t *indices, const floa
     double *eps = (double *)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
     double *next = (double *)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
     double *Y0 = (double *)malloc(sizeof(double) * (size_t)n * dim);
-    double *mv = (double *)malloc(sizeof(double) * (size_t)dim);
-    if (!eps || !next || !Y0 || !mv) {
-        free(eps); free(next); free(Y0); free(mv);
+    if (!eps || !next || !Y0) {
+        free(eps); free(next); free(Y0);
         return -1;
     }
     for (int64_t e = 0; e < nnz; ++e) {
@@ -582,8 +589,11 @@ int oracle_umap_layout(const int64_t *indptr, const int32_t *indices, const floa
     for (int t = 0; t < n_epochs; ++t) {
         double alpha = alpha0 * (1.0 - (double)t / (double)n_epochs);
         memcpy(Y0, Y, sizeof(double) * (size_t)n * dim);
+        /* vertex i reads only Y0 and writes only Y_i and its own row's next[] */
+#pragma omp parallel for schedule(dynamic, 512)
         for (int64_t i = 0; i < n; ++i) {
             const double *yi = Y0 + i * dim;
+            double mv[dim];
             for (int c = 0; c < dim; ++c) mv[c] = 0.0;
             for (int64_t e = indptr[i]; e < indptr[i + 1]; ++e) {
                 if (eps[e] < 0.0 || next[e] > (double)t) continue;
@@ -592,7 +602,10 @@ int oracle_umap_layout(const int64_t *indptr, const int32_t *indices, const floa
                 double d2 = 0.0;
                 for (int c = 0; c < dim; ++c) d2 = d2 + (yi[c] - yj[c]) * (yi[c] - yj[c]);
                 double g = 0.0;
-                if (d2 > 0.0) g = (-2.0 * a * b * pow(d2, b - 1.0)) / (a * pow(d2, b) + 1.0);
+                if (d2 > 0.0) {
+                    double pb = pow_rn(d2, b);
+                    g = (-2.0 * a * b * (pb / d2)) / (a * pb + 1.0);
+                }
                 for (int c = 0; c < dim; ++c) mv[c] = mv[c] + clip4(g * (yi[c] - yj[c])) * alpha;
                 for (int p = 0; p < neg; ++p) {
                     uint64_t st = seed + ((uint64_t)t * (1ull << 40) + (uint64_t)e * 16ull + (uint64_t)p + 1ull) *
@@ -603,7 +616,7 @@ int oracle_umap_layout(const int64_t *indptr, const int32_t *indices, const floa
                     double dk = 0.0;
                     for (int c = 0; c < dim; ++c) dk = dk + (yi[c] - yk[c]) * (yi[c] - yk[c]);
                     if (dk > 0.0) {
-                        double gr = (2.0 * gamma * b) / ((0.001 + dk) * (a * pow(dk, b) + 1.0));
+                        double gr = (2.0 * gamma * b) / ((0.001 + dk) * (a * pow_rn(dk, b) + 1.0));
                         for (int c = 0; c < dim; ++c) mv[c] = mv[c] + clip4(gr * (yi[c] - yk[c])) * alpha;
                     } else {
                         for (int c = 0; c < dim; ++c) mv[c] = mv[c] + 4.0 * alpha;
@@ -613,6 +626,6 @@ int oracle_umap_layout(const int64_t *indptr, const int32_t *indices, const floa
             for (int c = 0; c < dim; ++c) Y[i * dim + c] = yi[c] + mv[c];
         }
     }
-    free(eps); free(next); free(Y0); free(mv);
+    free(eps); free(next); free(Y0);
     return 0;
 }

@@ -15,6 +15,7 @@ torch's current stream.  Functions mirror the C calls:
   (``rsc_edistance_*``)
 * :mod:`.pca`             -> the sparse PCA that produces the embedding
   (``rsc_pca``, ``rsc_pca_covariance``)
+* :mod:`.umap`            -> the UMAP layout of the graph (``rsc_umap_layout``)
 """
 
 from __future__ import annotations
@@ -32,7 +33,7 @@ __all__ = [
     "RSC_FP32", "RSC_BF16", "RSC_FP8_E4M3", "RSC_EUCLIDEAN", "RSC_COSINE", "abi_version", "knn_batched", "knn_batched_autotune",
     "knn_batched_workspace_bytes", "Router", "partition_kmeans", "partition_lists", "partition_labels",
     "knn_probed", "knn_routed", "edistance_groups", "edistance_sums", "edistance_pairwise", "edistance_onesided",
-    "pca", "pca_covariance",
+    "pca", "pca_covariance", "umap_layout", "UMAP_A", "UMAP_B",
 ]
 
 
@@ -263,3 +264,4 @@ from .routed import (Router, knn_probed, knn_routed, partition_kmeans, partition
 from .edistance import (edistance_groups, edistance_onesided, edistance_pairwise,  # noqa: E402
                         edistance_sums)
 from .pca import pca, pca_covariance  # noqa: E402
+from .umap import UMAP_A, UMAP_B, umap_layout  # noqa: E402

@@ -107,6 +107,9 @@ SIGNATURES = {
     "rsc_pca_workspace_bytes": (_SZ, [_I64, _I32, _I32]),
     "rsc_pca_covariance": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _P, _SZ, _P]),
     "rsc_pca": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _I32, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    "rsc_umap_workspace_bytes": (_SZ, [_I64, _I64, _I32, _I32]),
+    "rsc_umap_layout": (ctypes.c_int, [_P, _P, _P, _I64, _I64, _I32, _P, _I32, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double, _I32, _U64, _P, _SZ, _P]),
     "rsc_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "rsc_profile_reset": (ctypes.c_int, []),
     "rsc_profile_get": (ctypes.c_int, [ctypes.c_char_p, _P, _P]),

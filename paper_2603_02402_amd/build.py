@@ -41,9 +41,16 @@ COMMON = [
 ]
 
 
+# Sources whose arithmetic must round every product and sum on its own: the
+# UMAP layout reproduces a sequential float64 evaluation bit for bit, and the
+# header definitions of the rounded intrinsics would otherwise be contracted
+# into fused multiply-adds after inlining.
+PER_FILE = {"umap.hip": ["-ffp-contract=off"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ_DIR, os.path.basename(src) + ".o")
-    cmd = [_hipcc(), *COMMON, "-c", src, "-o", obj]
+    cmd = [_hipcc(), *COMMON, *PER_FILE.get(os.path.basename(src), []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stderr}")

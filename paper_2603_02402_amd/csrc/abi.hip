@@ -563,6 +563,23 @@ int rsc_pca(const int64_t *indptr, const int32_t *indices, const float *data, in
                    static_cast<hipStream_t>(stream));
 }
 
+size_t rsc_umap_workspace_bytes(int64_t n, int64_t nnz, int32_t dim, int32_t neg) {
+    return umap_workspace_bytes(n, nnz, dim, neg);
+}
+
+int rsc_umap_layout(const int64_t *indptr, const int32_t *indices, const float *weights, int64_t n, int64_t nnz,
+                    int32_t dim, float *Y, int32_t n_epochs, double a, double b, double gamma, double alpha0,
+                    int32_t neg, uint64_t seed, void *workspace, size_t workspace_bytes, void *stream) {
+    clear_error();
+    if (!aligned(indptr, 8) || !aligned(indices, 4) || !aligned(weights, 4) || !aligned(Y, 4) ||
+        !aligned(workspace, 256)) {
+        set_error("misaligned array or workspace");
+        return RSC_ERR_INVALID_ARG;
+    }
+    return umap_layout(indptr, indices, weights, n, nnz, dim, Y, n_epochs, a, b, gamma, alpha0, neg, seed, workspace,
+                       workspace_bytes, static_cast<hipStream_t>(stream));
+}
+
 int rsc_profile_enable(int enable) {
     Profiler &p = profiler();
     std::lock_guard<std::mutex> lock(p.mu);

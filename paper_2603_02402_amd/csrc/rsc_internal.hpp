@@ -224,6 +224,13 @@ int pca_covariance(const int64_t *indptr, const int32_t *indices, const float *d
 int pca_run(const int64_t *indptr, const int32_t *indices, const float *data, int64_t n, int p, int k, double *mean,
             double *cov, double *evals, double *loadings, float *Z, void *ws, size_t ws_bytes, hipStream_t s);
 
+// ---- UMAP layout (umap.hip) -----------------------------------------------
+
+size_t umap_workspace_bytes(int64_t n, int64_t nnz, int dim, int neg);
+int umap_layout(const int64_t *indptr, const int32_t *indices, const float *weights, int64_t n, int64_t nnz,
+                int dim, float *Y, int n_epochs, double a, double b, double gamma, double alpha0, int neg,
+                uint64_t seed, void *ws, size_t ws_bytes, hipStream_t s);
+
 // ---- graph stages (graph.hip) --------------------------------------------
 
 size_t graph_workspace_bytes(int64_t n, int k);

@@ -1,0 +1,489 @@
+// UMAP layout of the fuzzy graph: edge-sampled stochastic gradient descent
+// on the cross-entropy between the graph's weights and the embedding's
+// similarities q(d2) = 1 / (1 + a d2^b) (the layout step of UMAP, the
+// embedding method the paper runs on this graph).
+//
+// Reading (deterministic by construction):
+//   * edge e of weight w_e is due every w_max / w_e epochs (never if
+//     w_e < w_max / n_epochs), first at epoch w_max / w_e;
+//   * within an epoch every move is computed from the embedding at the start
+//     of the epoch; vertex i sums the moves of the edges of its own CSR row,
+//     in row order, and the sums are applied at the end of the epoch (the
+//     symmetric graph holds each edge in both rows, so both ends move);
+//   * a due edge (i, j) attracts i towards j by clip(g (y_i - y_j)) alpha_t
+//     with g = -2 a b (d2^b / d2) / (a d2^b + 1) (0 for d2 = 0), then draws `neg`
+//     vertices k from a counter-based SplitMix64 (state seed + (t 2^40 + e 16
+//     + p + 1) 0x9E3779B97F4A7C15) and repels i from each (k != i) by
+//     clip(g' (y_i - y_k)) alpha_t, g' = 2 gamma b / ((0.001 + d2)(a d2^b + 1)),
+//     or by 4 alpha_t per coordinate when the points coincide;
+//   * clip to [-4, 4]; alpha_t = alpha0 (1 - t / n_epochs).
+// The embedding is kept in float64 and every sum runs in the order stated,
+// with explicitly rounded operations (no fused multiply-adds), and the power
+// d2^b is the correctly rounded one (double-double evaluation), so the result
+// is the same function of the inputs as any sequential implementation that
+// follows these steps: the dynamics amplify a one-ulp difference in a power
+// into visibly different layouts within tens of epochs.
+//
+// One epoch, edge-parallel where the work is:
+//   1. count the due edges of each tile of 4096 edges;
+//   2. exclusive scan of the tile counts (one block);
+//   3. rank the due edges within each tile (wave ballots, in edge order) and
+//      write the list of due edges in CSR order -- those of one vertex form
+//      one contiguous range -- the position of every edge in that list, and
+//      the due edges' next-sample epochs;
+//   4. terms: one thread per (due edge, sample) -- the attraction and each
+//      negative sample -- computes its clipped, scaled move (the powers and
+//      the random gathers: nearly all of the arithmetic);
+//   5. sums: each vertex adds its terms in row order (staged through LDS by
+//      the wave of 64 vertices that holds it), skipping the negative samples
+//      that drew the vertex itself (marked by the term pass), and writes the
+//      new position (float64 embeddings ping-pong between two buffers).
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "crpow.hpp"
+#include "rsc_internal.hpp"
+
+// Every product and sum below is rounded on its own, as written.
+#pragma clang fp contract(off)
+
+namespace rsc {
+namespace {
+
+constexpr int kMaxDim = 8;
+constexpr int kMaxNeg = 64;
+constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
+constexpr int kTileSteps = 16;                  // 256-edge steps per tile
+constexpr int64_t kTile = 256 * kTileSteps;     // edges per tile of the compaction
+
+__device__ __forceinline__ uint64_t sm64_mix(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// x mod n for x < 2^53, n < 2^31, from inv_n = 1/n rounded: the float64
+// quotient is within 3 of the true one, and the integer remainder is then
+// moved into [0, n) (the same residue as an integer division gives).
+__device__ __forceinline__ int64_t mod_n(uint64_t x, int64_t n, double inv_n) {
+    const int64_t q = (int64_t)__builtin_floor(__dmul_rn((double)x, inv_n));
+    int64_t r = (int64_t)x - q * n;
+    while (r < 0) r += n;
+    while (r >= n) r -= n;
+    return r;
+}
+
+// Negative sample p of edge e in epoch t.
+__device__ __forceinline__ int64_t negative(uint64_t seed, int t, int64_t e, int p, int64_t n, double inv_n) {
+    const uint64_t st = seed + ((uint64_t)t * (1ull << 40) + (uint64_t)e * 16ull + (uint64_t)p + 1ull) * kGolden;
+    return mod_n(sm64_mix(st) >> 11, n, inv_n);
+}
+
+__device__ __forceinline__ double clip4(double x) { return x > 4.0 ? 4.0 : (x < -4.0 ? -4.0 : x); }
+
+__device__ __forceinline__ double epoch_alpha(double alpha0, int t, int n_epochs) {
+    return __dmul_rn(alpha0, __dsub_rn(1.0, __ddiv_rn((double)t, (double)n_epochs)));
+}
+
+__global__ __launch_bounds__(256) void k_umap_wmax(const float *__restrict__ w, int64_t nnz,
+                                                   uint32_t *__restrict__ max_bits) {
+    __shared__ float part[4];
+    float m = 0.f;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x)
+        m = fmaxf(m, w[e]);
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0)  // weights are >= 0: their bit patterns order as the values
+        atomicMax(max_bits, __float_as_uint(fmaxf(fmaxf(part[0], part[1]), fmaxf(part[2], part[3]))));
+}
+
+__global__ __launch_bounds__(256) void k_umap_init(const float *__restrict__ w, int64_t nnz,
+                                                   const uint32_t *__restrict__ max_bits, int n_epochs,
+                                                   double *__restrict__ eps, double *__restrict__ next,
+                                                   const float *__restrict__ Yin, int64_t ny,
+                                                   double *__restrict__ Y) {
+    const double wmax = (double)__uint_as_float(*max_bits);
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
+        const double we = (double)w[e];
+        const double v = (we > 0.0 && we >= wmax / (double)n_epochs) ? wmax / we : -1.0;
+        eps[e] = v;
+        next[e] = v;
+    }
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < ny; e += (int64_t)gridDim.x * blockDim.x)
+        Y[e] = (double)Yin[e];
+}
+
+// Row of every edge (the vertex whose move it makes).
+__global__ __launch_bounds__(256) void k_umap_rows(const int64_t *__restrict__ indptr, int64_t n,
+                                                   uint32_t *__restrict__ erow) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        for (int64_t e = indptr[i]; e < indptr[i + 1]; ++e) erow[e] = (uint32_t)i;
+}
+
+__device__ __forceinline__ bool is_due(const double *__restrict__ eps, const double *__restrict__ next, int64_t e,
+                                       int64_t nnz, int t) {
+    return e < nnz && !(eps[e] < 0.0) && !(next[e] > (double)t);
+}
+
+// Due edges of each tile.
+__global__ __launch_bounds__(256) void k_umap_count(const double *__restrict__ eps, const double *__restrict__ next,
+                                                    int64_t nnz, int t, uint32_t *__restrict__ tile_cnt) {
+    __shared__ uint32_t part[4];
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    uint32_t c = 0;
+#pragma unroll 4
+    for (int k = 0; k < kTileSteps; ++k) c += is_due(eps, next, base + k * 256 + threadIdx.x, nnz, t) ? 1u : 0u;
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) tile_cnt[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
+}
+
+// Exclusive scan of the T tile counts; one block of 1024 threads.
+__global__ __launch_bounds__(1024) void k_umap_tile_scan(const uint32_t *__restrict__ cnt, int64_t T,
+                                                         uint32_t *__restrict__ off) {
+    __shared__ uint32_t part[1024];
+    const int tid = threadIdx.x;
+    const int64_t per = (T + 1023) / 1024;
+    const int64_t lo = std::min<int64_t>(T, tid * per), hi = std::min<int64_t>(T, lo + per);
+    uint32_t sum = 0;
+    for (int64_t i = lo; i < hi; ++i) sum += cnt[i];
+    part[tid] = sum;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        const uint32_t v = tid >= d ? part[tid - d] : 0u;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[tid] - sum;
+    for (int64_t i = lo; i < hi; ++i) {
+        off[i] = run;
+        run += cnt[i];
+    }
+}
+
+// Rank the due edges of a tile in edge order: pos[e] = due edges before e;
+// list[pos[e]] = e for a due edge, whose next-sample epoch advances by eps.
+// The last tile writes the total to pos[nnz].
+__global__ __launch_bounds__(256) void k_umap_scatter(const double *__restrict__ eps, double *__restrict__ next,
+                                                      int64_t nnz, int t, const uint32_t *__restrict__ tile_off,
+                                                      uint32_t *__restrict__ pos, uint32_t *__restrict__ list) {
+    __shared__ uint32_t part[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    uint32_t off = tile_off[blockIdx.x];
+    for (int k = 0; k < kTileSteps; ++k) {
+        const int64_t e = base + k * 256 + threadIdx.x;
+        const bool due = is_due(eps, next, e, nnz, t);
+        const uint64_t mask = __ballot(due);
+        if (lane == 0) part[wv] = (uint32_t)__popcll(mask);
+        __syncthreads();
+        uint32_t before = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull)), step = 0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            before += v < wv ? part[v] : 0u;
+            step += part[v];
+        }
+        if (e < nnz) pos[e] = off + before;
+        if (due) {
+            list[off + before] = (uint32_t)e;
+            next[e] = __dadd_rn(next[e], eps[e]);
+        }
+        off += step;
+        __syncthreads();  // part is rewritten by the next step
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) pos[nnz] = off;
+}
+
+// One thread per (due edge j, sample p): p = 0 the attraction, p >= 1 the
+// negative sample p - 1.  The move goes to terms[(j (1 + neg) + p) dim + c];
+// a negative sample that drew the vertex itself writes a NaN in coordinate 0,
+// which the sum skips (moves of finite positions are always finite).
+__global__ __launch_bounds__(256) void k_umap_terms(const uint32_t *__restrict__ list,
+                                                    const uint32_t *__restrict__ count,
+                                                    const uint32_t *__restrict__ erow,
+                                                    const int32_t *__restrict__ indices, int64_t n, int dim,
+                                                    const double *__restrict__ Y0, int t, int n_epochs, double a,
+                                                    double b, double gamma, double alpha0, int neg, uint64_t seed,
+                                                    double inv_n, double *__restrict__ terms) {
+    const double alpha = epoch_alpha(alpha0, t, n_epochs);
+    const double ab2 = __dmul_rn(__dmul_rn(-2.0, a), b);  // -2 a b
+    const double gb2 = __dmul_rn(__dmul_rn(2.0, gamma), b);
+    const int per = 1 + neg;
+    const int64_t total = (int64_t)(*count) * per;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < total; s += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = s / per;
+        const int p = (int)(s - j * per);
+        const int64_t e = list[j];
+        const int64_t i = erow[e];
+        const int64_t other = p == 0 ? (int64_t)indices[e] : negative(seed, t, e, p - 1, n, inv_n);
+        double *out = terms + s * dim;
+        if (p > 0 && other == i) {
+            out[0] = __builtin_nan("");
+            continue;
+        }
+        double df[kMaxDim];
+        double d2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < kMaxDim; ++c)
+            if (c < dim) {
+                df[c] = __dsub_rn(Y0[i * dim + c], Y0[other * dim + c]);
+                d2 = __dadd_rn(d2, __dmul_rn(df[c], df[c]));
+            }
+        // one power per slot, whichever the kind of sample (a wave holds both)
+        const double pb = d2 > 0.0 ? crp::pow_rn(d2, b) : 0.0;
+        if (p > 0 && !(d2 > 0.0)) {  // repulsion from the same position
+#pragma unroll
+            for (int c = 0; c < kMaxDim; ++c)
+                if (c < dim) out[c] = __dmul_rn(4.0, alpha);
+            continue;
+        }
+        double g;
+        if (p == 0)
+            g = d2 > 0.0 ? __ddiv_rn(__dmul_rn(ab2, __ddiv_rn(pb, d2)), __dadd_rn(__dmul_rn(a, pb), 1.0)) : 0.0;
+        else
+            g = __ddiv_rn(gb2, __dmul_rn(__dadd_rn(0.001, d2), __dadd_rn(__dmul_rn(a, pb), 1.0)));
+#pragma unroll
+        for (int c = 0; c < kMaxDim; ++c)
+            if (c < dim) out[c] = __dmul_rn(clip4(__dmul_rn(g, df[c])), alpha);
+    }
+}
+
+// One wave per 64 consecutive vertices, lane L for vertex i0 + L.  The due
+// edges of vertex i are list[pos[indptr[i]] .. pos[indptr[i+1]]), in row
+// order, and their terms the slots [pos[indptr[i]] (1 + neg),
+// pos[indptr[i+1]] (1 + neg)), so the wave's slots form one range: it is
+// staged through LDS in coalesced chunks, and each lane adds its own
+// vertex's slots in order.
+constexpr int kSumLds = 1024;  // float64 terms staged per chunk
+constexpr int kSumUnroll = 8;  // slots read from LDS per round, then added in order
+
+template <int DIMS>  // coordinates held in registers: dim <= DIMS
+__global__ __launch_bounds__(64) void k_umap_sum(const int64_t *__restrict__ indptr,
+                                                 const uint32_t *__restrict__ pos,
+                                                 const double *__restrict__ terms, int64_t n, int dim,
+                                                 const double *__restrict__ Y0, double *__restrict__ Y1, int neg) {
+    __shared__ double buf[kSumLds];
+    const int per = 1 + neg;
+    const int lane = threadIdx.x;
+    const int64_t chunk = kSumLds / dim;  // slots per chunk
+    for (int64_t i0 = (int64_t)blockIdx.x * 64; i0 < n; i0 += (int64_t)gridDim.x * 64) {
+        const int64_t i = i0 + lane;
+        const int64_t S0 = (int64_t)pos[indptr[i0]] * per;
+        const int64_t S1 = (int64_t)pos[indptr[std::min<int64_t>(i0 + 64, n)]] * per;
+        int64_t lo = 0, hi = 0;
+        if (i < n) {
+            lo = (int64_t)pos[indptr[i]] * per;
+            hi = (int64_t)pos[indptr[i + 1]] * per;
+        }
+        double mv[DIMS];
+#pragma unroll
+        for (int c = 0; c < DIMS; ++c) mv[c] = 0.0;
+        for (int64_t c0 = S0; c0 < S1; c0 += chunk) {
+            const int64_t c1 = std::min<int64_t>(c0 + chunk, S1);
+            const int64_t nd = (c1 - c0) * dim;
+            double r[kSumLds / 64];  // all loads of the chunk in flight at once
+#pragma unroll
+            for (int u = 0; u < kSumLds / 64; ++u) {
+                const int64_t q = (int64_t)u * 64 + lane;
+                r[u] = q < nd ? terms[c0 * dim + q] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < kSumLds / 64; ++u) buf[u * 64 + lane] = r[u];
+            __syncthreads();
+            const int64_t s1 = std::min<int64_t>(hi, c1);
+            for (int64_t sb = std::max<int64_t>(lo, c0); sb < s1; sb += kSumUnroll) {
+                double v[kSumUnroll][DIMS];
+#pragma unroll
+                for (int u = 0; u < kSumUnroll; ++u) {
+                    const double *tm = buf + (sb + u - c0) * dim;
+#pragma unroll
+                    for (int c = 0; c < DIMS; ++c) v[u][c] = (sb + u < s1 && c < dim) ? tm[c] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < kSumUnroll; ++u) {
+                    if (sb + u >= s1 || __builtin_isnan(v[u][0])) continue;  // NaN: a sample that drew i itself
+#pragma unroll
+                    for (int c = 0; c < DIMS; ++c)
+                        if (c < dim) mv[c] = __dadd_rn(mv[c], v[u][c]);
+                }
+            }
+            __syncthreads();  // buf is refilled by the next chunk
+        }
+        if (i < n) {
+#pragma unroll
+            for (int c = 0; c < DIMS; ++c)
+                if (c < dim) Y1[i * dim + c] = __dadd_rn(Y0[i * dim + c], mv[c]);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_umap_out(const double *__restrict__ Y, int64_t ny, float *__restrict__ out) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < ny; e += (int64_t)gridDim.x * blockDim.x)
+        out[e] = (float)Y[e];
+}
+
+__global__ void k_umap_zero(uint32_t *x, int32_t *err) {
+    *x = 0u;
+    *err = 0;
+}
+
+// indptr ascending from 0 to nnz, indices in [0, n), weights finite and >= 0.
+__global__ __launch_bounds__(256) void k_umap_check(const int64_t *__restrict__ indptr,
+                                                    const int32_t *__restrict__ indices,
+                                                    const float *__restrict__ w, const float *__restrict__ Y,
+                                                    int64_t n, int64_t nnz, int64_t ny, int32_t *__restrict__ err) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = indptr[i];
+        if (v < 0 || v > nnz || (i == 0 && v != 0) || (i == n && v != nnz) || (i < n && indptr[i + 1] < v))
+            atomicOr(err, 1);
+    }
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
+        if (indices[e] < 0 || indices[e] >= n) atomicOr(err, 2);
+        if (!(w[e] >= 0.f) || isinf(w[e])) atomicOr(err, 4);
+    }
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < ny; e += (int64_t)gridDim.x * blockDim.x)
+        if (!isfinite(Y[e])) atomicOr(err, 8);
+}
+
+struct Ws {
+    double *eps, *next, *terms, *Y0, *Y1;
+    uint32_t *pos, *list, *erow, *tile_cnt, *tile_off, *maxb;
+    int32_t *err;
+};
+
+int64_t n_tiles(int64_t nnz) { return std::max<int64_t>(1, (nnz + kTile - 1) / kTile); }
+
+size_t carve(int64_t n, int64_t nnz, int dim, int neg, void *ws, Ws *w) {
+    const size_t m = (size_t)std::max<int64_t>(nnz, 1);
+    const size_t T = (size_t)n_tiles(nnz);
+    Carver cv(ws);
+    double *eps = cv.take<double>(m);
+    double *next = cv.take<double>(m);
+    uint32_t *pos = cv.take<uint32_t>(m + 1);
+    uint32_t *list = cv.take<uint32_t>(m);
+    uint32_t *erow = cv.take<uint32_t>(m);
+    double *terms = cv.take<double>(m * (size_t)(1 + neg) * (size_t)dim);
+    double *Y0 = cv.take<double>((size_t)n * dim);
+    double *Y1 = cv.take<double>((size_t)n * dim);
+    uint32_t *tile_cnt = cv.take<uint32_t>(T);
+    uint32_t *tile_off = cv.take<uint32_t>(T);
+    uint32_t *maxb = cv.take<uint32_t>(1);
+    int32_t *err = cv.take<int32_t>(1);
+    if (w) *w = Ws{eps, next, terms, Y0, Y1, pos, list, erow, tile_cnt, tile_off, maxb, err};
+    return cv.used;
+}
+
+unsigned grid(int64_t m) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(16384, (m + 255) / 256)); }
+
+bool shape_ok(int64_t n, int64_t nnz, int dim, int neg) {
+    return n >= 1 && n <= INT32_MAX && nnz >= 0 && nnz < (int64_t)UINT32_MAX && dim >= 1 && dim <= kMaxDim &&
+           neg >= 0 && neg <= kMaxNeg;
+}
+
+}  // namespace
+
+size_t umap_workspace_bytes(int64_t n, int64_t nnz, int dim, int neg) {
+    if (!shape_ok(n, nnz, dim, neg)) return 0;
+    return carve(n, nnz, dim, neg, nullptr, nullptr);
+}
+
+int umap_layout(const int64_t *indptr, const int32_t *indices, const float *weights, int64_t n, int64_t nnz,
+                int dim, float *Y, int n_epochs, double a, double b, double gamma, double alpha0, int neg,
+                uint64_t seed, void *ws, size_t ws_bytes, hipStream_t s) {
+    if (!indptr || !Y || (nnz > 0 && (!indices || !weights))) {
+        set_error("umap_layout: null argument");
+        return RSC_ERR_INVALID_ARG;
+    }
+    if (n < 1 || nnz < 0 || dim < 1 || dim > kMaxDim || n_epochs < 1 || neg < 0 || neg > kMaxNeg ||
+        !(a > 0.0) || !(b > 0.0) || !(gamma >= 0.0) || !(alpha0 > 0.0)) {
+        set_error("umap_layout: need n >= 1, 1 <= dim <= 8, n_epochs >= 1, 0 <= neg <= 64, a, b, alpha0 > 0, "
+                  "gamma >= 0");
+        return RSC_ERR_INVALID_ARG;
+    }
+    if (!shape_ok(n, nnz, dim, neg) || n_epochs >= (1 << 23)) {
+        set_error("umap_layout: supports n < 2^31, nnz < 2^32 - 1 and epochs < 2^23");
+        return RSC_ERR_UNSUPPORTED;
+    }
+    Ws w;
+    const size_t need = carve(n, nnz, dim, neg, nullptr, nullptr);
+    if (need == 0 || !ws || ws_bytes < need) {
+        set_error("umap_layout: workspace too small");
+        return RSC_ERR_WORKSPACE;
+    }
+    carve(n, nnz, dim, neg, ws, &w);
+    const int64_t ny = n * dim;
+    int st;
+    hipLaunchKernelGGL(k_umap_zero, dim3(1), dim3(1), 0, s, w.maxb, w.err);
+    hipLaunchKernelGGL(k_umap_check, dim3(grid(std::max(std::max(nnz, n + 1), ny))), dim3(256), 0, s, indptr,
+                       indices, weights, (const float *)Y, n, nnz, ny, w.err);
+    int32_t host_err = 0;
+    if ((st = launch_status("umap check")) != RSC_OK ||
+        (st = hip_status(hipMemcpyAsync(&host_err, w.err, 4, hipMemcpyDeviceToHost, s), "read check")) != RSC_OK ||
+        (st = hip_status(hipStreamSynchronize(s), "synchronise")) != RSC_OK)
+        return st;
+    if (host_err & 8) {
+        set_error("umap_layout: a non-finite initial position");
+        return RSC_ERR_INVALID_ARG;
+    }
+    if (host_err) {
+        set_error(host_err & 1 ? "umap_layout: indptr is not an ascending list from 0 to nnz"
+                               : host_err & 2 ? "umap_layout: a column index outside [0, n)"
+                                              : "umap_layout: a negative or non-finite weight");
+        return RSC_ERR_BAD_GRAPH;
+    }
+    {
+        ScopedTimer tm("umap_init", s);
+        hipLaunchKernelGGL(k_umap_wmax, dim3((unsigned)std::min<int64_t>(1024, (nnz + 255) / 256 + 1)), dim3(256), 0,
+                           s, weights, nnz, w.maxb);
+        hipLaunchKernelGGL(k_umap_init, dim3(grid(std::max(nnz, ny))), dim3(256), 0, s, weights, nnz,
+                           (const uint32_t *)w.maxb, n_epochs, w.eps, w.next, (const float *)Y, ny, w.Y0);
+        hipLaunchKernelGGL(k_umap_rows, dim3(grid(n)), dim3(256), 0, s, indptr, n, w.erow);
+    }
+    if ((st = launch_status("umap init")) != RSC_OK) return st;
+    const int64_t T = n_tiles(nnz);
+    const unsigned g_terms = grid(nnz * (1 + neg));
+    const unsigned g_sum = (unsigned)std::min<int64_t>(32768, (n + 63) / 64);
+    {
+        ScopedTimer tm("umap_epochs", s);
+        for (int t = 0; t < n_epochs; ++t) {
+            {
+                ScopedTimer td("umap_due", s);
+                hipLaunchKernelGGL(k_umap_count, dim3((unsigned)T), dim3(256), 0, s, (const double *)w.eps,
+                                   (const double *)w.next, nnz, t, w.tile_cnt);
+                hipLaunchKernelGGL(k_umap_tile_scan, dim3(1), dim3(1024), 0, s, (const uint32_t *)w.tile_cnt, T,
+                                   w.tile_off);
+                hipLaunchKernelGGL(k_umap_scatter, dim3((unsigned)T), dim3(256), 0, s, (const double *)w.eps, w.next,
+                                   nnz, t, (const uint32_t *)w.tile_off, w.pos, w.list);
+            }
+            {
+                ScopedTimer tt("umap_terms", s);
+                hipLaunchKernelGGL(k_umap_terms, dim3(g_terms), dim3(256), 0, s, (const uint32_t *)w.list,
+                                   (const uint32_t *)(w.pos + nnz), (const uint32_t *)w.erow, indices, n, dim,
+                                   (const double *)w.Y0, t, n_epochs, a, b, gamma, alpha0, neg, seed,
+                                   1.0 / (double)n, w.terms);
+            }
+            {
+                ScopedTimer tsum("umap_sum", s);
+                if (dim <= 2)
+                    hipLaunchKernelGGL(k_umap_sum<2>, dim3(g_sum), dim3(64), 0, s, indptr, (const uint32_t *)w.pos,
+                                       (const double *)w.terms, n, dim, (const double *)w.Y0, w.Y1, neg);
+                else
+                    hipLaunchKernelGGL(k_umap_sum<kMaxDim>, dim3(g_sum), dim3(64), 0, s, indptr,
+                                       (const uint32_t *)w.pos, (const double *)w.terms, n, dim,
+                                       (const double *)w.Y0, w.Y1, neg);
+            }
+            std::swap(w.Y0, w.Y1);
+        }
+    }
+    if ((st = launch_status("umap epochs")) != RSC_OK) return st;
+    hipLaunchKernelGGL(k_umap_out, dim3(grid(ny)), dim3(256), 0, s, (const double *)w.Y0, ny, Y);
+    return launch_status("umap output");
+}
+
+}  // namespace rsc

@@ -353,3 +353,10 @@ def sparse_expression(n: int | None = None, p: int | None = None, density: float
     indptr = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(counts, out=indptr[1:])
     return indptr, np.concatenate(ind_parts), np.concatenate(val_parts)
+
+
+# Initial embedding for the UMAP layout: UMAP's random initialisation,
+# coordinates uniform on [-10, 10].
+def umap_init(n: int, dim: int = 2, seed: int = 31) -> np.ndarray:
+    """``float32 [n, dim]`` uniform on [-10, 10]."""
+    return _rng(seed).uniform(-10.0, 10.0, size=(n, dim)).astype(np.float32)

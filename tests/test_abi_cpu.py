@@ -277,3 +277,34 @@ def test_edistance_groups_validation(lib):
     assert lib.rsc_edistance_groups(FAKE, 0, 3, FAKE, FAKE, FAKE, 1 << 20, None) == -1
     assert lib.rsc_edistance_groups(FAKE, 10, 0, FAKE, FAKE, FAKE, 1 << 20, None) == -1
     assert "edistance_groups" in _err(lib)
+
+
+def test_umap_validation(lib):
+    def call(n=100, nnz=1000, dim=2, n_epochs=200, a=0.58, b=1.33, gamma=1.0, alpha0=1.0, neg=5, ws=1 << 30):
+        return lib.rsc_umap_layout(FAKE, FAKE, FAKE, n, nnz, dim, FAKE, n_epochs, a, b, gamma, alpha0, neg,
+                                   ctypes.c_uint64(0), FAKE, ws, None)
+
+    assert lib.rsc_umap_layout(None, FAKE, FAKE, 100, 1000, 2, FAKE, 200, 0.58, 1.33, 1.0, 1.0, 5,
+                               ctypes.c_uint64(0), FAKE, 1 << 30, None) == -1 and "null" in _err(lib)
+    for bad in (dict(n=0), dict(dim=0), dict(dim=9), dict(n_epochs=0), dict(neg=-1), dict(neg=65), dict(a=0.0),
+                dict(b=-1.0), dict(gamma=-0.5), dict(alpha0=0.0), dict(nnz=-1)):
+        assert call(**bad) == -1, bad
+    assert call(n_epochs=1 << 23) != 0 and "epochs" in _err(lib)
+    assert call(nnz=1 << 32) != 0 and "2^32" in _err(lib)
+    assert call(ws=64) == -7 and "workspace" in _err(lib)
+    assert lib.rsc_umap_workspace_bytes(100, 1000, 9, 5) == 0
+    assert lib.rsc_umap_workspace_bytes(100, 1000, 2, 65) == 0
+    # float64 eps / next, uint32 positions / list / rows, the terms of
+    # every edge's samples and two float64 embeddings
+    assert lib.rsc_umap_workspace_bytes(100, 1000, 2, 5) >= 1000 * (16 + 12 + 6 * 2 * 8) + 2 * 100 * 2 * 8
+
+
+def test_umap_default_curve_is_the_fit():
+    # the binding's default (a, b) is the least-squares fit for min_dist 0.5,
+    # spread 1 that the oracle computes
+    from oracle import umap as ou
+
+    import paper_2603_02402_amd as rsc
+
+    a, b = ou.fit_ab(0.5, 1.0)
+    assert abs(rsc.UMAP_A - a) < 1e-6 * a and abs(rsc.UMAP_B - b) < 1e-6 * b
