@@ -265,7 +265,7 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 matrix
 PEAK_FP64_VECTOR_OPS = 39.3
 # float64 add / multiply / fma instructions of one slot of k_umap_terms (the
 # straight-line correctly rounded power plus the move), counted in its assembly
-UMAP_TERM_FP64_OPS = 619
+UMAP_TERM_FP64_OPS = 394
 
 
 def edistance_form(args, rsc) -> dict:

@@ -142,12 +142,107 @@ __device__ __forceinline__ dd exp_dd(dd E, int *n_out) {
     return add_d(q, 1.0);
 }
 
-// x^y rounded to nearest (x > 0 finite, y finite, result normal)
+// x^y rounded to nearest (x > 0 finite, y finite, result normal), by the
+// series above alone (no tables).
 __device__ __forceinline__ double pow_rn(double x, double y) {
     const dd L = log_dd(x);
     const dd E = mul_d(L, y);
     int n;
     const dd v = exp_dd(E, &n);
+    return __builtin_ldexp(v.h + v.l, n);
+}
+
+// ---- table-driven form ------------------------------------------------------
+//
+// log: x = 2^e f with f in [1, 2) and the cell c = 1 + (2j + 1)/128 of
+// f (j = floor(64 (f - 1))); with s = (f - c)/(f + c), |s| <= 2^-8,
+// log f = log c + 2 s sum_{i<7} s^(2i) / (2i + 1) (truncation below 2^-110).
+// exp: E = (m / 64) ln 2 + r with m = rint(64 E / ln 2), |r| <= ln2 / 128;
+// exp E = 2^(m div 64) 2^((m mod 64) / 64) (1 + expm1 r), expm1 by its
+// Taylor series to degree 10 (truncation below 2^-107).
+// The 64 values log c_j and the 64 values 2^(k/64) (double-doubles) are made
+// by the series above (make_pow_tables), accurate to about 2^-97.
+
+constexpr int kPowCells = 64;
+
+struct PowTables {
+    dd logc[kPowCells];  // log(1 + (2j + 1)/128)
+    dd exp2[kPowCells];  // 2^(k/64)
+};
+
+// Entry t of the tables (t < 64: log c_t; else 2^((t - 64)/64)).
+__device__ __forceinline__ dd pow_table_entry(int t) {
+    if (t < kPowCells) return log_dd(1.0 + (double)(2 * t + 1) * 0x1p-7);
+    const double kf = (double)(t - kPowCells) * 0x1p-6;  // exact
+    const dd E = mul_d(dd{kLn2Hi, kLn2Lo}, kf);
+    int n;
+    const dd v = exp_dd(E, &n);
+    return {__builtin_ldexp(v.h, n), __builtin_ldexp(v.l, n)};
+}
+
+__device__ __forceinline__ dd log_dd_t(double x, const dd *__restrict__ logc) {
+    int e;
+    double f = __builtin_frexp(x, &e);  // [0.5, 1)
+    f = f * 2.0;                        // [1, 2), exact
+    e = e - 1;
+    const int j = (int)((f - 1.0) * 64.0);  // exact product, 0 .. 63
+    const double c = 1.0 + (double)(2 * j + 1) * 0x1p-7;
+    const double num = f - c;  // exact (f and c within a factor 2)
+    const dd den = two_sum(f, c);
+    const double sh = num / den.h;
+    const double rem = __builtin_fma(-sh, den.h, num) - sh * den.l;
+    const dd s = fast_two_sum(sh, rem / den.h);
+    const dd z = mul(s, s);
+    double t = 1.0 / 13.0;  // terms 4 .. 6, below 2^-60 of the sum: double
+    t = t * z.h + 1.0 / 11.0;
+    t = t * z.h + 1.0 / 9.0;
+    dd p = {t, 0.0};
+#pragma unroll
+    for (int i = 3; i >= 1; --i) p = add(mul(p, z), recip((double)(2 * i + 1)));
+    p = add_d(mul(p, z), 1.0);
+    dd lf = mul(s, p);
+    lf.h = lf.h * 2.0;
+    lf.l = lf.l * 2.0;
+    lf = add(lf, logc[j]);
+    const double ed = (double)e;
+    dd el = two_prod(ed, kLn2Hi);
+    el = add_d(el, ed * kLn2Lo);
+    return add(el, lf);
+}
+
+// exp E = (hi + lo) 2^n
+__device__ __forceinline__ dd exp_dd_t(dd E, const dd *__restrict__ exp2t, int *n_out) {
+    const double mf = __builtin_rint(E.h * 0x1.71547652b82fep6);  // 64 E / ln 2
+    const dd t = two_prod(mf, kLn2Hi * 0x1p-6);
+    const double rh = E.h - t.h;  // exact: E.h within a factor 2 of t.h, or mf = 0
+    dd r = two_sum(rh, E.l);
+    r = add_d(r, -t.l);
+    const dd u = two_prod(mf, kLn2Lo * 0x1p-6);
+    r = add(r, dd{-u.h, -u.l});
+    double w = 1.0 / 3628800.0;  // degrees 6 .. 10: double
+    w = w * r.h + 1.0 / 362880.0;
+    w = w * r.h + 1.0 / 40320.0;
+    w = w * r.h + 1.0 / 5040.0;
+    w = w * r.h + 1.0 / 720.0;
+    dd a = add(mul_d(r, w), recip(120.0));
+    a = add(mul(a, r), recip(24.0));
+    a = add(mul(a, r), recip(6.0));
+    a = add_d(mul(a, r), 0.5);
+    a = add_d(mul(a, r), 1.0);
+    const dd q = mul(a, r);
+    const int m = (int)mf;
+    const int k = m & (kPowCells - 1);
+    *n_out = (m - k) / kPowCells;  // exact division
+    const dd T = exp2t[k];
+    return add(T, mul(q, T));
+}
+
+// x^y rounded to nearest (x > 0 finite, y finite, result normal)
+__device__ __forceinline__ double pow_rn_t(double x, double y, const PowTables &tb) {
+    const dd L = log_dd_t(x, tb.logc);
+    const dd E = mul_d(L, y);
+    int n;
+    const dd v = exp_dd_t(E, tb.exp2, &n);
     return __builtin_ldexp(v.h + v.l, n);
 }
 

@@ -19,13 +19,15 @@
 //   * clip to [-4, 4]; alpha_t = alpha0 (1 - t / n_epochs).
 // The embedding is kept in float64 and every sum runs in the order stated,
 // with explicitly rounded operations (no fused multiply-adds), and the power
-// d2^b is the correctly rounded one (double-double evaluation), so the result
+// d2^b is the correctly rounded one (table-driven double-double evaluation,
+// the tables made on the device by a table-free series), so the result
 // is the same function of the inputs as any sequential implementation that
 // follows these steps: the dynamics amplify a one-ulp difference in a power
 // into visibly different layouts within tens of epochs.
 //
 // One epoch, edge-parallel where the work is:
-//   1. count the due edges of each tile of 4096 edges;
+//   1. count the due edges of each tile of 4096 edges (at epoch 0; later
+//      epochs take the counts that the previous epoch's step 3 made);
 //   2. exclusive scan of the tile counts (one block);
 //   3. rank the due edges within each tile (wave ballots, in edge order) and
 //      write the list of due edges in CSR order -- those of one vertex form
@@ -117,6 +119,17 @@ __global__ __launch_bounds__(256) void k_umap_init(const float *__restrict__ w, 
         Y[e] = (double)Yin[e];
 }
 
+// The power's tables (double-doubles), made on the device by the table-free
+// series: entry t < 64 is log c_t, entry 64 + k is 2^(k/64).
+__global__ __launch_bounds__(128) void k_umap_tables(crp::PowTables *__restrict__ tb) {
+    const int t = threadIdx.x;
+    const crp::dd v = crp::pow_table_entry(t);
+    if (t < crp::kPowCells)
+        tb->logc[t] = v;
+    else
+        tb->exp2[t - crp::kPowCells] = v;
+}
+
 // Row of every edge (the vertex whose move it makes).
 __global__ __launch_bounds__(256) void k_umap_rows(const int64_t *__restrict__ indptr, int64_t n,
                                                    uint32_t *__restrict__ erow) {
@@ -169,17 +182,26 @@ __global__ __launch_bounds__(1024) void k_umap_tile_scan(const uint32_t *__restr
 
 // Rank the due edges of a tile in edge order: pos[e] = due edges before e;
 // list[pos[e]] = e for a due edge, whose next-sample epoch advances by eps.
-// The last tile writes the total to pos[nnz].
+// The last tile writes the total to pos[nnz].  The tile's due edges of the
+// next epoch are counted on the way (into tile_cnt, already consumed by the
+// scan of this epoch).
 __global__ __launch_bounds__(256) void k_umap_scatter(const double *__restrict__ eps, double *__restrict__ next,
                                                       int64_t nnz, int t, const uint32_t *__restrict__ tile_off,
-                                                      uint32_t *__restrict__ pos, uint32_t *__restrict__ list) {
+                                                      uint32_t *__restrict__ pos, uint32_t *__restrict__ list,
+                                                      uint32_t *__restrict__ tile_cnt) {
     __shared__ uint32_t part[4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t base = (int64_t)blockIdx.x * kTile;
     uint32_t off = tile_off[blockIdx.x];
+    uint32_t due_next = 0;
     for (int k = 0; k < kTileSteps; ++k) {
         const int64_t e = base + k * 256 + threadIdx.x;
-        const bool due = is_due(eps, next, e, nnz, t);
+        double ee = -1.0, nx = 0.0;
+        if (e < nnz) {
+            ee = eps[e];
+            nx = next[e];
+        }
+        const bool due = !(ee < 0.0) && !(nx > (double)t);
         const uint64_t mask = __ballot(due);
         if (lane == 0) part[wv] = (uint32_t)__popcll(mask);
         __syncthreads();
@@ -192,12 +214,18 @@ __global__ __launch_bounds__(256) void k_umap_scatter(const double *__restrict__
         if (e < nnz) pos[e] = off + before;
         if (due) {
             list[off + before] = (uint32_t)e;
-            next[e] = __dadd_rn(next[e], eps[e]);
+            nx = __dadd_rn(nx, ee);
+            next[e] = nx;
         }
+        due_next += (!(ee < 0.0) && !(nx > (double)(t + 1))) ? 1u : 0u;
         off += step;
         __syncthreads();  // part is rewritten by the next step
     }
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) pos[nnz] = off;
+    for (int o = 32; o > 0; o >>= 1) due_next += __shfl_xor(due_next, o, 64);
+    if (lane == 0) part[wv] = due_next;
+    __syncthreads();
+    if (threadIdx.x == 0) tile_cnt[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
 }
 
 // One thread per (due edge j, sample p): p = 0 the attraction, p >= 1 the
@@ -210,7 +238,14 @@ __global__ __launch_bounds__(256) void k_umap_terms(const uint32_t *__restrict__
                                                     const int32_t *__restrict__ indices, int64_t n, int dim,
                                                     const double *__restrict__ Y0, int t, int n_epochs, double a,
                                                     double b, double gamma, double alpha0, int neg, uint64_t seed,
-                                                    double inv_n, double *__restrict__ terms) {
+                                                    double inv_n, const crp::PowTables *__restrict__ tables,
+                                                    double *__restrict__ terms) {
+    __shared__ crp::PowTables tb;
+    {
+        static_assert(sizeof(crp::PowTables) == 256 * sizeof(double), "one double per thread");
+        reinterpret_cast<double *>(&tb)[threadIdx.x] = reinterpret_cast<const double *>(tables)[threadIdx.x];
+    }
+    __syncthreads();
     const double alpha = epoch_alpha(alpha0, t, n_epochs);
     const double ab2 = __dmul_rn(__dmul_rn(-2.0, a), b);  // -2 a b
     const double gb2 = __dmul_rn(__dmul_rn(2.0, gamma), b);
@@ -236,7 +271,7 @@ __global__ __launch_bounds__(256) void k_umap_terms(const uint32_t *__restrict__
                 d2 = __dadd_rn(d2, __dmul_rn(df[c], df[c]));
             }
         // one power per slot, whichever the kind of sample (a wave holds both)
-        const double pb = d2 > 0.0 ? crp::pow_rn(d2, b) : 0.0;
+        const double pb = d2 > 0.0 ? crp::pow_rn_t(d2, b, tb) : 0.0;
         if (p > 0 && !(d2 > 0.0)) {  // repulsion from the same position
 #pragma unroll
             for (int c = 0; c < kMaxDim; ++c)
@@ -260,7 +295,7 @@ __global__ __launch_bounds__(256) void k_umap_terms(const uint32_t *__restrict__
 // pos[indptr[i+1]] (1 + neg)), so the wave's slots form one range: it is
 // staged through LDS in coalesced chunks, and each lane adds its own
 // vertex's slots in order.
-constexpr int kSumLds = 1024;  // float64 terms staged per chunk
+constexpr int kSumLds = 2048;  // float64 terms staged per chunk (16 KiB)
 constexpr int kSumUnroll = 8;  // slots read from LDS per round, then added in order
 
 template <int DIMS>  // coordinates held in registers: dim <= DIMS
@@ -352,6 +387,7 @@ __global__ __launch_bounds__(256) void k_umap_check(const int64_t *__restrict__ 
 }
 
 struct Ws {
+    crp::PowTables *tables;
     double *eps, *next, *terms, *Y0, *Y1;
     uint32_t *pos, *list, *erow, *tile_cnt, *tile_off, *maxb;
     int32_t *err;
@@ -363,6 +399,7 @@ size_t carve(int64_t n, int64_t nnz, int dim, int neg, void *ws, Ws *w) {
     const size_t m = (size_t)std::max<int64_t>(nnz, 1);
     const size_t T = (size_t)n_tiles(nnz);
     Carver cv(ws);
+    crp::PowTables *tables = cv.take<crp::PowTables>(1);
     double *eps = cv.take<double>(m);
     double *next = cv.take<double>(m);
     uint32_t *pos = cv.take<uint32_t>(m + 1);
@@ -375,7 +412,7 @@ size_t carve(int64_t n, int64_t nnz, int dim, int neg, void *ws, Ws *w) {
     uint32_t *tile_off = cv.take<uint32_t>(T);
     uint32_t *maxb = cv.take<uint32_t>(1);
     int32_t *err = cv.take<int32_t>(1);
-    if (w) *w = Ws{eps, next, terms, Y0, Y1, pos, list, erow, tile_cnt, tile_off, maxb, err};
+    if (w) *w = Ws{tables, eps, next, terms, Y0, Y1, pos, list, erow, tile_cnt, tile_off, maxb, err};
     return cv.used;
 }
 
@@ -444,6 +481,7 @@ int umap_layout(const int64_t *indptr, const int32_t *indices, const float *weig
         hipLaunchKernelGGL(k_umap_init, dim3(grid(std::max(nnz, ny))), dim3(256), 0, s, weights, nnz,
                            (const uint32_t *)w.maxb, n_epochs, w.eps, w.next, (const float *)Y, ny, w.Y0);
         hipLaunchKernelGGL(k_umap_rows, dim3(grid(n)), dim3(256), 0, s, indptr, n, w.erow);
+        hipLaunchKernelGGL(k_umap_tables, dim3(1), dim3(2 * crp::kPowCells), 0, s, w.tables);
     }
     if ((st = launch_status("umap init")) != RSC_OK) return st;
     const int64_t T = n_tiles(nnz);
@@ -454,19 +492,20 @@ int umap_layout(const int64_t *indptr, const int32_t *indices, const float *weig
         for (int t = 0; t < n_epochs; ++t) {
             {
                 ScopedTimer td("umap_due", s);
-                hipLaunchKernelGGL(k_umap_count, dim3((unsigned)T), dim3(256), 0, s, (const double *)w.eps,
-                                   (const double *)w.next, nnz, t, w.tile_cnt);
+                if (t == 0)  // later epochs' counts come from the previous scatter
+                    hipLaunchKernelGGL(k_umap_count, dim3((unsigned)T), dim3(256), 0, s, (const double *)w.eps,
+                                       (const double *)w.next, nnz, t, w.tile_cnt);
                 hipLaunchKernelGGL(k_umap_tile_scan, dim3(1), dim3(1024), 0, s, (const uint32_t *)w.tile_cnt, T,
                                    w.tile_off);
                 hipLaunchKernelGGL(k_umap_scatter, dim3((unsigned)T), dim3(256), 0, s, (const double *)w.eps, w.next,
-                                   nnz, t, (const uint32_t *)w.tile_off, w.pos, w.list);
+                                   nnz, t, (const uint32_t *)w.tile_off, w.pos, w.list, w.tile_cnt);
             }
             {
                 ScopedTimer tt("umap_terms", s);
                 hipLaunchKernelGGL(k_umap_terms, dim3(g_terms), dim3(256), 0, s, (const uint32_t *)w.list,
                                    (const uint32_t *)(w.pos + nnz), (const uint32_t *)w.erow, indices, n, dim,
                                    (const double *)w.Y0, t, n_epochs, a, b, gamma, alpha0, neg, seed,
-                                   1.0 / (double)n, w.terms);
+                                   1.0 / (double)n, (const crp::PowTables *)w.tables, w.terms);
             }
             {
                 ScopedTimer tsum("umap_sum", s);
