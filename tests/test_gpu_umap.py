@@ -168,6 +168,49 @@ def test_bad_graph_rejected(rsc):
     torch.cuda.synchronize()
 
 
+def test_pipeline_end_to_end(rsc):
+    # kNN -> connectivities -> layout on the GPU against the oracle's whole
+    # pipeline on the same cells
+    import torch
+
+    import oracle
+
+    X = synth.mixture(3000, d=50, n_clusters=9, seed=43)
+    idx, dist, g = rsc.knn_graph(torch.from_numpy(X).to("cuda:0"), 15)
+    o = oracle.knn_graph(X, 15)
+    assert np.array_equal(g.indptr.cpu().numpy(), o["indptr"])
+    assert np.array_equal(g.indices.cpu().numpy(), o["indices"])
+    assert np.array_equal(g.data.cpu().numpy(), o["data"])
+    Y0 = synth.umap_init(3000, 2, seed=44)
+    got = rsc.umap_layout(g, torch.from_numpy(Y0).to("cuda:0"), n_epochs=50, seed=5).cpu().numpy()
+    want = cpu_layout((o["indptr"], o["indices"], o["data"]), Y0, 50, seed=5)
+    report("end to end", got, want)
+    assert np.array_equal(got, want.astype(np.float32))
+
+
+@pytest.mark.parametrize("kw", [dict(neg=0), dict(gamma=0.0), dict(neg=64, seed=123), dict(alpha0=0.25, a=1.2, b=0.8)])
+def test_parameters_match_oracle(rsc, graph, kw):
+    Y0 = synth.umap_init(2000, 2, seed=9)
+    log(f"[umap] parameters {kw}")
+    got = gpu_layout(rsc, graph, Y0, n_epochs=12, **kw)
+    want = cpu_layout(graph, Y0, 12, **kw)
+    report(f"params {kw}", got, want)
+    assert np.array_equal(got, want.astype(np.float32))
+
+
+def test_single_vertex_and_self_draws(rsc):
+    # n = 1: every negative sample draws the vertex itself; n = 2 with one
+    # edge: about half of them do
+    one = (np.array([0, 0], np.int64), np.zeros(0, np.int32), np.zeros(0, np.float32))
+    Y1 = synth.umap_init(1, 2, seed=3)
+    assert np.array_equal(gpu_layout(rsc, one, Y1, n_epochs=4), Y1)
+    two = (np.array([0, 1, 2], np.int64), np.array([1, 0], np.int32), np.ones(2, np.float32))
+    Y2 = synth.umap_init(2, 3, seed=4)
+    got = gpu_layout(rsc, two, Y2, n_epochs=9, neg=7, seed=8)
+    want = cpu_layout(two, Y2, 9, neg=7, seed=8)
+    assert np.array_equal(got, want.astype(np.float32))
+
+
 def test_full_size_first_epochs_match_oracle(rsc):
     # the bench's graph size: 1M vertices, kNN-shaped lists of 15 with hubs,
     # connectivities from the oracle; epochs 1 and 2 are active
