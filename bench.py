@@ -263,9 +263,10 @@ def cosine_form(args, rsc, Xt, ws, out) -> dict:
 PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 matrix
 # float64 vector instruction rate: 256 CUs x 64 lanes x 2.4 GHz (78.6 TFLOP/s counts an FMA as 2)
 PEAK_FP64_VECTOR_OPS = 39.3
-# float64 add / multiply / fma instructions of one slot of k_umap_terms (the
-# straight-line correctly rounded power plus the move), counted in its assembly
-UMAP_TERM_FP64_OPS = 394
+# float64 add / multiply / fma instructions per slot of k_umap_epoch<2>: the
+# straight-line move (correctly rounded power included, 382, counted in its
+# assembly) and the slot's 2 adds of the ordered sum
+UMAP_MOVE_FP64_OPS = 384
 
 
 def edistance_form(args, rsc) -> dict:
@@ -500,22 +501,23 @@ def umap_form(args, rsc, csr=None) -> dict:
     ms = (time.perf_counter() - t0) * 1e3 / steps
     rsc.profile_enable(False)
     kern = {}
-    for name in ["umap_init", "umap_epochs", "umap_due", "umap_terms", "umap_sum"]:
+    for name in ["umap_init", "umap_epochs", "umap_due", "umap_moves"]:
         tot, cnt = rsc.profile_get(name)
         if cnt:
             kern[name] = round(tot / steps, 3)
     wts = data.cpu().numpy()
     samples = umap_samples(wts, n_epochs)
     ep_ms = kern.get("umap_epochs")
-    terms = None
-    if kern.get("umap_terms"):
-        # the term kernel is bound by float64 vector issue (the correctly rounded
-        # power): UMAP_TERM_FP64_OPS float64 instructions per slot, one slot per
-        # (edge sample, draw)
+    moves = None
+    if kern.get("umap_moves"):
+        # the epoch kernel is bound by float64 vector issue (the correctly
+        # rounded power): UMAP_MOVE_FP64_OPS float64 instructions per slot, one
+        # slot per (edge sample, draw)
         slots = samples * (1 + neg)
-        rate = slots * UMAP_TERM_FP64_OPS / (kern["umap_terms"] / 1e3) / 1e12
-        terms = {"bound": "alu", "unit": "T float64 ops/s", "slots": slots, "ops_per_slot": UMAP_TERM_FP64_OPS,
-                 "achieved": round(rate, 2), "peak": PEAK_FP64_VECTOR_OPS, "frac": round(rate / PEAK_FP64_VECTOR_OPS, 4)}
+        rate = slots * UMAP_MOVE_FP64_OPS / (kern["umap_moves"] / 1e3) / 1e12
+        moves = {"bound": "alu", "kernel": "k_umap_epoch<2>", "unit": "T float64 ops/s", "slots": slots,
+                 "ops_per_slot": UMAP_MOVE_FP64_OPS, "achieved": round(rate, 2), "peak": PEAK_FP64_VECTOR_OPS,
+                 "frac": round(rate / PEAK_FP64_VECTOR_OPS, 4)}
     finite = bool(torch.isfinite(Y).all().item())
     cpu = None
     if not args.no_cpu_baseline:
@@ -526,7 +528,7 @@ def umap_form(args, rsc, csr=None) -> dict:
             "ms_per_call": round(ms, 2), "layouts_per_s": round(1e3 / ms, 3), "kernel_ms": kern,
             "edge_samples": samples, "pow_evaluations_approx": samples * (1 + neg),
             "edge_samples_per_s": round(samples / (ep_ms / 1e3), 1) if ep_ms else None,
-            "ms_per_epoch": round(ep_ms / n_epochs, 4) if ep_ms else None, "term_kernel_roofline": terms,
+            "ms_per_epoch": round(ep_ms / n_epochs, 4) if ep_ms else None, "epoch_kernel_roofline": moves,
             "finite": finite, "cpu_baseline": cpu}
 
 

@@ -562,8 +562,8 @@ int rsc_pca(const int64_t *indptr, const int32_t *indices, const float *data, in
  * Synchronises `stream` once, to report a malformed graph as
  * RSC_ERR_BAD_GRAPH before any epoch runs.  Supports n < 2^31 and
  * nnz < 2^32 - 1; the workspace (rsc_umap_workspace_bytes, 0 for an
- * unsupported shape) holds about nnz (28 + 8 dim (1 + neg)) + 16 n dim bytes:
- * the move terms of every due edge of an epoch are kept for the ordered sums.
+ * unsupported shape) holds about 28 nnz + 16 n dim bytes (the sampling
+ * schedule, the due-edge list and two float64 embeddings).
  */
 size_t rsc_umap_workspace_bytes(int64_t n, int64_t nnz, int32_t dim, int32_t neg);
 int rsc_umap_layout(const int64_t *indptr, const int32_t *indices, const float *weights, int64_t n, int64_t nnz,

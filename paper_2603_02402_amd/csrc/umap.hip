@@ -33,13 +33,14 @@
 //      write the list of due edges in CSR order -- those of one vertex form
 //      one contiguous range -- the position of every edge in that list, and
 //      the due edges' next-sample epochs;
-//   4. terms: one thread per (due edge, sample) -- the attraction and each
-//      negative sample -- computes its clipped, scaled move (the powers and
-//      the random gathers: nearly all of the arithmetic);
-//   5. sums: each vertex adds its terms in row order (staged through LDS by
-//      the wave of 64 vertices that holds it), skipping the negative samples
-//      that drew the vertex itself (marked by the term pass), and writes the
-//      new position (float64 embeddings ping-pong between two buffers).
+//   4. moves and sums, one wave per 64 consecutive vertices: the due edges of
+//      those vertices form one range of the list, and each (due edge, draw)
+//      slot -- the attraction and each negative sample -- one move.  Chunk by
+//      chunk the lanes compute the range's moves (the powers and the random
+//      gathers: nearly all of the arithmetic) into LDS, one slot per lane,
+//      then each lane adds its own vertex's moves in row order, skipping the
+//      negative samples that drew the vertex itself, and writes the new
+//      position (float64 embeddings ping-pong between two buffers).
 
 #include <hip/hip_runtime.h>
 
@@ -86,8 +87,10 @@ __device__ __forceinline__ int64_t negative(uint64_t seed, int t, int64_t e, int
 
 __device__ __forceinline__ double clip4(double x) { return x > 4.0 ? 4.0 : (x < -4.0 ? -4.0 : x); }
 
-__device__ __forceinline__ double epoch_alpha(double alpha0, int t, int n_epochs) {
-    return __dmul_rn(alpha0, __dsub_rn(1.0, __ddiv_rn((double)t, (double)n_epochs)));
+// alpha0 (1 - t / n_epochs), each operation rounded to nearest (the file is
+// compiled without contraction, on the host as on the device)
+__host__ __device__ inline double epoch_alpha(double alpha0, int t, int n_epochs) {
+    return alpha0 * (1.0 - (double)t / (double)n_epochs);
 }
 
 __global__ __launch_bounds__(256) void k_umap_wmax(const float *__restrict__ w, int64_t nnz,
@@ -228,85 +231,86 @@ __global__ __launch_bounds__(256) void k_umap_scatter(const double *__restrict__
     if (threadIdx.x == 0) tile_cnt[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
 }
 
-// One thread per (due edge j, sample p): p = 0 the attraction, p >= 1 the
-// negative sample p - 1.  The move goes to terms[(j (1 + neg) + p) dim + c];
-// a negative sample that drew the vertex itself writes a NaN in coordinate 0,
-// which the sum skips (moves of finite positions are always finite).
-__global__ __launch_bounds__(256) void k_umap_terms(const uint32_t *__restrict__ list,
-                                                    const uint32_t *__restrict__ count,
-                                                    const uint32_t *__restrict__ erow,
-                                                    const int32_t *__restrict__ indices, int64_t n, int dim,
-                                                    const double *__restrict__ Y0, int t, int n_epochs, double a,
-                                                    double b, double gamma, double alpha0, int neg, uint64_t seed,
-                                                    double inv_n, const crp::PowTables *__restrict__ tables,
-                                                    double *__restrict__ terms) {
-    __shared__ crp::PowTables tb;
-    {
-        static_assert(sizeof(crp::PowTables) == 256 * sizeof(double), "one double per thread");
-        reinterpret_cast<double *>(&tb)[threadIdx.x] = reinterpret_cast<const double *>(tables)[threadIdx.x];
+// Epoch constants of the moves.
+struct Moves {
+    double alpha, a, b, ab2, gb2, inv_n;  // ab2 = -2 a b, gb2 = 2 gamma b
+    int64_t n;
+    int t, dim, per;
+    uint64_t seed;
+};
+
+// Slot s of the epoch (due edge j = s / per, draw p = s mod per): p = 0 the
+// attraction along the edge, p >= 1 the negative sample p - 1.  Writes the
+// clipped, scaled move to out[0 .. dim); a negative sample that drew the
+// vertex itself writes a NaN in out[0], which the sum skips (moves of finite
+// positions are always finite).
+__device__ __forceinline__ void slot_move(const Moves &m, int64_t s, const uint32_t *__restrict__ list,
+                                          const uint32_t *__restrict__ erow, const int32_t *__restrict__ indices,
+                                          const double *__restrict__ Y0, const crp::PowTables &tb, double *out) {
+    const int64_t j = s / m.per;
+    const int p = (int)(s - j * m.per);
+    const int64_t e = list[j];
+    const int64_t i = erow[e];
+    const int64_t other = p == 0 ? (int64_t)indices[e] : negative(m.seed, m.t, e, p - 1, m.n, m.inv_n);
+    if (p > 0 && other == i) {
+        out[0] = __builtin_nan("");
+        return;
     }
-    __syncthreads();
-    const double alpha = epoch_alpha(alpha0, t, n_epochs);
-    const double ab2 = __dmul_rn(__dmul_rn(-2.0, a), b);  // -2 a b
-    const double gb2 = __dmul_rn(__dmul_rn(2.0, gamma), b);
-    const int per = 1 + neg;
-    const int64_t total = (int64_t)(*count) * per;
-    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < total; s += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t j = s / per;
-        const int p = (int)(s - j * per);
-        const int64_t e = list[j];
-        const int64_t i = erow[e];
-        const int64_t other = p == 0 ? (int64_t)indices[e] : negative(seed, t, e, p - 1, n, inv_n);
-        double *out = terms + s * dim;
-        if (p > 0 && other == i) {
-            out[0] = __builtin_nan("");
-            continue;
+    const int dim = m.dim;
+    double df[kMaxDim];
+    double d2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < kMaxDim; ++c)
+        if (c < dim) {
+            df[c] = __dsub_rn(Y0[i * dim + c], Y0[other * dim + c]);
+            d2 = __dadd_rn(d2, __dmul_rn(df[c], df[c]));
         }
-        double df[kMaxDim];
-        double d2 = 0.0;
+    // one power per slot, whichever the kind of sample (a wave holds both)
+    const double pb = d2 > 0.0 ? crp::pow_rn_t(d2, m.b, tb) : 0.0;
+    if (p > 0 && !(d2 > 0.0)) {  // repulsion from the same position
 #pragma unroll
         for (int c = 0; c < kMaxDim; ++c)
-            if (c < dim) {
-                df[c] = __dsub_rn(Y0[i * dim + c], Y0[other * dim + c]);
-                d2 = __dadd_rn(d2, __dmul_rn(df[c], df[c]));
-            }
-        // one power per slot, whichever the kind of sample (a wave holds both)
-        const double pb = d2 > 0.0 ? crp::pow_rn_t(d2, b, tb) : 0.0;
-        if (p > 0 && !(d2 > 0.0)) {  // repulsion from the same position
-#pragma unroll
-            for (int c = 0; c < kMaxDim; ++c)
-                if (c < dim) out[c] = __dmul_rn(4.0, alpha);
-            continue;
-        }
-        double g;
-        if (p == 0)
-            g = d2 > 0.0 ? __ddiv_rn(__dmul_rn(ab2, __ddiv_rn(pb, d2)), __dadd_rn(__dmul_rn(a, pb), 1.0)) : 0.0;
-        else
-            g = __ddiv_rn(gb2, __dmul_rn(__dadd_rn(0.001, d2), __dadd_rn(__dmul_rn(a, pb), 1.0)));
-#pragma unroll
-        for (int c = 0; c < kMaxDim; ++c)
-            if (c < dim) out[c] = __dmul_rn(clip4(__dmul_rn(g, df[c])), alpha);
+            if (c < dim) out[c] = __dmul_rn(4.0, m.alpha);
+        return;
     }
+    double g;
+    if (p == 0)
+        g = d2 > 0.0 ? __ddiv_rn(__dmul_rn(m.ab2, __ddiv_rn(pb, d2)), __dadd_rn(__dmul_rn(m.a, pb), 1.0)) : 0.0;
+    else
+        g = __ddiv_rn(m.gb2, __dmul_rn(__dadd_rn(0.001, d2), __dadd_rn(__dmul_rn(m.a, pb), 1.0)));
+#pragma unroll
+    for (int c = 0; c < kMaxDim; ++c)
+        if (c < dim) out[c] = __dmul_rn(clip4(__dmul_rn(g, df[c])), m.alpha);
 }
 
-// One wave per 64 consecutive vertices, lane L for vertex i0 + L.  The due
-// edges of vertex i are list[pos[indptr[i]] .. pos[indptr[i+1]]), in row
-// order, and their terms the slots [pos[indptr[i]] (1 + neg),
-// pos[indptr[i+1]] (1 + neg)), so the wave's slots form one range: it is
-// staged through LDS in coalesced chunks, and each lane adds its own
-// vertex's slots in order.
-constexpr int kSumLds = 2048;  // float64 terms staged per chunk (16 KiB)
-constexpr int kSumUnroll = 8;  // slots read from LDS per round, then added in order
+// One wave (block) per 64 consecutive vertices, lane L for vertex i0 + L.
+// The due edges of vertex i are list[pos[indptr[i]] .. pos[indptr[i+1]]), in
+// row order, and its slots [pos[indptr[i]] per, pos[indptr[i+1]] per), so the
+// wave's slots form one range.  Chunk by chunk, the lanes compute the range's
+// moves into LDS (consecutive slots on consecutive lanes), then each lane
+// adds its own vertex's moves in order.
+constexpr int kMoveLds = 1024;  // float64 moves per chunk (8 KiB)
+constexpr int kSumUnroll = 8;   // moves read from LDS per round, then added in order
 
 template <int DIMS>  // coordinates held in registers: dim <= DIMS
-__global__ __launch_bounds__(64) void k_umap_sum(const int64_t *__restrict__ indptr,
-                                                 const uint32_t *__restrict__ pos,
-                                                 const double *__restrict__ terms, int64_t n, int dim,
-                                                 const double *__restrict__ Y0, double *__restrict__ Y1, int neg) {
-    __shared__ double buf[kSumLds];
-    const int per = 1 + neg;
+__global__ __launch_bounds__(64) void k_umap_epoch(const int64_t *__restrict__ indptr,
+                                                   const uint32_t *__restrict__ pos,
+                                                   const uint32_t *__restrict__ list,
+                                                   const uint32_t *__restrict__ erow,
+                                                   const int32_t *__restrict__ indices, const double *__restrict__ Y0,
+                                                   double *__restrict__ Y1, Moves m,
+                                                   const crp::PowTables *__restrict__ tables) {
+    __shared__ crp::PowTables tb;
+    __shared__ double buf[kMoveLds];
+    static_assert(sizeof(crp::PowTables) == 256 * sizeof(double), "four doubles per lane");
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        reinterpret_cast<double *>(&tb)[u * 64 + threadIdx.x] = reinterpret_cast<const double *>(tables)[u * 64 + threadIdx.x];
+    __syncthreads();
     const int lane = threadIdx.x;
-    const int64_t chunk = kSumLds / dim;  // slots per chunk
+    const int dim = m.dim, per = m.per;
+    const int64_t n = m.n;
+    const int64_t chunk = kMoveLds / dim;  // slots per chunk
     for (int64_t i0 = (int64_t)blockIdx.x * 64; i0 < n; i0 += (int64_t)gridDim.x * 64) {
         const int64_t i = i0 + lane;
         const int64_t S0 = (int64_t)pos[indptr[i0]] * per;
@@ -321,15 +325,7 @@ __global__ __launch_bounds__(64) void k_umap_sum(const int64_t *__restrict__ ind
         for (int c = 0; c < DIMS; ++c) mv[c] = 0.0;
         for (int64_t c0 = S0; c0 < S1; c0 += chunk) {
             const int64_t c1 = std::min<int64_t>(c0 + chunk, S1);
-            const int64_t nd = (c1 - c0) * dim;
-            double r[kSumLds / 64];  // all loads of the chunk in flight at once
-#pragma unroll
-            for (int u = 0; u < kSumLds / 64; ++u) {
-                const int64_t q = (int64_t)u * 64 + lane;
-                r[u] = q < nd ? terms[c0 * dim + q] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < kSumLds / 64; ++u) buf[u * 64 + lane] = r[u];
+            for (int64_t s = c0 + lane; s < c1; s += 64) slot_move(m, s, list, erow, indices, Y0, tb, buf + (s - c0) * dim);
             __syncthreads();
             const int64_t s1 = std::min<int64_t>(hi, c1);
             for (int64_t sb = std::max<int64_t>(lo, c0); sb < s1; sb += kSumUnroll) {
@@ -388,7 +384,7 @@ __global__ __launch_bounds__(256) void k_umap_check(const int64_t *__restrict__ 
 
 struct Ws {
     crp::PowTables *tables;
-    double *eps, *next, *terms, *Y0, *Y1;
+    double *eps, *next, *Y0, *Y1;
     uint32_t *pos, *list, *erow, *tile_cnt, *tile_off, *maxb;
     int32_t *err;
 };
@@ -405,14 +401,13 @@ size_t carve(int64_t n, int64_t nnz, int dim, int neg, void *ws, Ws *w) {
     uint32_t *pos = cv.take<uint32_t>(m + 1);
     uint32_t *list = cv.take<uint32_t>(m);
     uint32_t *erow = cv.take<uint32_t>(m);
-    double *terms = cv.take<double>(m * (size_t)(1 + neg) * (size_t)dim);
     double *Y0 = cv.take<double>((size_t)n * dim);
     double *Y1 = cv.take<double>((size_t)n * dim);
     uint32_t *tile_cnt = cv.take<uint32_t>(T);
     uint32_t *tile_off = cv.take<uint32_t>(T);
     uint32_t *maxb = cv.take<uint32_t>(1);
     int32_t *err = cv.take<int32_t>(1);
-    if (w) *w = Ws{tables, eps, next, terms, Y0, Y1, pos, list, erow, tile_cnt, tile_off, maxb, err};
+    if (w) *w = Ws{tables, eps, next, Y0, Y1, pos, list, erow, tile_cnt, tile_off, maxb, err};
     return cv.used;
 }
 
@@ -485,8 +480,7 @@ int umap_layout(const int64_t *indptr, const int32_t *indices, const float *weig
     }
     if ((st = launch_status("umap init")) != RSC_OK) return st;
     const int64_t T = n_tiles(nnz);
-    const unsigned g_terms = grid(nnz * (1 + neg));
-    const unsigned g_sum = (unsigned)std::min<int64_t>(32768, (n + 63) / 64);
+    const unsigned g_epoch = (unsigned)std::min<int64_t>(32768, (n + 63) / 64);
     {
         ScopedTimer tm("umap_epochs", s);
         for (int t = 0; t < n_epochs; ++t) {
@@ -501,21 +495,17 @@ int umap_layout(const int64_t *indptr, const int32_t *indices, const float *weig
                                    nnz, t, (const uint32_t *)w.tile_off, w.pos, w.list, w.tile_cnt);
             }
             {
-                ScopedTimer tt("umap_terms", s);
-                hipLaunchKernelGGL(k_umap_terms, dim3(g_terms), dim3(256), 0, s, (const uint32_t *)w.list,
-                                   (const uint32_t *)(w.pos + nnz), (const uint32_t *)w.erow, indices, n, dim,
-                                   (const double *)w.Y0, t, n_epochs, a, b, gamma, alpha0, neg, seed,
-                                   1.0 / (double)n, (const crp::PowTables *)w.tables, w.terms);
-            }
-            {
-                ScopedTimer tsum("umap_sum", s);
+                ScopedTimer tt("umap_moves", s);
+                const Moves mv{epoch_alpha(alpha0, t, n_epochs), a, b, (-2.0 * a) * b, (2.0 * gamma) * b,
+                               1.0 / (double)n, n, t, dim, 1 + neg, seed};
                 if (dim <= 2)
-                    hipLaunchKernelGGL(k_umap_sum<2>, dim3(g_sum), dim3(64), 0, s, indptr, (const uint32_t *)w.pos,
-                                       (const double *)w.terms, n, dim, (const double *)w.Y0, w.Y1, neg);
+                    hipLaunchKernelGGL(k_umap_epoch<2>, dim3(g_epoch), dim3(64), 0, s, indptr, (const uint32_t *)w.pos,
+                                       (const uint32_t *)w.list, (const uint32_t *)w.erow, indices,
+                                       (const double *)w.Y0, w.Y1, mv, (const crp::PowTables *)w.tables);
                 else
-                    hipLaunchKernelGGL(k_umap_sum<kMaxDim>, dim3(g_sum), dim3(64), 0, s, indptr,
-                                       (const uint32_t *)w.pos, (const double *)w.terms, n, dim,
-                                       (const double *)w.Y0, w.Y1, neg);
+                    hipLaunchKernelGGL(k_umap_epoch<kMaxDim>, dim3(g_epoch), dim3(64), 0, s, indptr,
+                                       (const uint32_t *)w.pos, (const uint32_t *)w.list, (const uint32_t *)w.erow,
+                                       indices, (const double *)w.Y0, w.Y1, mv, (const crp::PowTables *)w.tables);
             }
             std::swap(w.Y0, w.Y1);
         }
