@@ -726,7 +726,7 @@ def test_umap_attraction_is_the_gradient_of_minus_log_q():
     from oracle import umap as ou
 
     a, b = ou.fit_ab(0.5, 1.0)
-    y0 = np.array([[0.3, -0.2], [1.1, 0.4]])
+    y0 = np.array([[0.3, -0.2], [1.4, 0.5]])  # d2 = 1.7 (not 1, where every power of d2 is 1)
     Y = ou.layout(*_two_points(), y0, n_epochs=2, a=a, b=b, neg=0)  # epoch 1 samples the edge, alpha 1/2
 
     def loss(yi):
@@ -792,3 +792,67 @@ def test_umap_schedule_translation_and_clipping():
     # coincident points: the attraction is 0 and no step exceeds 4 alpha per coordinate
     Yc = ou.layout(*_two_points(), np.zeros((2, 2)), n_epochs=2, a=a, b=b, neg=0)
     assert np.array_equal(Yc, np.zeros((2, 2)))
+
+
+def _draws(seed, t, e, neg, n):
+    """The vertices the negatives of edge e draw in epoch t (the counter-based
+    SplitMix64 of the reading, through the pinned generator)."""
+    from oracle import umap as ou
+
+    g = 0x9E3779B97F4A7C15
+    out = []
+    for p in range(neg):
+        st = (seed + (t * (1 << 40) + e * 16 + p + 1) * g) % (1 << 64)
+        out.append((ou.splitmix64_next((st - g) % (1 << 64)) >> 11) % n)
+    return out
+
+
+def test_umap_self_draws_are_skipped():
+    # a lone vertex with a self-loop: the attraction has d2 = 0 and every
+    # negative sample draws the vertex itself, which UMAP skips: it never moves
+    from oracle import umap as ou
+
+    y0 = np.array([[1.5, -2.5]])
+    Y = ou.layout(np.array([0, 1], np.int64), np.array([0], np.int32), np.ones(1, np.float32), y0, n_epochs=5,
+                  a=1.0, b=1.0, neg=6, seed=4)
+    assert np.array_equal(Y, y0)
+
+
+def test_umap_repulsion_is_regularised_near_coincidence():
+    # two vertices 1e-9 apart: the repulsion coefficient stays finite (its
+    # 0.001 regulariser), so the move is of the order of the separation; an
+    # unregularised coefficient would clip every such move to 4 alpha
+    from oracle import umap as ou
+
+    seed, neg = 11, 8
+    hits = sum(k == 1 for k in _draws(seed, 1, 0, neg, 2))  # draws of vertex 0 that hit vertex 1 in epoch 1
+    assert hits > 0
+    y0 = np.array([[0.0, 0.0], [1e-9, 0.0]])
+    Y = ou.layout(*_two_points(), y0, n_epochs=2, a=1.0, b=1.0, neg=neg, seed=seed)
+    assert 0 < np.abs(Y[0] - y0[0]).max() < 1e-4
+
+
+def test_umap_coincident_points_are_pushed_by_four_alpha():
+    # UMAP's rule for a negative sample at the vertex's own position: a push
+    # of 4 alpha per coordinate.  Two distinct vertices at the origin, epoch 1
+    # (alpha 1/2): vertex 0 moves by 2 per coordinate for every draw of vertex 1
+    from oracle import umap as ou
+
+    seed, neg = 5, 6
+    hits = sum(k == 1 for k in _draws(seed, 1, 0, neg, 2))
+    assert 0 < hits < neg
+    Y = ou.layout(*_two_points(), np.zeros((2, 2)), n_epochs=2, a=1.0, b=1.0, neg=neg, seed=seed)
+    np.testing.assert_array_equal(Y[0], [2.0 * hits, 2.0 * hits])
+
+
+def test_umap_moves_are_clipped_at_four():
+    # an enormous repulsion strength: each repulsive move is clipped to 4 alpha
+    # away from the drawn vertex (alpha 1/2 in epoch 1)
+    from oracle import umap as ou
+
+    seed, neg = 5, 6
+    hits = sum(k == 1 for k in _draws(seed, 1, 0, neg, 2))
+    y0 = np.array([[0.0, 0.0], [1.0, 0.0]])
+    Ya = ou.layout(*_two_points(), y0, n_epochs=2, a=1.0, b=1.0, neg=0)
+    Yr = ou.layout(*_two_points(), y0, n_epochs=2, a=1.0, b=1.0, gamma=1e6, neg=neg, seed=seed)
+    np.testing.assert_allclose(Yr[0] - Ya[0], [-2.0 * hits, 0.0], rtol=0, atol=1e-12)
