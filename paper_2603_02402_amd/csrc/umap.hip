@@ -240,46 +240,67 @@ struct Moves {
 };
 
 // Slot s of the epoch (due edge j = s / per, draw p = s mod per): p = 0 the
-// attraction along the edge, p >= 1 the negative sample p - 1.  Writes the
-// clipped, scaled move to out[0 .. dim); a negative sample that drew the
-// vertex itself writes a NaN in out[0], which the sum skips (moves of finite
-// positions are always finite).
-__device__ __forceinline__ void slot_move(const Moves &m, int64_t s, const uint32_t *__restrict__ list,
-                                          const uint32_t *__restrict__ erow, const int32_t *__restrict__ indices,
-                                          const double *__restrict__ Y0, const crp::PowTables &tb, double *out) {
+// attraction along the edge, p >= 1 the negative sample p - 1.  slot_fetch
+// gathers what the move needs (the two embedding rows), slot_move computes
+// the clipped, scaled move into out[0 .. dim); a negative sample that drew
+// the vertex itself writes a NaN in out[0], which the sum skips (moves of
+// finite positions are always finite).
+template <int DIMS>
+struct SlotIn {
+    double yi[DIMS], yo[DIMS];
+    int p;
+    bool self;
+};
+
+template <int DIMS>
+__device__ __forceinline__ void slot_fetch(const Moves &m, int64_t s, const uint32_t *__restrict__ list,
+                                           const uint32_t *__restrict__ erow, const int32_t *__restrict__ indices,
+                                           const double *__restrict__ Y0, SlotIn<DIMS> &in) {
     const int64_t j = s / m.per;
     const int p = (int)(s - j * m.per);
     const int64_t e = list[j];
     const int64_t i = erow[e];
     const int64_t other = p == 0 ? (int64_t)indices[e] : negative(m.seed, m.t, e, p - 1, m.n, m.inv_n);
-    if (p > 0 && other == i) {
+    in.p = p;
+    in.self = p > 0 && other == i;
+#pragma unroll
+    for (int c = 0; c < DIMS; ++c) {
+        in.yi[c] = c < m.dim ? Y0[i * m.dim + c] : 0.0;
+        in.yo[c] = c < m.dim ? Y0[other * m.dim + c] : 0.0;
+    }
+}
+
+template <int DIMS>
+__device__ __forceinline__ void slot_move(const Moves &m, const SlotIn<DIMS> &in, const crp::PowTables &tb,
+                                          double *out) {
+    if (in.self) {
         out[0] = __builtin_nan("");
         return;
     }
     const int dim = m.dim;
-    double df[kMaxDim];
+    double df[DIMS];
     double d2 = 0.0;
 #pragma unroll
-    for (int c = 0; c < kMaxDim; ++c)
+    for (int c = 0; c < DIMS; ++c)
         if (c < dim) {
-            df[c] = __dsub_rn(Y0[i * dim + c], Y0[other * dim + c]);
+            df[c] = __dsub_rn(in.yi[c], in.yo[c]);
             d2 = __dadd_rn(d2, __dmul_rn(df[c], df[c]));
         }
     // one power per slot, whichever the kind of sample (a wave holds both)
     const double pb = d2 > 0.0 ? crp::pow_rn_t(d2, m.b, tb) : 0.0;
-    if (p > 0 && !(d2 > 0.0)) {  // repulsion from the same position
+    if (in.p > 0 && !(d2 > 0.0)) {  // repulsion from the same position
 #pragma unroll
-        for (int c = 0; c < kMaxDim; ++c)
+        for (int c = 0; c < DIMS; ++c)
             if (c < dim) out[c] = __dmul_rn(4.0, m.alpha);
         return;
     }
     double g;
-    if (p == 0)
+    if (in.p == 0)
         g = d2 > 0.0 ? __ddiv_rn(__dmul_rn(m.ab2, __ddiv_rn(pb, d2)), __dadd_rn(__dmul_rn(m.a, pb), 1.0)) : 0.0;
     else
         g = __ddiv_rn(m.gb2, __dmul_rn(__dadd_rn(0.001, d2), __dadd_rn(__dmul_rn(m.a, pb), 1.0)));
 #pragma unroll
-    for (int c = 0; c < kMaxDim; ++c)
+    for (int c = 0; c < DIMS; ++c)
         if (c < dim) out[c] = __dmul_rn(clip4(__dmul_rn(g, df[c])), m.alpha);
 }
 
@@ -325,7 +346,24 @@ __global__ __launch_bounds__(64) void k_umap_epoch(const int64_t *__restrict__ i
         for (int c = 0; c < DIMS; ++c) mv[c] = 0.0;
         for (int64_t c0 = S0; c0 < S1; c0 += chunk) {
             const int64_t c1 = std::min<int64_t>(c0 + chunk, S1);
-            for (int64_t s = c0 + lane; s < c1; s += 64) slot_move(m, s, list, erow, indices, Y0, tb, buf + (s - c0) * dim);
+            // a lane fetches four of its slots (two when dim > 2) before
+            // computing them, so that their dependent loads (list, edge, two
+            // embedding rows) overlap; deeper groups raise the register count
+            // and cost more occupancy than they hide
+            constexpr int PFD = DIMS <= 2 ? 4 : 2;
+            for (int64_t sb = c0 + lane; sb < c1; sb += (int64_t)PFD * 64) {
+                SlotIn<DIMS> in[PFD];
+#pragma unroll
+                for (int u = 0; u < PFD; ++u) {
+                    const int64_t s = sb + (int64_t)u * 64;
+                    if (s < c1) slot_fetch<DIMS>(m, s, list, erow, indices, Y0, in[u]);
+                }
+#pragma unroll
+                for (int u = 0; u < PFD; ++u) {
+                    const int64_t s = sb + (int64_t)u * 64;
+                    if (s < c1) slot_move<DIMS>(m, in[u], tb, buf + (s - c0) * dim);
+                }
+            }
             __syncthreads();
             const int64_t s1 = std::min<int64_t>(hi, c1);
             for (int64_t sb = std::max<int64_t>(lo, c0); sb < s1; sb += kSumUnroll) {
