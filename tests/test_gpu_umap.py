@@ -211,17 +211,27 @@ def test_single_vertex_and_self_draws(rsc):
     assert np.array_equal(got, want.astype(np.float32))
 
 
-def test_full_size_first_epochs_match_oracle(rsc):
-    # the bench's graph size: 1M vertices, kNN-shaped lists of 15 with hubs,
-    # connectivities from the oracle; epochs 1 and 2 are active
+@pytest.fixture(scope="module")
+def full_graph():
     import oracle
 
     n, k = 1_000_000, 15
     idx, dist = synth.random_knn_lists(n, k, seed=12)
     indptr, indices, data, _, _ = oracle.connectivities(idx, dist)
-    log(f"[umap] full size n={n} nnz={len(indices)} 3 epochs")
+    return indptr, indices, data
+
+
+@pytest.mark.parametrize("n_epochs", [3, 6])
+def test_full_size_epochs_match_oracle(rsc, full_graph, n_epochs):
+    # the bench's graph size: 1M vertices, kNN-shaped lists of 15 with hubs,
+    # connectivities from the oracle; with 3 epochs the edges of weight >=
+    # w_max / 2 are sampled, with 6 those of weight >= w_max / 6, over 5
+    # active epochs
+    indptr, indices, data = full_graph
+    n = len(indptr) - 1
+    log(f"[umap] full size n={n} nnz={len(indices)} {n_epochs} epochs")
     Y0 = synth.umap_init(n, 2, seed=13)
-    got = gpu_layout(rsc, (indptr, indices, data), Y0, n_epochs=3, seed=17)
-    want = cpu_layout((indptr, indices, data), Y0, 3, seed=17)
-    report("full size 3 epochs", got, want)
+    got = gpu_layout(rsc, (indptr, indices, data), Y0, n_epochs=n_epochs, seed=17)
+    want = cpu_layout((indptr, indices, data), Y0, n_epochs, seed=17)
+    report(f"full size {n_epochs} epochs", got, want)
     assert np.array_equal(got, want.astype(np.float32))
