@@ -70,6 +70,8 @@ def _load():
             lib.oracle_umap_layout.restype = i32
             lib.oracle_splitmix64_next.argtypes = [ctypes.c_uint64]
             lib.oracle_splitmix64_next.restype = ctypes.c_uint64
+            lib.oracle_umap_negative.argtypes = [ctypes.c_uint64, i32, i64, i32, i64]
+            lib.oracle_umap_negative.restype = i64
             _lib = lib
     return _lib
 

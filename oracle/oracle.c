@@ -531,24 +531,27 @@ int oracle_edistance_sums(const float *X, int64_t n, int d, const int64_t *offse
  *              the epoch (Y); vertex i sums the moves of its own edges in
  *              CSR order, then Y_i += the sum.  For each edge e = (i, j)
  *              of row i that is due (next_e <= t; then next_e += eps_e):
- *                attraction: d2 = |Y_i - Y_j|^2, g = -2 a b (d2^b / d2) /
- *                  (a d2^b + 1) if d2 > 0 else 0 (d2^(b-1) taken as
- *                  d2^b / d2); move_i += clip(g (Y_i - Y_j)) alpha_t per
- *                  coordinate;
+ *                attraction: d2 = |Y_i - Y_j|^2, g = -2 a b d2^(b-1) /
+ *                  (a d2^b + 1) if d2 > 0 else 0 (UMAP's published
+ *                  gradient of -log q, both powers as written);
+ *                  move_i += clip(g (Y_i - Y_j)) alpha_t per coordinate;
  *                `neg` repulsions from vertices k = splitmix64(seed, t, e,
  *                  p) mod n, p = 0 .. neg-1 (k == i skipped): d2 = |Y_i -
  *                  Y_k|^2, if d2 > 0: g = 2 gamma b / ((0.001 + d2)(a d2^b
  *                  + 1)), move_i += clip(g (Y_i - Y_k)) alpha_t, else
  *                  move_i += 4 alpha_t per coordinate;
  *   clip(x)    = max(-4, min(4, x));
- *   d2^b       the power rounded to the nearest double (evaluated in
- *              quadruple precision, then rounded), so that the result is one
- *              defined function of the inputs, whatever library computes it.
+ *   d2^b, d2^(b-1)  each power rounded to the nearest double (evaluated
+ *              in quadruple precision, then rounded), so that the result is
+ *              one defined function of the inputs, whatever library computes
+ *              it; b - 1 is the float64 difference.
  *
- * splitmix64: state s = seed + (t * 2^40 + e * 2^4 + p + 1) * 0x9E3779B97F4A7C15
+ * splitmix64: state s = seed + (t * 2^40 + e * 2^6 + p + 1) * 0x9E3779B97F4A7C15
  * (mod 2^64), then the SplitMix64 finaliser (xor-shift 30, multiply by
  * 0xBF58476D1CE4E5B9, xor-shift 27, multiply by 0x94D049BB133111EB,
- * xor-shift 31); k = (out >> 11) mod n.
+ * xor-shift 31); k = (out >> 11) mod n.  The edge term's stride 2^6 is the
+ * largest `neg` (64), so no two (edge, draw) pairs of an epoch share a
+ * counter (e < 2^32 keeps e * 2^6 below the epoch term).
  *
  * Y is n x dim float64, updated in place.  Returns 0, or -1 for invalid
  * arguments.
@@ -561,6 +564,13 @@ static uint64_t sm64_mix(uint64_t z) {
 
 uint64_t oracle_splitmix64_next(uint64_t state) { return sm64_mix(state + 0x9E3779B97F4A7C15ull); }
 
+/* The vertex that negative sample p of edge e draws in epoch t. */
+int64_t oracle_umap_negative(uint64_t seed, int t, int64_t e, int p, int64_t n) {
+    uint64_t st = seed + ((uint64_t)t * (1ull << 40) + (uint64_t)e * 64ull + (uint64_t)p + 1ull) *
+                             0x9E3779B97F4A7C15ull;
+    return (int64_t)((sm64_mix(st) >> 11) % (uint64_t)n);
+}
+
 static double clip4(double x) { return x > 4.0 ? 4.0 : (x < -4.0 ? -4.0 : x); }
 
 /* x^y rounded to nearest: the quadruple-precision power (about 113 bits) rounded to double */
@@ -569,7 +579,7 @@ static double pow_rn(double x, double y) { return (double)powq((__float128)x, (_
 int oracle_umap_layout(const int64_t *indptr, const int32_t *indices, const float *weights, int64_t n, int dim,
                        double *Y, int n_epochs, double a, double b, double gamma, double alpha0, int neg,
                        uint64_t seed) {
-    if (n < 1 || dim < 1 || n_epochs < 0 || neg < 0) return -1;
+    if (n < 1 || dim < 1 || n_epochs < 0 || neg < 0 || neg > 64) return -1;
     int64_t nnz = indptr[n];
     double wmax = 0.0;
     for (int64_t e = 0; e < nnz; ++e)
@@ -602,15 +612,10 @@ int oracle_umap_layout(const int64_t *indptr, const int32_t *indices, const floa
                 double d2 = 0.0;
                 for (int c = 0; c < dim; ++c) d2 = d2 + (yi[c] - yj[c]) * (yi[c] - yj[c]);
                 double g = 0.0;
-                if (d2 > 0.0) {
-                    double pb = pow_rn(d2, b);
-                    g = (-2.0 * a * b * (pb / d2)) / (a * pb + 1.0);
-                }
+                if (d2 > 0.0) g = (-2.0 * a * b * pow_rn(d2, b - 1.0)) / (a * pow_rn(d2, b) + 1.0);
                 for (int c = 0; c < dim; ++c) mv[c] = mv[c] + clip4(g * (yi[c] - yj[c])) * alpha;
                 for (int p = 0; p < neg; ++p) {
-                    uint64_t st = seed + ((uint64_t)t * (1ull << 40) + (uint64_t)e * 16ull + (uint64_t)p + 1ull) *
-                                             0x9E3779B97F4A7C15ull;
-                    int64_t k = (int64_t)((sm64_mix(st) >> 11) % (uint64_t)n);
+                    int64_t k = oracle_umap_negative(seed, t, e, p, n);
                     if (k == i) continue;
                     const double *yk = Y0 + k * dim;
                     double dk = 0.0;

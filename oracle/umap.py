@@ -36,6 +36,11 @@ def splitmix64_next(state: int) -> int:
     return int(_load().oracle_splitmix64_next(ctypes.c_uint64(state)))
 
 
+def negative(seed: int, t: int, e: int, p: int, n: int) -> int:
+    """The vertex that negative sample ``p`` of edge ``e`` draws in epoch ``t``."""
+    return int(_load().oracle_umap_negative(ctypes.c_uint64(seed), t, e, p, n))
+
+
 def fit_ab(min_dist: float = 0.5, spread: float = 1.0):
     """``(a, b)`` by least squares (scipy's curve_fit)."""
     from scipy.optimize import curve_fit

@@ -92,6 +92,24 @@ def test_knn_rectangular(oracle_mod):
     np.testing.assert_allclose(d2, np.take_along_axis(D, ref, axis=1), rtol=1e-12)
 
 
+def test_pair_d2_matches_cdist(oracle_mod):
+    # the exact squared distances the precision tests judge with: scipy's
+    # float64 cdist on random pairs, including i == j and repeated pairs
+    rng = np.random.default_rng(31)
+    for n, d in [(50, 1), (300, 7), (1000, 50), (64, 129)]:
+        X = (rng.standard_normal((n, d)) * rng.uniform(0.01, 100.0, d)).astype(np.float32)
+        ii = rng.integers(0, n, 2000)
+        jj = rng.integers(0, n, 2000)
+        jj[:20] = ii[:20]
+        got = oracle_mod.pair_d2(X, ii, jj)
+        X64 = X.astype(np.float64)
+        ref = np.array([cdist(X64[i:i + 1], X64[j:j + 1], "sqeuclidean")[0, 0] for i, j in zip(ii, jj)])
+        np.testing.assert_allclose(got, ref, rtol=1e-13, atol=0)
+        assert np.all(got[:20] == 0.0)
+    with pytest.raises(ValueError):
+        oracle_mod.pair_d2(X, np.array([0]), np.array([n]))
+
+
 def test_lattice_ties_lowest_index_first(oracle_mod):
     n, k = 40, 7
     X = synth.lattice_1d(n, d=3)
@@ -751,7 +769,7 @@ def test_umap_repulsion_is_the_gradient_of_minus_log_one_minus_q():
     Ya = ou.layout(ip, ix, w, y0, n_epochs=2, a=a, b=b, gamma=gamma, neg=0)
     Yr = ou.layout(ip, ix, w, y0, n_epochs=2, a=a, b=b, gamma=gamma, neg=1, seed=7)
     # which vertex the single negative of vertex 0 drew (epoch 1, edge 0, draw 0)
-    st = (7 + ((1 << 40) + 0 * 16 + 0 + 1) * 0x9E3779B97F4A7C15) % (1 << 64)
+    st = (7 + ((1 << 40) + 0 * 64 + 0 + 1) * 0x9E3779B97F4A7C15) % (1 << 64)
     kk = (ou.splitmix64_next((st - 0x9E3779B97F4A7C15) % (1 << 64)) >> 11) % 3
     rep = Yr[0] - Ya[0]
     if kk == 0:
@@ -794,7 +812,7 @@ def test_umap_schedule_translation_and_clipping():
     assert np.array_equal(Yc, np.zeros((2, 2)))
 
 
-def _draws(seed, t, e, neg, n):
+def _draws(seed, t, e, neg, n, stride=64):
     """The vertices the negatives of edge e draw in epoch t (the counter-based
     SplitMix64 of the reading, through the pinned generator)."""
     from oracle import umap as ou
@@ -802,9 +820,41 @@ def _draws(seed, t, e, neg, n):
     g = 0x9E3779B97F4A7C15
     out = []
     for p in range(neg):
-        st = (seed + (t * (1 << 40) + e * 16 + p + 1) * g) % (1 << 64)
+        st = (seed + (t * (1 << 40) + e * stride + p + 1) * g) % (1 << 64)
         out.append((ou.splitmix64_next((st - g) % (1 << 64)) >> 11) % n)
     return out
+
+
+def test_umap_negative_draws_follow_the_counter_and_never_repeat_a_counter():
+    # the oracle's draw function is the pinned generator at the reading's counter
+    from oracle import umap as ou
+
+    for seed, t, e, n in [(0, 0, 0, 7), (3, 5, 11, 1000), (2**63 + 5, 199, 2**31 + 3, 2**31 - 1)]:
+        assert [ou.negative(seed, t, e, p, n) for p in range(64)] == _draws(seed, t, e, 64, n)
+    # with 64 draws per edge, the draws of neighbouring edges share no counter:
+    # over 40 edges x 64 draws into 2^31 - 1 vertices every draw is distinct
+    # (a stride of 16 per edge would make draws 16..63 of edge e repeat draws
+    # 0..47 of edge e + 1)
+    n = 2**31 - 1
+    draws = [ou.negative(9, 4, e, p, n) for e in range(40) for p in range(64)]
+    assert len(set(draws)) == len(draws)
+    assert _draws(9, 4, 0, 64, n, stride=16)[16:] == _draws(9, 4, 1, 64, n, stride=16)[:48]
+
+
+def test_umap_layout_draws_of_a_later_edge_use_the_full_stride():
+    # vertex 1's only edge is edge 1 (the second CSR entry); with an enormous
+    # repulsion strength every draw of vertex 0 by that edge's 64 negatives
+    # pushes vertex 1 by 4 alpha = 2 (epoch 1) along +x, away from vertex 0
+    from oracle import umap as ou
+
+    seed, neg = 21, 64
+    hits = sum(k == 0 for k in _draws(seed, 1, 1, neg, 2))
+    hits16 = sum(k == 0 for k in _draws(seed, 1, 1, neg, 2, stride=16))
+    assert hits != hits16  # the case tells the two strides apart
+    y0 = np.array([[0.0, 0.0], [1.0, 0.0]])
+    Ya = ou.layout(*_two_points(), y0, n_epochs=2, a=1.0, b=1.0, neg=0)
+    Yr = ou.layout(*_two_points(), y0, n_epochs=2, a=1.0, b=1.0, gamma=1e6, neg=neg, seed=seed)
+    np.testing.assert_allclose(Yr[1] - Ya[1], [2.0 * hits, 0.0], rtol=0, atol=1e-12)
 
 
 def test_umap_self_draws_are_skipped():
