@@ -1,5 +1,5 @@
-// x^y rounded to the nearest double, for x > 0 and a result in the normal
-// range, on the device.
+// x^y rounded to the nearest double, for x > 0 (normal or subnormal) and
+// |y log x| < 2^20, on the device.
 //
 // Evaluated as exp(y log x) in double-double arithmetic (pairs hi + lo of
 // doubles, |lo| <= ulp(hi) / 2, each product and sum built from exact
@@ -142,14 +142,32 @@ __device__ __forceinline__ dd exp_dd(dd E, int *n_out) {
     return add_d(q, 1.0);
 }
 
-// x^y rounded to nearest (x > 0 finite, y finite, result normal), by the
-// series above alone (no tables).
+// (v.h + v.l) 2^n rounded once to the nearest double (ties to even), for
+// v.h in [0.7, 2.1] with |v.l| <= ulp(v.h) / 2.  For n >= -1021 the value is
+// normal or overflows, and rounding v.h + v.l then scaling is exact.  Below,
+// the result lies on the subnormal grid of 2^-1074 (which also spaces the
+// binade [2^-1022, 2^-1021)): z = v 2^(n + 1074) is rounded to an integer,
+// with the tail deciding the halfway cases of the head.
+__device__ __forceinline__ double scale_round(dd v, int n) {
+    if (n >= -1021) return __builtin_ldexp(v.h + v.l, n);
+    const int s = n + 1074;
+    if (s < -2) return 0.0;  // below 2^-1076: less than half a grid step
+    const double zh = __builtin_ldexp(v.h, s), zl = __builtin_ldexp(v.l, s);  // exact scalings
+    double r = __builtin_rint(zh);
+    const double f = zh - r;  // exact: |f| <= 1/2 on zh's own grid
+    if (f == 0.5 && zl > 0.0) r = r + 1.0;
+    if (f == -0.5 && zl < 0.0) r = r - 1.0;
+    return __builtin_ldexp(r, -1074);  // r < 2^53: exact
+}
+
+// x^y rounded to nearest (x > 0 finite, |y log x| < 2^20), by the series
+// above alone (no tables).
 __device__ __forceinline__ double pow_rn(double x, double y) {
     const dd L = log_dd(x);
     const dd E = mul_d(L, y);
     int n;
     const dd v = exp_dd(E, &n);
-    return __builtin_ldexp(v.h + v.l, n);
+    return scale_round(v, n);
 }
 
 // ---- table-driven form ------------------------------------------------------
@@ -237,13 +255,26 @@ __device__ __forceinline__ dd exp_dd_t(dd E, const dd *__restrict__ exp2t, int *
     return add(T, mul(q, T));
 }
 
-// x^y rounded to nearest (x > 0 finite, y finite, result normal)
+// x^y rounded to nearest (x > 0 finite, |y log x| < 2^20); results beyond
+// the largest double give +inf, results in the subnormal range are rounded
+// on its grid
 __device__ __forceinline__ double pow_rn_t(double x, double y, const PowTables &tb) {
     const dd L = log_dd_t(x, tb.logc);
     const dd E = mul_d(L, y);
     int n;
     const dd v = exp_dd_t(E, tb.exp2, &n);
-    return __builtin_ldexp(v.h + v.l, n);
+    return scale_round(v, n);
+}
+
+// x^y1 and x^y2, each rounded to nearest as pow_rn_t, sharing one logarithm
+__device__ __forceinline__ void pow2_rn_t(double x, double y1, double y2, const PowTables &tb, double *r1,
+                                          double *r2) {
+    const dd L = log_dd_t(x, tb.logc);
+    int n1, n2;
+    const dd v1 = exp_dd_t(mul_d(L, y1), tb.exp2, &n1);
+    const dd v2 = exp_dd_t(mul_d(L, y2), tb.exp2, &n2);
+    *r1 = scale_round(v1, n1);
+    *r2 = scale_round(v2, n2);
 }
 
 }  // namespace crp

@@ -11,19 +11,20 @@
 //     in row order, and the sums are applied at the end of the epoch (the
 //     symmetric graph holds each edge in both rows, so both ends move);
 //   * a due edge (i, j) attracts i towards j by clip(g (y_i - y_j)) alpha_t
-//     with g = -2 a b (d2^b / d2) / (a d2^b + 1) (0 for d2 = 0), then draws `neg`
-//     vertices k from a counter-based SplitMix64 (state seed + (t 2^40 + e 16
-//     + p + 1) 0x9E3779B97F4A7C15) and repels i from each (k != i) by
-//     clip(g' (y_i - y_k)) alpha_t, g' = 2 gamma b / ((0.001 + d2)(a d2^b + 1)),
-//     or by 4 alpha_t per coordinate when the points coincide;
+//     with g = -2 a b d2^(b-1) / (a d2^b + 1) (0 for d2 = 0), then draws `neg`
+//     vertices k from a counter-based SplitMix64 (state seed + (t 2^40 + e 64
+//     + p + 1) 0x9E3779B97F4A7C15; the edge stride is the largest neg) and
+//     repels i from each (k != i) by clip(g' (y_i - y_k)) alpha_t,
+//     g' = 2 gamma b / ((0.001 + d2)(a d2^b + 1)), or by 4 alpha_t per
+//     coordinate when the points coincide;
 //   * clip to [-4, 4]; alpha_t = alpha0 (1 - t / n_epochs).
 // The embedding is kept in float64 and every sum runs in the order stated,
-// with explicitly rounded operations (no fused multiply-adds), and the power
-// d2^b is the correctly rounded one (table-driven double-double evaluation,
-// the tables made on the device by a table-free series), so the result
-// is the same function of the inputs as any sequential implementation that
-// follows these steps: the dynamics amplify a one-ulp difference in a power
-// into visibly different layouts within tens of epochs.
+// with explicitly rounded operations (no fused multiply-adds), and the powers
+// d2^b and d2^(b-1) are the correctly rounded ones (table-driven double-double
+// evaluation, the tables made on the device by a table-free series), so the
+// result is the same function of the inputs as any sequential implementation
+// that follows these steps: the dynamics amplify a one-ulp difference in a
+// power into visibly different layouts within tens of epochs.
 //
 // One epoch, edge-parallel where the work is:
 //   1. count the due edges of each tile of 4096 edges (at epoch 0; later
@@ -37,10 +38,12 @@
 //      those vertices form one range of the list, and each (due edge, draw)
 //      slot -- the attraction and each negative sample -- one move.  Chunk by
 //      chunk the lanes compute the range's moves (the powers and the random
-//      gathers: nearly all of the arithmetic) into LDS, one slot per lane,
-//      then each lane adds its own vertex's moves in row order, skipping the
-//      negative samples that drew the vertex itself, and writes the new
-//      position (float64 embeddings ping-pong between two buffers).
+//      gathers: nearly all of the arithmetic) into LDS, the attractions
+//      first and then the negative samples, one slot per lane; then each lane
+//      adds its own vertex's moves in row order, skipping the negative
+//      samples that drew the vertex itself (marked in a flag per slot), and
+//      writes the new position (float64 embeddings ping-pong between two
+//      buffers).
 
 #include <hip/hip_runtime.h>
 
@@ -81,7 +84,7 @@ __device__ __forceinline__ int64_t mod_n(uint64_t x, int64_t n, double inv_n) {
 
 // Negative sample p of edge e in epoch t.
 __device__ __forceinline__ int64_t negative(uint64_t seed, int t, int64_t e, int p, int64_t n, double inv_n) {
-    const uint64_t st = seed + ((uint64_t)t * (1ull << 40) + (uint64_t)e * 16ull + (uint64_t)p + 1ull) * kGolden;
+    const uint64_t st = seed + ((uint64_t)t * (1ull << 40) + (uint64_t)e * (uint64_t)kMaxNeg + (uint64_t)p + 1ull) * kGolden;
     return mod_n(sm64_mix(st) >> 11, n, inv_n);
 }
 
@@ -233,35 +236,29 @@ __global__ __launch_bounds__(256) void k_umap_scatter(const double *__restrict__
 
 // Epoch constants of the moves.
 struct Moves {
-    double alpha, a, b, ab2, gb2, inv_n;  // ab2 = -2 a b, gb2 = 2 gamma b
+    double alpha, a, b, bm1, ab2, gb2, inv_n;  // bm1 = b - 1, ab2 = -2 a b, gb2 = 2 gamma b
     int64_t n;
     int t, dim, per;
     uint64_t seed;
 };
 
-// Slot s of the epoch (due edge j = s / per, draw p = s mod per): p = 0 the
-// attraction along the edge, p >= 1 the negative sample p - 1.  slot_fetch
-// gathers what the move needs (the two embedding rows), slot_move computes
-// the clipped, scaled move into out[0 .. dim); a negative sample that drew
-// the vertex itself writes a NaN in out[0], which the sum skips (moves of
-// finite positions are always finite).
+// Slot (due edge j, draw p) of the epoch: p = 0 the attraction along the
+// edge, p >= 1 the negative sample p - 1.  slot_fetch gathers what the move
+// needs (the two embedding rows); a negative sample that drew the vertex
+// itself is marked and makes no move.
 template <int DIMS>
 struct SlotIn {
     double yi[DIMS], yo[DIMS];
-    int p;
     bool self;
 };
 
 template <int DIMS>
-__device__ __forceinline__ void slot_fetch(const Moves &m, int64_t s, const uint32_t *__restrict__ list,
+__device__ __forceinline__ void slot_fetch(const Moves &m, int64_t j, int p, const uint32_t *__restrict__ list,
                                            const uint32_t *__restrict__ erow, const int32_t *__restrict__ indices,
                                            const double *__restrict__ Y0, SlotIn<DIMS> &in) {
-    const int64_t j = s / m.per;
-    const int p = (int)(s - j * m.per);
     const int64_t e = list[j];
     const int64_t i = erow[e];
     const int64_t other = p == 0 ? (int64_t)indices[e] : negative(m.seed, m.t, e, p - 1, m.n, m.inv_n);
-    in.p = p;
     in.self = p > 0 && other == i;
 #pragma unroll
     for (int c = 0; c < DIMS; ++c) {
@@ -271,45 +268,63 @@ __device__ __forceinline__ void slot_fetch(const Moves &m, int64_t s, const uint
 }
 
 template <int DIMS>
-__device__ __forceinline__ void slot_move(const Moves &m, const SlotIn<DIMS> &in, const crp::PowTables &tb,
-                                          double *out) {
-    if (in.self) {
-        out[0] = __builtin_nan("");
-        return;
-    }
-    const int dim = m.dim;
-    double df[DIMS];
+__device__ __forceinline__ double slot_d2(const Moves &m, const SlotIn<DIMS> &in, double *df) {
     double d2 = 0.0;
 #pragma unroll
     for (int c = 0; c < DIMS; ++c)
-        if (c < dim) {
+        if (c < m.dim) {
             df[c] = __dsub_rn(in.yi[c], in.yo[c]);
             d2 = __dadd_rn(d2, __dmul_rn(df[c], df[c]));
         }
-    // one power per slot, whichever the kind of sample (a wave holds both)
-    const double pb = d2 > 0.0 ? crp::pow_rn_t(d2, m.b, tb) : 0.0;
-    if (in.p > 0 && !(d2 > 0.0)) {  // repulsion from the same position
-#pragma unroll
-        for (int c = 0; c < DIMS; ++c)
-            if (c < dim) out[c] = __dmul_rn(4.0, m.alpha);
-        return;
+    return d2;
+}
+
+// Attraction: g = -2 a b d2^(b-1) / (a d2^b + 1), 0 when the points coincide.
+template <int DIMS>
+__device__ __forceinline__ void attract_move(const Moves &m, const SlotIn<DIMS> &in, const crp::PowTables &tb,
+                                             double *out) {
+    double df[DIMS];
+    const double d2 = slot_d2<DIMS>(m, in, df);
+    double g = 0.0;
+    if (d2 > 0.0) {
+        double pbm1, pb;
+        crp::pow2_rn_t(d2, m.bm1, m.b, tb, &pbm1, &pb);
+        g = __ddiv_rn(__dmul_rn(m.ab2, pbm1), __dadd_rn(__dmul_rn(m.a, pb), 1.0));
     }
-    double g;
-    if (in.p == 0)
-        g = d2 > 0.0 ? __ddiv_rn(__dmul_rn(m.ab2, __ddiv_rn(pb, d2)), __dadd_rn(__dmul_rn(m.a, pb), 1.0)) : 0.0;
-    else
-        g = __ddiv_rn(m.gb2, __dmul_rn(__dadd_rn(0.001, d2), __dadd_rn(__dmul_rn(m.a, pb), 1.0)));
 #pragma unroll
     for (int c = 0; c < DIMS; ++c)
-        if (c < dim) out[c] = __dmul_rn(clip4(__dmul_rn(g, df[c])), m.alpha);
+        if (c < m.dim) out[c] = __dmul_rn(clip4(__dmul_rn(g, df[c])), m.alpha);
+}
+
+// Repulsion: g = 2 gamma b / ((0.001 + d2)(a d2^b + 1)); a push of 4 alpha
+// per coordinate when the points coincide.
+template <int DIMS>
+__device__ __forceinline__ void repel_move(const Moves &m, const SlotIn<DIMS> &in, const crp::PowTables &tb,
+                                           double *out) {
+    double df[DIMS];
+    const double d2 = slot_d2<DIMS>(m, in, df);
+    if (!(d2 > 0.0)) {
+#pragma unroll
+        for (int c = 0; c < DIMS; ++c)
+            if (c < m.dim) out[c] = __dmul_rn(4.0, m.alpha);
+        return;
+    }
+    const double pb = crp::pow_rn_t(d2, m.b, tb);
+    const double g = __ddiv_rn(m.gb2, __dmul_rn(__dadd_rn(0.001, d2), __dadd_rn(__dmul_rn(m.a, pb), 1.0)));
+#pragma unroll
+    for (int c = 0; c < DIMS; ++c)
+        if (c < m.dim) out[c] = __dmul_rn(clip4(__dmul_rn(g, df[c])), m.alpha);
 }
 
 // One wave (block) per 64 consecutive vertices, lane L for vertex i0 + L.
 // The due edges of vertex i are list[pos[indptr[i]] .. pos[indptr[i+1]]), in
 // row order, and its slots [pos[indptr[i]] per, pos[indptr[i+1]] per), so the
-// wave's slots form one range.  Chunk by chunk, the lanes compute the range's
-// moves into LDS (consecutive slots on consecutive lanes), then each lane
-// adds its own vertex's moves in order.
+// wave's due edges, and their slots, form one range.  Chunk by chunk (whole
+// due edges), the lanes compute the moves into LDS -- first the attractions
+// (one lane per due edge: two powers each), then the negative samples (one
+// lane per draw: one power each), so that a wave's lanes evaluate the same
+// kind of move together -- then each lane adds its own vertex's moves in
+// slot order, skipping the draws marked as the vertex itself.
 constexpr int kMoveLds = 1024;  // float64 moves per chunk (8 KiB)
 constexpr int kSumUnroll = 8;   // moves read from LDS per round, then added in order
 
@@ -323,19 +338,25 @@ __global__ __launch_bounds__(64) void k_umap_epoch(const int64_t *__restrict__ i
                                                    const crp::PowTables *__restrict__ tables) {
     __shared__ crp::PowTables tb;
     __shared__ double buf[kMoveLds];
+    __shared__ uint8_t selfd[kMoveLds];  // slot drew the vertex itself
     static_assert(sizeof(crp::PowTables) == 256 * sizeof(double), "four doubles per lane");
 #pragma unroll
     for (int u = 0; u < 4; ++u)
         reinterpret_cast<double *>(&tb)[u * 64 + threadIdx.x] = reinterpret_cast<const double *>(tables)[u * 64 + threadIdx.x];
     __syncthreads();
     const int lane = threadIdx.x;
-    const int dim = m.dim, per = m.per;
+    const int dim = m.dim, per = m.per, neg = per - 1;
     const int64_t n = m.n;
-    const int64_t chunk = kMoveLds / dim;  // slots per chunk
+    const int jchunk = std::max(1, kMoveLds / (per * dim));  // due edges per chunk (per * dim <= 520)
+    // a lane fetches four of its slots (two when dim > 2) before computing
+    // them, so that their dependent loads (list, edge, two embedding rows)
+    // overlap; deeper groups raise the register count and cost more
+    // occupancy than they hide
+    constexpr int PFD = DIMS <= 2 ? 4 : 2;
     for (int64_t i0 = (int64_t)blockIdx.x * 64; i0 < n; i0 += (int64_t)gridDim.x * 64) {
         const int64_t i = i0 + lane;
-        const int64_t S0 = (int64_t)pos[indptr[i0]] * per;
-        const int64_t S1 = (int64_t)pos[indptr[std::min<int64_t>(i0 + 64, n)]] * per;
+        const int64_t J0 = pos[indptr[i0]];
+        const int64_t J1 = pos[indptr[std::min<int64_t>(i0 + 64, n)]];
         int64_t lo = 0, hi = 0;
         if (i < n) {
             lo = (int64_t)pos[indptr[i]] * per;
@@ -344,39 +365,63 @@ __global__ __launch_bounds__(64) void k_umap_epoch(const int64_t *__restrict__ i
         double mv[DIMS];
 #pragma unroll
         for (int c = 0; c < DIMS; ++c) mv[c] = 0.0;
-        for (int64_t c0 = S0; c0 < S1; c0 += chunk) {
-            const int64_t c1 = std::min<int64_t>(c0 + chunk, S1);
-            // a lane fetches four of its slots (two when dim > 2) before
-            // computing them, so that their dependent loads (list, edge, two
-            // embedding rows) overlap; deeper groups raise the register count
-            // and cost more occupancy than they hide
-            constexpr int PFD = DIMS <= 2 ? 4 : 2;
-            for (int64_t sb = c0 + lane; sb < c1; sb += (int64_t)PFD * 64) {
+        for (int64_t j0 = J0; j0 < J1; j0 += jchunk) {
+            const int nj = (int)std::min<int64_t>(jchunk, J1 - j0);
+            // attractions: slot jj * per of the chunk
+            for (int jb = lane; jb < nj; jb += PFD * 64) {
+                SlotIn<DIMS> in[PFD];
+#pragma unroll
+                for (int u = 0; u < PFD; ++u)
+                    if (jb + u * 64 < nj) slot_fetch<DIMS>(m, j0 + jb + u * 64, 0, list, erow, indices, Y0, in[u]);
+#pragma unroll
+                for (int u = 0; u < PFD; ++u) {
+                    const int jj = jb + u * 64;
+                    if (jj < nj) {
+                        attract_move<DIMS>(m, in[u], tb, buf + jj * per * dim);
+                        selfd[jj * per] = 0;
+                    }
+                }
+            }
+            // negative samples: draw q of the chunk is slot (q / neg) per + 1 + q mod neg
+            const int nq = nj * neg;
+            for (int qb = lane; qb < nq; qb += PFD * 64) {
                 SlotIn<DIMS> in[PFD];
 #pragma unroll
                 for (int u = 0; u < PFD; ++u) {
-                    const int64_t s = sb + (int64_t)u * 64;
-                    if (s < c1) slot_fetch<DIMS>(m, s, list, erow, indices, Y0, in[u]);
+                    const int q = qb + u * 64;
+                    if (q < nq) {
+                        const int jj = q / neg;
+                        slot_fetch<DIMS>(m, j0 + jj, 1 + q - jj * neg, list, erow, indices, Y0, in[u]);
+                    }
                 }
 #pragma unroll
                 for (int u = 0; u < PFD; ++u) {
-                    const int64_t s = sb + (int64_t)u * 64;
-                    if (s < c1) slot_move<DIMS>(m, in[u], tb, buf + (s - c0) * dim);
+                    const int q = qb + u * 64;
+                    if (q < nq) {
+                        const int jj = q / neg;
+                        const int sl = jj * per + 1 + q - jj * neg;
+                        selfd[sl] = in[u].self ? 1 : 0;
+                        if (!in[u].self) repel_move<DIMS>(m, in[u], tb, buf + sl * dim);
+                    }
                 }
             }
             __syncthreads();
-            const int64_t s1 = std::min<int64_t>(hi, c1);
+            const int64_t c0 = j0 * per;
+            const int64_t s1 = std::min<int64_t>(hi, (j0 + nj) * per);
             for (int64_t sb = std::max<int64_t>(lo, c0); sb < s1; sb += kSumUnroll) {
                 double v[kSumUnroll][DIMS];
+                bool skip[kSumUnroll];
 #pragma unroll
                 for (int u = 0; u < kSumUnroll; ++u) {
+                    const bool in_range = sb + u < s1;
+                    skip[u] = !in_range || selfd[in_range ? sb + u - c0 : 0] != 0;
                     const double *tm = buf + (sb + u - c0) * dim;
 #pragma unroll
-                    for (int c = 0; c < DIMS; ++c) v[u][c] = (sb + u < s1 && c < dim) ? tm[c] : 0.0;
+                    for (int c = 0; c < DIMS; ++c) v[u][c] = (in_range && c < dim) ? tm[c] : 0.0;
                 }
 #pragma unroll
                 for (int u = 0; u < kSumUnroll; ++u) {
-                    if (sb + u >= s1 || __builtin_isnan(v[u][0])) continue;  // NaN: a sample that drew i itself
+                    if (skip[u]) continue;
 #pragma unroll
                     for (int c = 0; c < DIMS; ++c)
                         if (c < dim) mv[c] = __dadd_rn(mv[c], v[u][c]);
@@ -471,9 +516,10 @@ int umap_layout(const int64_t *indptr, const int32_t *indices, const float *weig
         return RSC_ERR_INVALID_ARG;
     }
     if (n < 1 || nnz < 0 || dim < 1 || dim > kMaxDim || n_epochs < 1 || neg < 0 || neg > kMaxNeg ||
-        !(a > 0.0) || !(b > 0.0) || !(gamma >= 0.0) || !(alpha0 > 0.0)) {
-        set_error("umap_layout: need n >= 1, 1 <= dim <= 8, n_epochs >= 1, 0 <= neg <= 64, a, b, alpha0 > 0, "
-                  "gamma >= 0");
+        !(a > 0.0) || !(b > 0.0) || !(b <= 64.0) || !(gamma >= 0.0) || !(alpha0 > 0.0) || !(a < INFINITY) ||
+        !(gamma < INFINITY) || !(alpha0 < INFINITY)) {
+        set_error("umap_layout: need n >= 1, 1 <= dim <= 8, n_epochs >= 1, 0 <= neg <= 64, 0 < b <= 64, "
+                  "finite a, alpha0 > 0 and finite gamma >= 0");
         return RSC_ERR_INVALID_ARG;
     }
     if (!shape_ok(n, nnz, dim, neg) || n_epochs >= (1 << 23)) {
@@ -534,7 +580,7 @@ int umap_layout(const int64_t *indptr, const int32_t *indices, const float *weig
             }
             {
                 ScopedTimer tt("umap_moves", s);
-                const Moves mv{epoch_alpha(alpha0, t, n_epochs), a, b, (-2.0 * a) * b, (2.0 * gamma) * b,
+                const Moves mv{epoch_alpha(alpha0, t, n_epochs), a, b, b - 1.0, (-2.0 * a) * b, (2.0 * gamma) * b,
                                1.0 / (double)n, n, t, dim, 1 + neg, seed};
                 if (dim <= 2)
                     hipLaunchKernelGGL(k_umap_epoch<2>, dim3(g_epoch), dim3(64), 0, s, indptr, (const uint32_t *)w.pos,

@@ -2,10 +2,10 @@
 oracle, plus the determinism and the degenerate cases of the schedule.
 
 Both sides run the same float64 operations in the same order (explicitly
-rounded on the GPU, no contraction in the oracle) and take the power d2^b
-correctly rounded (double-double on the GPU, quadruple precision rounded in
-the oracle), so the layouts are the same function of the inputs: the float32
-outputs must agree bit for bit at every depth.  (With the math libraries'
+rounded on the GPU, no contraction in the oracle) and take the powers d2^b
+and d2^(b-1) correctly rounded (double-double on the GPU, quadruple precision
+rounded in the oracle), so the layouts are the same function of the inputs:
+the float32 outputs must agree bit for bit at every depth.  (With the math libraries'
 own pow, which each miss the nearest double in about 1 case in 1000, the
 layouts agree bitwise for a few epochs and then part: the dynamics amplify a
 one-ulp difference.)
@@ -209,6 +209,18 @@ def test_single_vertex_and_self_draws(rsc):
     got = gpu_layout(rsc, two, Y2, n_epochs=9, neg=7, seed=8)
     want = cpu_layout(two, Y2, 9, neg=7, seed=8)
     assert np.array_equal(got, want.astype(np.float32))
+
+
+def test_overflowing_power_turns_nan_on_both_sides(rsc):
+    # b = 60 and points 1e6 apart: d2^b and d2^(b-1) exceed the largest
+    # double, the attraction is inf / inf, and the layout turns NaN exactly
+    # where the oracle's does (no move is silently dropped)
+    two = (np.array([0, 1, 2, 2], np.int64), np.array([1, 0], np.int32), np.ones(2, np.float32))
+    Y0 = np.array([[0.0, 0.0], [1e6, 0.0], [5.0, 5.0]], np.float32)
+    got = gpu_layout(rsc, two, Y0, n_epochs=3, a=1.0, b=60.0, neg=3, seed=2)
+    want = cpu_layout(two, Y0, 3, a=1.0, b=60.0, neg=3, seed=2).astype(np.float32)
+    assert np.isnan(want[:2]).all() and np.isfinite(want[2]).all()
+    assert np.array_equal(got, want, equal_nan=True)
 
 
 @pytest.fixture(scope="module")
