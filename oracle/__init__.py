@@ -10,7 +10,8 @@ numpy arrays.  ``mlp.py`` holds the float64 reference of the partition
 router's network, ``partition.py`` the k-means partitions and the routed
 form's candidate sets, ``edistance.py`` the group-pair distance sums and
 energy distances, ``pca.py`` the sparse PCA that produces the embedding,
-``umap.py`` the UMAP layout of the graph.
+``umap.py`` the UMAP layout of the graph, ``leiden.py`` Leiden communities
+of the graph (arithmetic in ``leiden.c``).
 """
 
 from __future__ import annotations
@@ -24,18 +25,20 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "leiden.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
 
 
 def build(force: bool = True) -> str:
-    """Compile ``oracle.c`` into ``liboracle.so`` with gcc (OpenMP, no contraction)."""
-    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+    """Compile ``oracle.c`` and ``leiden.c`` into ``liboracle.so`` with gcc (OpenMP, no contraction)."""
+    if (not force and os.path.exists(_LIB)
+            and all(os.path.getmtime(_LIB) >= os.path.getmtime(src) for src in _SRCS)):
         return _LIB
     tmp = _LIB + f".tmp{os.getpid()}"
     cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
-           "-fno-fast-math", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lquadmath", "-lm"]
+           "-fno-fast-math", "-Wall", "-Wextra", "-o", tmp, *_SRCS, "-lquadmath", "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, _LIB)
     return _LIB
@@ -72,6 +75,12 @@ def _load():
             lib.oracle_splitmix64_next.restype = ctypes.c_uint64
             lib.oracle_umap_negative.argtypes = [ctypes.c_uint64, i32, i64, i32, i64]
             lib.oracle_umap_negative.restype = i64
+            lib.oracle_leiden.argtypes = [P, P, P, i64, ctypes.c_double, P, P, P]
+            lib.oracle_leiden.restype = i32
+            lib.oracle_leiden_refine.argtypes = [P, P, P, i64, ctypes.c_double, P, P]
+            lib.oracle_leiden_refine.restype = i32
+            lib.oracle_leiden_scale.argtypes = [i64, ctypes.c_double]
+            lib.oracle_leiden_scale.restype = i32
             _lib = lib
     return _lib
 

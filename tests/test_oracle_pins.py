@@ -906,3 +906,182 @@ def test_umap_moves_are_clipped_at_four():
     Ya = ou.layout(*_two_points(), y0, n_epochs=2, a=1.0, b=1.0, neg=0)
     Yr = ou.layout(*_two_points(), y0, n_epochs=2, a=1.0, b=1.0, gamma=1e6, neg=neg, seed=seed)
     np.testing.assert_allclose(Yr[0] - Ya[0], [-2.0 * hits, 0.0], rtol=0, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Leiden communities (modularity by its definition, known optima, the
+# algorithm's connectivity guarantee, invariances of the fixed-point reading;
+# reading in leiden.c).
+# ---------------------------------------------------------------------------
+
+def _csr(A):
+    import scipy.sparse as sp
+
+    M = sp.csr_matrix(np.asarray(A, dtype=np.float64))
+    M.sort_indices()
+    return M.indptr.astype(np.int64), M.indices.astype(np.int32), M.data.astype(np.float32)
+
+
+def _cliques(sizes, bridges):
+    n = sum(sizes)
+    A = np.zeros((n, n))
+    off = np.cumsum([0] + list(sizes))
+    for a, b in zip(off[:-1], off[1:]):
+        A[a:b, a:b] = 1.0
+    np.fill_diagonal(A, 0.0)
+    for i, j in bridges:
+        A[i, j] = A[j, i] = 1.0
+    return A
+
+
+def _modularity_dense(A, labels, gamma):
+    # Q = 1/(2m) sum_ij (A_ij - gamma k_i k_j / 2m) [c_i = c_j]
+    A = np.asarray(A, dtype=np.float64)
+    k = A.sum(1)
+    two_m = k.sum()
+    same = labels[:, None] == labels[None, :]
+    return float(((A - gamma * np.outer(k, k) / two_m) * same).sum() / two_m)
+
+
+def _same_partition(a, b):
+    # equal up to renaming the communities
+    pairs = set(zip(a.tolist(), b.tolist()))
+    return len(pairs) == len(set(a.tolist())) == len(set(b.tolist()))
+
+
+def test_leiden_modularity_matches_its_definition():
+    from oracle import leiden as ol
+
+    rng = np.random.default_rng(3)
+    for n, p, gamma in [(30, 0.2, 1.0), (60, 0.1, 0.5), (80, 0.05, 2.0)]:
+        # weights on a binary grid of 1/8: exact in the fixed point, so the
+        # reported modularity is the dense formula's to rounding
+        W = np.triu((rng.random((n, n)) < p) * rng.integers(1, 9, (n, n)) / 8.0, 1)
+        A = W + W.T
+        lab, q, _ = ol.leiden(*_csr(A), gamma=gamma)
+        assert abs(q - _modularity_dense(A, lab, gamma)) < 1e-12
+        # the result is no worse than every vertex alone or one community per component
+        from scipy.sparse.csgraph import connected_components
+
+        _, comp = connected_components(A != 0, directed=False)
+        assert q >= _modularity_dense(A, np.arange(n), gamma) - 1e-12
+        assert q >= _modularity_dense(A, comp, gamma) - 1e-12
+
+
+def test_leiden_two_cliques_and_a_ring_of_cliques():
+    from oracle import leiden as ol
+
+    lab, _, _ = ol.leiden(*_csr(_cliques([5, 5], [(0, 5)])))
+    assert lab.tolist() == [0] * 5 + [1] * 5
+    sizes = [5] * 6
+    off = np.cumsum([0] + sizes)
+    A = _cliques(sizes, [(off[i], off[(i + 1) % 6] + 1) for i in range(6)])
+    lab, q, _ = ol.leiden(*_csr(A))
+    assert lab.tolist() == sum([[c] * 5 for c in range(6)], [])
+    # one clique per community: In = 20 each, Tot = 22 each, 2m = 132
+    assert abs(q - 6 * (20 / 132 - (22 / 132) ** 2)) < 1e-12
+
+
+def test_leiden_recovers_a_planted_partition():
+    from oracle import leiden as ol
+
+    rng = np.random.default_rng(0)
+    blocks = np.repeat(np.arange(4), 50)
+    P = np.where(blocks[:, None] == blocks[None, :], 0.5, 0.01)
+    A = np.triu(rng.random((200, 200)) < P, 1).astype(float)
+    A = A + A.T
+    lab, _, _ = ol.leiden(*_csr(A))
+    assert _same_partition(lab, blocks)
+
+
+def test_leiden_communities_are_connected_and_gamma_limits():
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components
+
+    import oracle
+    from oracle import leiden as ol
+
+    X = synth.mixture(2000, d=50, n_clusters=12, seed=41)
+    g = oracle.knn_graph(X, 15)
+    M = sp.csr_matrix((g["data"], g["indices"], g["indptr"]))
+    lab, q, levels = ol.leiden(g["indptr"], g["indices"], g["data"])
+    assert levels >= 2 and q > 0.5
+    for c in np.unique(lab):
+        rows = np.where(lab == c)[0]
+        assert connected_components(M[rows][:, rows], directed=False)[0] == 1, f"community {c} is disconnected"
+    # labels numbered by first appearance
+    first = [int(lab[np.where(lab == c)[0][0]]) for c in np.unique(lab)]
+    assert lab[0] == 0 and sorted(first) == list(range(len(first)))
+    order = [lab[np.where(lab == c)[0][0]] for c in sorted(np.unique(lab), key=lambda c: np.where(lab == c)[0][0])]
+    assert order == list(range(len(order)))
+    # a vanishing resolution merges each connected component into one community
+    ncomp, comp = connected_components(M, directed=False)
+    lab0, _, _ = ol.leiden(g["indptr"], g["indices"], g["data"], gamma=1e-7)
+    assert _same_partition(lab0, comp)
+    # a huge resolution leaves every vertex alone
+    labh, _, _ = ol.leiden(g["indptr"], g["indices"], g["data"], gamma=1e6)
+    assert labh.tolist() == list(range(2000))
+
+
+def test_leiden_fixed_point_invariances():
+    from oracle import leiden as ol
+
+    import oracle
+
+    X = synth.mixture(1500, d=50, n_clusters=8, seed=7)
+    g = oracle.knn_graph(X, 15)
+    ip, ix, w = g["indptr"], g["indices"], g["data"]
+    lab, q, _ = ol.leiden(ip, ix, w)
+    # scaling every weight by a power of two moves the fixed-point exponent
+    # by the same amount: the integers, and so the labels, are unchanged
+    assert ol.scale(len(ix), float(w.max()) * 8) == ol.scale(len(ix), float(w.max())) - 3
+    lab8, q8, _ = ol.leiden(ip, ix, (w * np.float32(8)).astype(np.float32))
+    assert np.array_equal(lab, lab8) and q8 == q
+    # the order of the columns within a row does not matter (every sum is exact)
+    rng = np.random.default_rng(5)
+    ix2, w2 = ix.copy(), w.copy()
+    for i in range(len(ip) - 1):
+        p = rng.permutation(ip[i + 1] - ip[i]) + ip[i]
+        ix2[ip[i]:ip[i + 1]] = ix[p]
+        w2[ip[i]:ip[i + 1]] = w[p]
+    lab2, _, _ = ol.leiden(ip, ix2, w2)
+    assert np.array_equal(lab, lab2)
+
+
+def test_leiden_degenerate_graphs():
+    from oracle import leiden as ol
+
+    # no edges: every vertex alone
+    lab, q, _ = ol.leiden(np.zeros(6, np.int64), np.zeros(0, np.int32), np.zeros(0, np.float32))
+    assert lab.tolist() == list(range(5)) and q == 0.0
+    # isolated vertices beside two cliques keep their own communities
+    A = np.zeros((13, 13))
+    A[:10, :10] = _cliques([5, 5], [(0, 5)])
+    lab, _, _ = ol.leiden(*_csr(A))
+    assert lab.tolist() == [0] * 5 + [1] * 5 + [2, 3, 4]
+    with pytest.raises(ValueError):
+        ol.leiden(*_csr(A), gamma=0.0)
+
+
+def test_leiden_refinement_by_hand():
+    """The refinement step on a 6-vertex graph, derived by hand from the
+    reading.  Edges: triangle 0-1-2 (weight 1), 0-3 (1), 3-4 (3), 4-5 (1);
+    communities C = {0, 1, 2, 3}, D = {4, 5}; gamma = 1.  Degrees k = (3, 2,
+    2, 4, 4, 1), 2m = 16, Tot(C) = 11, Tot(D) = 5.
+      Vertex 3 is not well connected to C: K(3, C - 3) = 1 < k3 (Tot(C) - k3)
+      / 2m = 4 * 7 / 16 = 1.75, so it never joins (it could join {0} with
+      gain 1 - 4 * 3 / 16 = 0.25 >= 0 otherwise).
+      Round 1: 1 -> {0} (gain 1 - 2 * 3 / 16 = 0.625; {0} well connected:
+      E = 3 >= 3 * 8 / 16); 2 prefers {1} (gain 1 - 2 * 2 / 16 = 0.75 over
+      0.625 for {0}), but 1 moves in the same round, so 2's join is
+      cancelled; 5 -> {4} (gain 1 - 1 * 4 / 16 = 0.75).
+      Round 2: 2 -> {0, 1} (K = 2, gain 2 - 2 * 5 / 16 = 1.375; E({0, 1},
+      C - {0, 1}) = 3 >= 5 * 6 / 16).  Round 3: no join.
+    Refined: {0, 1, 2}, {3}, {4, 5}."""
+    from oracle import leiden as ol
+
+    A = np.zeros((6, 6))
+    for i, j, w in [(0, 1, 1), (0, 2, 1), (1, 2, 1), (0, 3, 1), (3, 4, 3), (4, 5, 1)]:
+        A[i, j] = A[j, i] = w
+    R = ol.refine(*_csr(A), np.array([0, 0, 0, 0, 4, 4]))
+    assert R.tolist() == [0, 0, 0, 3, 4, 4]
