@@ -174,8 +174,9 @@ int rsc_knn_read_stats(const void *workspace, size_t workspace_bytes, rsc_knn_st
  * Each sample is its own exact kNN problem (the paper analyses large
  * collections chunk by chunk along the cell axis: Methods, "Memory
  * management and scaling"); results use global row ids, so the kNN graph is
- * block-diagonal and rsc_connectivities applied to the whole output gives the
- * per-sample connectivities at once.
+ * block-diagonal; rsc_connectivities_batched builds the per-sample
+ * connectivities of the whole output at once (and checks that no edge leaves
+ * its sample).
  */
 size_t rsc_knn_batched_workspace_bytes(const int64_t *offsets, int32_t S, int32_t d, int32_t k);
 
@@ -230,6 +231,29 @@ size_t rsc_connectivities_workspace_bytes(int64_t n, int32_t k);
 int rsc_connectivities(const int32_t *idx, const float *dist, int64_t n, int32_t k, int64_t *indptr,
                        int32_t *indices, float *data, int64_t cap, int64_t *nnz, double *rho, double *sigma,
                        void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Connectivities of a batch of samples (the output of rsc_knn_batched):
+ * each sample's fuzzy simplicial set on its own rows, the samples' graphs
+ * side by side in one block-diagonal CSR with global row ids (the paper
+ * analyses large collections sample by sample through offset tables:
+ * Methods, "Perturbation distance computation" and "Memory management and
+ * scaling").
+ *   offsets  HOST int64 [S + 1]: sample s is rows offsets[s] ..
+ *            offsets[s+1]-1; offsets[0] = 0, every sample at least k rows,
+ *            offsets[S] = n <= 2^31 - 2 (RSC_ERR_INVALID_ARG otherwise).
+ *            Copied during the call.
+ *   idx, dist, indptr, indices, data, cap, nnz  as for rsc_connectivities
+ *            over the n rows (cap >= 2 n (k-1)).
+ * Every neighbour in columns 1..k-1 of a row must lie in the row's own
+ * sample: an edge to another sample gives RSC_ERR_BAD_GRAPH after the call,
+ * as do the malformed lists rsc_connectivities rejects.  Synchronises
+ * `stream`.
+ */
+size_t rsc_connectivities_batched_workspace_bytes(const int64_t *offsets, int32_t S, int32_t k);
+int rsc_connectivities_batched(const int32_t *idx, const float *dist, const int64_t *offsets, int32_t S, int32_t k,
+                               int64_t *indptr, int32_t *indices, float *data, int64_t cap, int64_t *nnz,
+                               void *workspace, size_t workspace_bytes, void *stream);
 
 /* ---------------------------------------------------------------------- */
 /* Routed form: coarse partitions, learned router, probed search           */
@@ -542,11 +566,13 @@ int rsc_pca(const int64_t *indptr, const int32_t *indices, const float *data, in
  * computed from the embedding at the start of t and vertex i sums the moves
  * of its own row's due edges in CSR order -- an attraction towards the
  * neighbour, then `neg` repulsions from vertices drawn by a counter-based
- * SplitMix64 (state seed + (t 2^40 + e 16 + p + 1) 0x9E3779B97F4A7C15,
- * k = (mix >> 11) mod n) -- each coordinate clipped to [-4, 4] and scaled by
- * alpha0 (1 - t / n_epochs); attraction -2 a b (d2^b / d2) / (a d2^b + 1),
- * repulsion 2 gamma b / ((0.001 + d2)(a d2^b + 1)), with d2^b the correctly
- * rounded power.  The embedding is kept in float64 and every operation is
+ * SplitMix64 (state seed + (t 2^40 + e 64 + p + 1) 0x9E3779B97F4A7C15,
+ * k = (mix >> 11) mod n; the edge stride 64 is the largest neg, so no two
+ * draws of an epoch share a counter; a draw of the vertex itself is
+ * skipped) -- each coordinate clipped to [-4, 4] and scaled by
+ * alpha0 (1 - t / n_epochs); attraction -2 a b d2^(b-1) / (a d2^b + 1),
+ * repulsion 2 gamma b / ((0.001 + d2)(a d2^b + 1)), with d2^(b-1) and d2^b
+ * each the correctly rounded power.  The embedding is kept in float64 and every operation is
  * rounded as written, so the layout is bitwise reproducible and equals that
  * of any sequential implementation of these steps.
  *   indptr, indices, weights  DEVICE CSR of the symmetric graph (the
@@ -558,7 +584,9 @@ int rsc_pca(const int64_t *indptr, const int32_t *indices, const float *data, in
  *   a, b     the similarity curve (min_dist 0.5, spread 1: a = 0.58303,
  *            b = 1.33417, the least-squares fit of UMAP's target curve);
  *            gamma the repulsion strength (1), alpha0 the initial rate (1),
- *            neg the negative samples per due edge (5).
+ *            neg the negative samples per due edge (5); a > 0 finite,
+ *            0 < b <= 64, 0 <= neg <= 64, n_epochs >= 1, else
+ *            RSC_ERR_INVALID_ARG.
  * Synchronises `stream` once, to report a malformed graph as
  * RSC_ERR_BAD_GRAPH before any epoch runs.  Supports n < 2^31 and
  * nnz < 2^32 - 1; the workspace (rsc_umap_workspace_bytes, 0 for an

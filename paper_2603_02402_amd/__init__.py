@@ -8,6 +8,7 @@ torch's current stream.  Functions mirror the C calls:
 * :func:`connectivities`  -> ``rsc_connectivities``
 * :func:`knn_graph`       -> both, the whole neighbourhood-graph step
 * :func:`knn_batched`     -> ``rsc_knn_batched`` (many samples, one launch)
+* :func:`connectivities_batched` -> ``rsc_connectivities_batched``
 * :mod:`.routed`          -> partitions, the router network, probed and
   routed kNN (``rsc_partition_*``, ``rsc_router_*``, ``rsc_knn_probed``,
   ``rsc_knn_routed``)
@@ -31,7 +32,7 @@ __all__ = [
     "knn", "knn_graph", "connectivities", "knn_workspace_bytes", "connectivities_workspace_bytes",
     "read_knn_stats", "profile_enable", "profile_reset", "profile_get", "RscError", "Workspace",
     "RSC_FP32", "RSC_BF16", "RSC_FP8_E4M3", "RSC_EUCLIDEAN", "RSC_COSINE", "abi_version", "knn_batched", "knn_batched_autotune",
-    "knn_batched_workspace_bytes", "Router", "partition_kmeans", "partition_lists", "partition_labels",
+    "knn_batched_workspace_bytes", "connectivities_batched", "Router", "partition_kmeans", "partition_lists", "partition_labels",
     "knn_probed", "knn_routed", "edistance_groups", "edistance_sums", "edistance_pairwise", "edistance_onesided",
     "pca", "pca_covariance", "umap_layout", "UMAP_A", "UMAP_B",
 ]
@@ -224,6 +225,36 @@ def knn_batched(X, offsets, k: int, out=None, workspace: Workspace | None = None
         idx, dist = out
     check(lib.rsc_knn_batched(_ptr(X), p, S, d, k, _ptr(idx), _ptr(dist), _ptr(ws), ws.numel(), _stream()))
     return idx, dist
+
+
+def connectivities_batched(idx, dist, offsets, workspace: Workspace | None = None, out=None):
+    """Per-sample fuzzy simplicial sets of a batched kNN result as one
+    block-diagonal CSR (``offsets`` on the host; see
+    ``rsc_connectivities_batched``).  Returns a :class:`Graph` without
+    rho/sigma."""
+    torch = _torch()
+    _check_dev(idx, dist)
+    if idx.dtype != torch.int32 or dist.dtype != torch.float32 or idx.shape != dist.shape or idx.dim() != 2:
+        raise ValueError("idx (int32) and dist (float32) must be n x k")
+    n, k = idx.shape
+    off, p = _host_offsets(offsets)
+    S = len(off) - 1
+    lib = load()
+    need = lib.rsc_connectivities_batched_workspace_bytes(p, S, k)
+    ws = (workspace or Workspace(idx.device)).get(need if need else 256)
+    cap = max(1, 2 * n * (k - 1))
+    if out is None:
+        indptr = torch.empty(n + 1, dtype=torch.int64, device=idx.device)
+        indices = torch.empty(cap, dtype=torch.int32, device=idx.device)
+        data = torch.empty(cap, dtype=torch.float32, device=idx.device)
+    else:
+        indptr, indices, data = out
+        cap = indices.numel()
+    nnz = ctypes.c_int64(0)
+    check(lib.rsc_connectivities_batched(_ptr(idx), _ptr(dist), p, S, k, _ptr(indptr), _ptr(indices), _ptr(data),
+                                         cap, ctypes.byref(nnz), _ptr(ws), ws.numel(), _stream()))
+    m = int(nnz.value)
+    return Graph(indptr, indices[:m], data[:m], None, None)
 
 
 def knn_batched_autotune(X, offsets, k: int, workspace: Workspace | None = None):

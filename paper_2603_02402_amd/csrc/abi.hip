@@ -227,10 +227,11 @@ size_t rsc_connectivities_workspace_bytes(int64_t n, int32_t k) {
     return graph_workspace_bytes(n, k);
 }
 
-int rsc_connectivities(const int32_t *idx, const float *dist, int64_t n, int32_t k, int64_t *indptr,
-                       int32_t *indices, float *data, int64_t cap, int64_t *nnz, double *rho, double *sigma,
-                       void *workspace, size_t workspace_bytes, void *stream) {
-    clear_error();
+// Checks shared by the connectivities entry points (sizes, pointers,
+// alignment, CSR capacity).
+static int check_conn_args(const int32_t *idx, const float *dist, int64_t n, int32_t k, const int64_t *indptr,
+                           const int32_t *indices, const float *data, int64_t cap, const int64_t *nnz,
+                           const double *rho, const double *sigma) {
     if (n < 1 || k < 1 || k > n) {
         set_error("need n >= 1 and 1 <= k <= n");
         return RSC_ERR_INVALID_ARG;
@@ -257,10 +258,56 @@ int rsc_connectivities(const int32_t *idx, const float *dist, int64_t n, int32_t
         set_error("CSR capacity must be at least 2 n (k-1) = " + std::to_string(need));
         return RSC_ERR_CAPACITY;
     }
-    int st = check_ws(workspace, workspace_bytes, graph_workspace_bytes(n, k));
+    return RSC_OK;
+}
+
+int rsc_connectivities(const int32_t *idx, const float *dist, int64_t n, int32_t k, int64_t *indptr,
+                       int32_t *indices, float *data, int64_t cap, int64_t *nnz, double *rho, double *sigma,
+                       void *workspace, size_t workspace_bytes, void *stream) {
+    clear_error();
+    int st = check_conn_args(idx, dist, n, k, indptr, indices, data, cap, nnz, rho, sigma);
     if (st != RSC_OK) return st;
-    return graph_run(idx, dist, n, k, indptr, indices, data, cap, nnz, rho, sigma, workspace,
+    st = check_ws(workspace, workspace_bytes, graph_workspace_bytes(n, k));
+    if (st != RSC_OK) return st;
+    return graph_run(idx, dist, n, k, indptr, indices, data, nnz, rho, sigma, workspace,
                      static_cast<hipStream_t>(stream));
+}
+
+// Sample offsets of the batched calls: S >= 1, offsets[0] = 0, each sample at
+// least k rows, total <= 2^31 - 2.  Returns the total row count or -1.
+static int64_t check_batch_offsets(const int64_t *offsets, int32_t S, int32_t k) {
+    if (!offsets || S < 1 || offsets[0] != 0) return -1;
+    for (int32_t s = 0; s < S; ++s)
+        if (offsets[s + 1] - offsets[s] < (int64_t)k) return -1;
+    if (offsets[S] > (int64_t)INT32_MAX - 1) return -1;
+    return offsets[S];
+}
+
+size_t rsc_connectivities_batched_workspace_bytes(const int64_t *offsets, int32_t S, int32_t k) {
+    const int64_t n = check_batch_offsets(offsets, S, k);
+    if (n < 1 || k < 1 || k > 256) return 0;
+    return graph_workspace_bytes(n, k, S);
+}
+
+int rsc_connectivities_batched(const int32_t *idx, const float *dist, const int64_t *offsets, int32_t S, int32_t k,
+                               int64_t *indptr, int32_t *indices, float *data, int64_t cap, int64_t *nnz,
+                               void *workspace, size_t workspace_bytes, void *stream) {
+    clear_error();
+    if (k < 1) {
+        set_error("need k >= 1");
+        return RSC_ERR_INVALID_ARG;
+    }
+    const int64_t n = check_batch_offsets(offsets, S, k);
+    if (n < 0) {
+        set_error("offsets must hold S + 1 >= 2 entries from 0, every sample at least k rows, at most 2^31 - 2 in all");
+        return RSC_ERR_INVALID_ARG;
+    }
+    int st = check_conn_args(idx, dist, n, k, indptr, indices, data, cap, nnz, nullptr, nullptr);
+    if (st != RSC_OK) return st;
+    st = check_ws(workspace, workspace_bytes, graph_workspace_bytes(n, k, S));
+    if (st != RSC_OK) return st;
+    return graph_run_batched(idx, dist, n, k, offsets, S, indptr, indices, data, nnz, workspace,
+                             static_cast<hipStream_t>(stream));
 }
 
 size_t rsc_partition_kmeans_workspace_bytes(int64_t n, int32_t d, int32_t parts) {

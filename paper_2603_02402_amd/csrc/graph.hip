@@ -12,18 +12,26 @@
 //   a_ij     exp(-max(0, d_ij - rho_i)/sigma_i);
 //   w_ij     a_ij + a_ji - a_ij a_ji over the union of both directions.
 //
-// Every stage is a bandwidth-bound pass over the n (k-1) directed edges:
-//   smooth      one thread per row, distances in registers;
-//   count       one thread per row: find the reverse edge in the neighbour's
-//               list (k-1 int32, one cache line), compute the union weight
-//               once, count kept entries; one-way edges add one entry to the
-//               neighbour's row (atomic counter);
-//   scan        int64 exclusive scan of the row lengths -> indptr;
-//   fill        each row writes its own entries in list order and appends
-//               the one-way reverse entries to the neighbour's row;
-//   sort        one wave per row ranks the (unique) columns and scatters
-//               them into ascending order, which also makes the output
-//               independent of the atomic append order.
+// Stages (m = k - 1 directed edges per row, E = n m edges):
+//   smooth   one thread per row: rho, the bisection for sigma, and the m
+//            directed weights a (float64, row-major n x m);
+//   probe    one lane per edge, whole rows per wave (64 / m rows): the lane
+//            of edge i -> j loads j's m neighbour ids in one batch and looks
+//            for i; the union weight is computed once from the two float64
+//            weights, and the row's kept entries are counted with a ballot.
+//            A kept one-way edge takes a slot among j's reverse entries from
+//            an atomic counter and records it, so no later pass needs
+//            another atomic;
+//   scan     two int64 exclusive scans in one pass: row lengths (own kept
+//            edges + reverse entries) -> indptr, and reverse counts -> the
+//            start of each row's reverse entries;
+//   fill     one lane per edge again: each kept one-way edge writes (i, w)
+//            as one 8-byte record into its slot of j's reverse entries;
+//   sort     one wave per row: the row's own edges (read from the edge
+//            arrays in place) and its reverse entries are ranked by column
+//            with lane broadcasts and written to their sorted positions in
+//            the CSR, which also makes the output independent of the atomic
+//            slot order.
 // Weights of a pair are computed from the same two float64 operands with
 // commutative operations, so w_ij and w_ji are bitwise equal.
 
@@ -42,10 +50,11 @@ constexpr int kWave = 64;
 constexpr int kScanThreads = 1024;
 constexpr int kScanItems = 4;
 constexpr int kScanTile = kScanThreads * kScanItems;
+constexpr int kEdgeBlock = 256;  // threads per block of the per-edge kernels (4 waves)
 
 struct GraphResult {
     int64_t nnz;
-    int32_t error;  // bit 0: index out of range or self; bit 1: repeated neighbour
+    int32_t error;  // bit 0: index out of range or self; bit 1: repeated neighbour; bit 2: edge leaves its sample
     int32_t degenerate;
 };
 
@@ -67,19 +76,40 @@ __global__ void k_init_result(GraphResult *r) {
     }
 }
 
-// Sum over the row's neighbour slots of exp(-max(0, d - rho)/sigma), in slot order.
+// Sum over the row's neighbour slots of exp(-g_j * rinv) with g_j =
+// max(0, d_j - rho), in slot order.  The bisection multiplies by the
+// reciprocal of sigma (one division per step instead of one per slot); the
+// weights themselves divide by sigma as the definition writes them.
 template <int KM>
-__device__ __forceinline__ double membership_sum(const double (&dd)[KM], int m, double rho, double sigma) {
+__device__ __forceinline__ double membership_sum(const double (&gg)[KM], int m, double rinv) {
     double s = 0.0;
 #pragma unroll
-    for (int j = 0; j < KM; ++j) {
-        if (j < m) {
-            double g = dd[j] - rho;
-            if (g < 0.0) g = 0.0;
-            s = __dadd_rn(s, exp(-g / sigma));
-        }
-    }
+    for (int j = 0; j < KM; ++j)
+        if (j < m) s = __dadd_rn(s, exp(-gg[j] * rinv));
     return s;
+}
+
+// Bisection for sigma from sigma = 1: double until the sum exceeds the
+// target, then halve the bracket; stop when the sum is within 1e-12 of the
+// target (relative), the bracket is one ulp wide, or after 200 steps.
+template <class SumFn>
+__device__ __forceinline__ double bisect_sigma(double target, SumFn sum_at) {
+    double sigma = 1.0;
+    double lo = 0.0, hi = INFINITY;
+    for (int it = 0; it < 200; ++it) {
+        const double f = sum_at(1.0 / sigma);
+        if (fabs(f - target) <= 1e-12 * target) break;
+        if (f > target)
+            hi = sigma;
+        else
+            lo = sigma;
+        if (isinf(hi))
+            sigma = sigma * 2.0;
+        else
+            sigma = (lo + hi) / 2.0;
+        if (!isinf(hi) && hi - lo <= ldexp(hi, -52)) break;
+    }
+    return sigma;
 }
 
 template <int KM>
@@ -98,9 +128,13 @@ __global__ __launch_bounds__(256) void k_smooth(const float *__restrict__ dist, 
     for (int j = 0; j < KM; ++j)
         if (j < m && dd[j] > 0.0 && (rho == 0.0 || dd[j] < rho)) rho = dd[j];
     int at_rho = 0;
+    double gg[KM];
 #pragma unroll
-    for (int j = 0; j < KM; ++j)
+    for (int j = 0; j < KM; ++j) {
         if (j < m && dd[j] <= rho) ++at_rho;
+        const double g = dd[j] - rho;
+        gg[j] = g < 0.0 ? 0.0 : g;
+    }
     const double target = log2((double)k);
     double sigma;
     double *ai = a + i * m;
@@ -112,29 +146,10 @@ __global__ __launch_bounds__(256) void k_smooth(const float *__restrict__ dist, 
             if (j < m) ai[j] = dd[j] <= rho ? 1.0 : 0.0;
         atomicAdd(&res->degenerate, 1);
     } else {
-        sigma = 1.0;
-        double lo = 0.0, hi = INFINITY;
-        for (int it = 0; it < 200; ++it) {
-            const double f = membership_sum<KM>(dd, m, rho, sigma);
-            if (fabs(f - target) <= 1e-12 * target) break;
-            if (f > target)
-                hi = sigma;
-            else
-                lo = sigma;
-            if (isinf(hi))
-                sigma = sigma * 2.0;
-            else
-                sigma = (lo + hi) / 2.0;
-            if (!isinf(hi) && hi - lo <= ldexp(hi, -52)) break;
-        }
+        sigma = bisect_sigma(target, [&](double rinv) { return membership_sum<KM>(gg, m, rinv); });
 #pragma unroll
-        for (int j = 0; j < KM; ++j) {
-            if (j < m) {
-                double g = dd[j] - rho;
-                if (g < 0.0) g = 0.0;
-                ai[j] = exp(-g / sigma);
-            }
-        }
+        for (int j = 0; j < KM; ++j)
+            if (j < m) ai[j] = exp(-gg[j] / sigma);
     }
     if (rho_out) rho_out[i] = rho;
     if (sigma_out) sigma_out[i] = sigma;
@@ -143,16 +158,6 @@ __global__ __launch_bounds__(256) void k_smooth(const float *__restrict__ dist, 
 // The same computation for rows with more than 64 neighbour slots: the
 // distances are read from memory (in slot order, as above) instead of being
 // held in registers.
-__device__ __forceinline__ double membership_sum_mem(const float *dr, int m, double rho, double sigma) {
-    double s = 0.0;
-    for (int j = 0; j < m; ++j) {
-        double g = (double)dr[j] - rho;
-        if (g < 0.0) g = 0.0;
-        s = __dadd_rn(s, exp(-g / sigma));
-    }
-    return s;
-}
-
 __global__ __launch_bounds__(256) void k_smooth_wide(const float *__restrict__ dist, int64_t n, int k,
                                                      double *__restrict__ a, double *__restrict__ rho_out,
                                                      double *__restrict__ sigma_out, GraphResult *__restrict__ res) {
@@ -176,21 +181,15 @@ __global__ __launch_bounds__(256) void k_smooth_wide(const float *__restrict__ d
         for (int j = 0; j < m; ++j) ai[j] = (double)dr[j] <= rho ? 1.0 : 0.0;
         atomicAdd(&res->degenerate, 1);
     } else {
-        sigma = 1.0;
-        double lo = 0.0, hi = INFINITY;
-        for (int it = 0; it < 200; ++it) {
-            const double f = membership_sum_mem(dr, m, rho, sigma);
-            if (fabs(f - target) <= 1e-12 * target) break;
-            if (f > target)
-                hi = sigma;
-            else
-                lo = sigma;
-            if (isinf(hi))
-                sigma = sigma * 2.0;
-            else
-                sigma = (lo + hi) / 2.0;
-            if (!isinf(hi) && hi - lo <= ldexp(hi, -52)) break;
-        }
+        sigma = bisect_sigma(target, [&](double rinv) {
+            double s = 0.0;
+            for (int j = 0; j < m; ++j) {
+                double g = (double)dr[j] - rho;
+                if (g < 0.0) g = 0.0;
+                s = __dadd_rn(s, exp(-g * rinv));
+            }
+            return s;
+        });
         for (int j = 0; j < m; ++j) {
             double g = (double)dr[j] - rho;
             if (g < 0.0) g = 0.0;
@@ -201,47 +200,114 @@ __global__ __launch_bounds__(256) void k_smooth_wide(const float *__restrict__ d
     if (sigma_out) sigma_out[i] = sigma;
 }
 
-// Union weight of each directed edge and the row lengths.
-__global__ __launch_bounds__(256) void k_union_count(const int32_t *__restrict__ idx, const double *__restrict__ a,
-                                                     int64_t n, int k, float *__restrict__ wf,
-                                                     uint8_t *__restrict__ mutual, int32_t *__restrict__ own,
-                                                     int32_t *__restrict__ rev_cnt, GraphResult *__restrict__ res) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int m = k - 1;
-    int kept = 0;
-    for (int s = 0; s < m; ++s) {
-        const int64_t e = i * m + s;
-        const int32_t j = idx[i * k + 1 + s];
-        if (j < 0 || j >= n || j == i) {
-            atomicOr(&res->error, 1);
-            wf[e] = 0.f;
-            mutual[e] = 0;
-            continue;
-        }
-        const int32_t *lj = idx + (int64_t)j * k + 1;
-        int sp = -1;
-        for (int t = 0; t < m; ++t) {
-            if (lj[t] == (int32_t)i) {
-                sp = t;
-                break;
+// Lane -> (row within the wave's group, slot) of the per-edge kernels.  A
+// group is R = 64 / m whole rows when m <= 32 (a row's edges sit on
+// consecutive lanes), else one row walked in chunks of 64 slots.
+struct EdgeMap {
+    int m, R;
+    int64_t groups;
+    __device__ EdgeMap(int64_t n, int m_) : m(m_), R(m_ <= 32 ? kWave / m_ : 1), groups((n + R - 1) / R) {}
+};
+
+// Sample bounds of row i: [seg[s], seg[s+1]) with seg ascending (S samples).
+__device__ __forceinline__ void sample_of(const int64_t *__restrict__ seg, int S, int64_t i, int64_t *lo,
+                                          int64_t *hi) {
+    int a = 0, b = S;  // invariant: seg[a] <= i < seg[b]
+    while (b - a > 1) {
+        const int c = (a + b) >> 1;
+        if (seg[c] <= i)
+            a = c;
+        else
+            b = c;
+    }
+    *lo = seg[a];
+    *hi = seg[b];
+}
+
+// Union weight of every directed edge, the rows' kept counts and the slots
+// of the one-way edges among their targets' reverse entries.
+//   wf[e]   float32 union weight (0: dropped, or a rejected edge);
+//   rs[e]   slot among row j's reverse entries (kept one-way edge), -1 for a
+//           mutual edge, -2 for a dropped or rejected one.
+__global__ __launch_bounds__(kEdgeBlock) void k_union_probe(const int32_t *__restrict__ idx,
+                                                            const double *__restrict__ a, int64_t n, int k,
+                                                            const int64_t *__restrict__ seg, int S,
+                                                            float *__restrict__ wf, int32_t *__restrict__ rs,
+                                                            int32_t *__restrict__ own,
+                                                            int32_t *__restrict__ rev_cnt,
+                                                            GraphResult *__restrict__ res) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const EdgeMap mp(n, k - 1);
+    const int m = mp.m;
+    const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    int err = 0;
+    for (int64_t g = wave0; g < mp.groups; g += waves) {
+        const int64_t i0 = g * mp.R;
+        int own_acc = 0;
+        const int chunks = mp.R > 1 ? 1 : (m + kWave - 1) / kWave;
+        for (int c = 0; c < chunks; ++c) {
+            int r, s;
+            if (mp.R > 1) {
+                r = lane / m;
+                s = lane - r * m;
+            } else {
+                r = 0;
+                s = c * kWave + lane;
+            }
+            const int64_t i = i0 + r;
+            const bool act = (mp.R > 1 ? r < mp.R : s < m) && i < n;
+            float f = 0.f;
+            if (act) {
+                const int64_t e = i * m + s;
+                const int32_t j = idx[i * k + 1 + s];
+                bool ok = j >= 0 && j < n && j != i;
+                if (ok && seg) {
+                    int64_t lo, hi;
+                    sample_of(seg, S, i, &lo, &hi);
+                    if (j < lo || j >= hi) err |= 4, ok = false;
+                } else if (!ok) {
+                    err |= 1;
+                }
+                int32_t slot = -2;
+                if (ok) {
+                    // position of i in j's list, its m ids loaded in batches of 16
+                    const int32_t *lj = idx + (int64_t)j * k + 1;
+                    int sp = -1;
+                    for (int t0 = 0; t0 < m && sp < 0; t0 += 16) {
+                        int32_t v[16];
+#pragma unroll
+                        for (int u = 0; u < 16; ++u) v[u] = t0 + u < m ? lj[t0 + u] : -1;
+#pragma unroll
+                        for (int u = 0; u < 16; ++u)
+                            if (sp < 0 && v[u] == (int32_t)i) sp = t0 + u;
+                    }
+                    const double x = a[e];
+                    double w = x;
+                    if (sp >= 0) {
+                        const double y = a[(int64_t)j * m + sp];
+                        w = __dsub_rn(__dadd_rn(x, y), __dmul_rn(x, y));
+                    }
+                    f = (float)w;
+                    if (sp >= 0)
+                        slot = -1;
+                    else if (f != 0.f)
+                        slot = atomicAdd(&rev_cnt[j], 1);
+                }
+                wf[e] = f;
+                rs[e] = slot;
+            }
+            const uint64_t kept = __ballot(act && f != 0.f);
+            if (mp.R > 1) {
+                const uint64_t row_mask = ((1ull << m) - 1ull) << (r * m);
+                if (act && s == 0) own[i] = __popcll(kept & row_mask);
+            } else {
+                own_acc += __popcll(kept);
             }
         }
-        const double x = a[e];
-        double w = x;
-        if (sp >= 0) {
-            const double y = a[(int64_t)j * m + sp];
-            w = __dsub_rn(__dadd_rn(x, y), __dmul_rn(x, y));
-        }
-        const float f = (float)w;
-        wf[e] = f;
-        mutual[e] = sp >= 0 ? 1 : 0;
-        if (f != 0.f) {
-            ++kept;
-            if (sp < 0) atomicAdd(&rev_cnt[j], 1);
-        }
+        if (mp.R == 1 && lane == 0 && i0 < n) own[i0] = own_acc;
     }
-    own[i] = kept;
+    if (err) atomicOr(&res->error, err);
 }
 
 __device__ __forceinline__ int64_t wave_incl_scan(int64_t v, int lane) {
@@ -252,149 +318,223 @@ __device__ __forceinline__ int64_t wave_incl_scan(int64_t v, int lane) {
     return v;
 }
 
-// Block-local exclusive scan of row lengths (own + reverse) into indptr.
+// Block-local exclusive scans of the row lengths (own + reverse) into indptr
+// and of the reverse counts into rbase; block totals of both into tot.
 __global__ __launch_bounds__(kScanThreads) void k_scan_local(const int32_t *__restrict__ own,
                                                               const int32_t *__restrict__ rev, int64_t n,
                                                               int64_t *__restrict__ indptr,
-                                                              int64_t *__restrict__ block_tot) {
-    __shared__ int64_t wsum[kScanThreads / kWave];
+                                                              int64_t *__restrict__ rbase,
+                                                              int64_t *__restrict__ tot) {
+    __shared__ int64_t wsum[2][kScanThreads / kWave];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)tid * kScanItems;
-    int64_t v[kScanItems];
-    int64_t tsum = 0;
+    int64_t v[kScanItems], q[kScanItems];
+    int64_t tsum = 0, qsum = 0;
 #pragma unroll
     for (int u = 0; u < kScanItems; ++u) {
         const int64_t i = base + u;
-        v[u] = i < n ? (int64_t)own[i] + rev[i] : 0;
+        q[u] = i < n ? (int64_t)rev[i] : 0;
+        v[u] = i < n ? (int64_t)own[i] + q[u] : 0;
         tsum += v[u];
+        qsum += q[u];
     }
     const int64_t incl = wave_incl_scan(tsum, lane);
-    if (lane == kWave - 1) wsum[wave] = incl;
-    __syncthreads();
-    if (wave == 0) {
-        int64_t s = lane < kScanThreads / kWave ? wsum[lane] : 0;
-        s = wave_incl_scan(s, lane);
-        if (lane < kScanThreads / kWave) wsum[lane] = s;
+    const int64_t qincl = wave_incl_scan(qsum, lane);
+    if (lane == kWave - 1) {
+        wsum[0][wave] = incl;
+        wsum[1][wave] = qincl;
     }
     __syncthreads();
-    int64_t run = incl - tsum + (wave > 0 ? wsum[wave - 1] : 0);
+    if (wave < 2) {
+        int64_t s = lane < kScanThreads / kWave ? wsum[wave][lane] : 0;
+        s = wave_incl_scan(s, lane);
+        if (lane < kScanThreads / kWave) wsum[wave][lane] = s;
+    }
+    __syncthreads();
+    int64_t run = incl - tsum + (wave > 0 ? wsum[0][wave - 1] : 0);
+    int64_t qrun = qincl - qsum + (wave > 0 ? wsum[1][wave - 1] : 0);
 #pragma unroll
     for (int u = 0; u < kScanItems; ++u) {
         const int64_t i = base + u;
-        if (i < n) indptr[i] = run;
+        if (i < n) {
+            indptr[i] = run;
+            rbase[i] = qrun;
+        }
         run += v[u];
+        qrun += q[u];
     }
-    if (tid == kScanThreads - 1) block_tot[blockIdx.x] = run;
+    if (tid == kScanThreads - 1) {
+        tot[2 * blockIdx.x] = run;
+        tot[2 * blockIdx.x + 1] = qrun;
+    }
 }
 
-// Exclusive scan of the block totals (one workgroup, chunked); writes nnz.
-__global__ __launch_bounds__(kScanThreads) void k_scan_totals(int64_t *__restrict__ block_tot, int64_t nb,
+// Exclusive scan of the block totals (one workgroup, chunked; pairs); writes nnz.
+__global__ __launch_bounds__(kScanThreads) void k_scan_totals(int64_t *__restrict__ tot, int64_t nb,
                                                                GraphResult *__restrict__ res) {
     __shared__ int64_t wsum[kScanThreads / kWave];
     __shared__ int64_t carry;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-    if (tid == 0) carry = 0;
-    __syncthreads();
-    for (int64_t c0 = 0; c0 < nb; c0 += kScanThreads) {
-        const int64_t i = c0 + tid;
-        const int64_t x = i < nb ? block_tot[i] : 0;
-        const int64_t incl = wave_incl_scan(x, lane);
-        if (lane == kWave - 1) wsum[wave] = incl;
+    for (int part = 0; part < 2; ++part) {
+        if (tid == 0) carry = 0;
         __syncthreads();
-        if (wave == 0) {
-            int64_t s = lane < kScanThreads / kWave ? wsum[lane] : 0;
-            s = wave_incl_scan(s, lane);
-            if (lane < kScanThreads / kWave) wsum[lane] = s;
+        for (int64_t c0 = 0; c0 < nb; c0 += kScanThreads) {
+            const int64_t i = c0 + tid;
+            const int64_t x = i < nb ? tot[2 * i + part] : 0;
+            const int64_t incl = wave_incl_scan(x, lane);
+            if (lane == kWave - 1) wsum[wave] = incl;
+            __syncthreads();
+            if (wave == 0) {
+                int64_t s = lane < kScanThreads / kWave ? wsum[lane] : 0;
+                s = wave_incl_scan(s, lane);
+                if (lane < kScanThreads / kWave) wsum[lane] = s;
+            }
+            __syncthreads();
+            const int64_t excl = incl - x + (wave > 0 ? wsum[wave - 1] : 0) + carry;
+            if (i < nb) tot[2 * i + part] = excl;
+            __syncthreads();
+            if (tid == kScanThreads - 1) carry = excl + x;
+            __syncthreads();
         }
-        __syncthreads();
-        const int64_t excl = incl - x + (wave > 0 ? wsum[wave - 1] : 0) + carry;
-        if (i < nb) block_tot[i] = excl;
-        __syncthreads();
-        if (tid == kScanThreads - 1) carry = excl + x;
+        if (tid == 0 && part == 0) res->nnz = carry;
         __syncthreads();
     }
-    if (tid == 0) res->nnz = carry;
 }
 
-__global__ __launch_bounds__(256) void k_scan_add(int64_t *__restrict__ indptr, int64_t n,
-                                                  const int64_t *__restrict__ block_tot,
+__global__ __launch_bounds__(256) void k_scan_add(int64_t *__restrict__ indptr, int64_t *__restrict__ rbase,
+                                                  int64_t n, const int64_t *__restrict__ tot,
                                                   const GraphResult *__restrict__ res) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) indptr[i] += block_tot[i / kScanTile];
+    if (i < n) {
+        const int64_t b = i / kScanTile;
+        indptr[i] += tot[2 * b];
+        rbase[i] += tot[2 * b + 1];
+    }
     if (i == n) indptr[n] = res->nnz;
 }
 
-__global__ __launch_bounds__(256) void k_union_fill(const int32_t *__restrict__ idx, int64_t n, int k,
-                                                    const float *__restrict__ wf, const uint8_t *__restrict__ mutual,
-                                                    const int32_t *__restrict__ own, const int64_t *__restrict__ indptr,
-                                                    int32_t *__restrict__ cursor, int32_t *__restrict__ tmp_col,
-                                                    float *__restrict__ tmp_val) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int m = k - 1;
-    int64_t p = indptr[i];
-    for (int s = 0; s < m; ++s) {
-        const int64_t e = i * m + s;
-        const float f = wf[e];
-        if (f == 0.f) continue;  // dropped zero, or a rejected edge
-        const int32_t j = idx[i * k + 1 + s];
-        tmp_col[p] = j;
-        tmp_val[p] = f;
-        ++p;
-        if (!mutual[e]) {
-            const int c = atomicAdd(&cursor[j], 1);
-            const int64_t q = indptr[j] + own[j] + c;
-            tmp_col[q] = (int32_t)i;
-            tmp_val[q] = f;
+// Each kept one-way edge i -> j writes (i, w) into its slot of j's reverse entries.
+__global__ __launch_bounds__(kEdgeBlock) void k_rev_fill(const int32_t *__restrict__ idx, int64_t n, int k,
+                                                         const float *__restrict__ wf,
+                                                         const int32_t *__restrict__ rs,
+                                                         const int64_t *__restrict__ rbase,
+                                                         int2 *__restrict__ rev) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const EdgeMap mp(n, k - 1);
+    const int m = mp.m;
+    const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    for (int64_t g = wave0; g < mp.groups; g += waves) {
+        const int64_t i0 = g * mp.R;
+        const int chunks = mp.R > 1 ? 1 : (m + kWave - 1) / kWave;
+        for (int c = 0; c < chunks; ++c) {
+            int r, s;
+            if (mp.R > 1) {
+                r = lane / m;
+                s = lane - r * m;
+            } else {
+                r = 0;
+                s = c * kWave + lane;
+            }
+            const int64_t i = i0 + r;
+            if (!((mp.R > 1 ? r < mp.R : s < m) && i < n)) continue;
+            const int64_t e = i * m + s;
+            const int32_t slot = rs[e];
+            if (slot < 0) continue;
+            const int32_t j = idx[i * k + 1 + s];
+            rev[rbase[j] + slot] = make_int2((int32_t)i, __float_as_int(wf[e]));
         }
     }
 }
 
-// One wave per row: rank every entry by column and scatter into place.
-__global__ __launch_bounds__(256) void k_row_sort(const int64_t *__restrict__ indptr, int64_t n,
-                                                  const int32_t *__restrict__ tmp_col,
-                                                  const float *__restrict__ tmp_val, int32_t *__restrict__ indices,
-                                                  float *__restrict__ data, GraphResult *__restrict__ res) {
+// Entry p of row i's unsorted list: its own slots first (dropped ones as
+// column INT_MAX), then its reverse entries.
+__device__ __forceinline__ void row_entry(const int32_t *__restrict__ idx, const float *__restrict__ wf,
+                                          const int2 *__restrict__ rev, int64_t i, int k, int m, int64_t rb,
+                                          int64_t p, int32_t *col, float *val) {
+    if (p < m) {
+        const float f = wf[i * m + p];
+        *val = f;
+        *col = f != 0.f ? idx[i * k + 1 + p] : INT_MAX;
+    } else {
+        const int2 t = rev[rb + (p - m)];
+        *col = t.x;
+        *val = __int_as_float(t.y);
+    }
+}
+
+// One wave per row: rank every kept entry by column (lane broadcasts) and
+// write it to its sorted position.
+__global__ __launch_bounds__(256) void k_row_sort(const int32_t *__restrict__ idx, const float *__restrict__ wf,
+                                                  const int2 *__restrict__ rev, const int32_t *__restrict__ rev_cnt,
+                                                  const int64_t *__restrict__ rbase,
+                                                  const int64_t *__restrict__ indptr, int64_t n, int k,
+                                                  int32_t *__restrict__ indices, float *__restrict__ data,
+                                                  GraphResult *__restrict__ res) {
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t row = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
-    if (row >= n) return;
-    const int64_t beg = indptr[row];
-    const int64_t len = indptr[row + 1] - beg;
-    for (int64_t e0 = 0; e0 < len; e0 += kWave) {
-        const int64_t e = e0 + lane;
-        const int32_t col = e < len ? tmp_col[beg + e] : INT_MAX;
-        const float val = e < len ? tmp_val[beg + e] : 0.f;
-        int64_t rank = 0;
-        bool dup = false;
-        for (int64_t c0 = 0; c0 < len; c0 += kWave) {
-            const int32_t oc = c0 + lane < len ? tmp_col[beg + c0 + lane] : INT_MAX;
-            const int lim = (int)((len - c0) < kWave ? (len - c0) : kWave);
-            for (int t = 0; t < lim; ++t) {
-                const int32_t x = __shfl(oc, t, kWave);
+    const int m = k - 1;
+    const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    bool dup = false;
+    for (int64_t i = wave0; i < n; i += waves) {
+        const int64_t rb = rbase[i];
+        const int64_t len = (int64_t)m + rev_cnt[i];
+        const int64_t out0 = indptr[i];
+        if (len <= kWave) {
+            int32_t col = INT_MAX;
+            float val = 0.f;
+            if (lane < len) row_entry(idx, wf, rev, i, k, m, rb, lane, &col, &val);
+            int rank = 0;
+            for (int t = 0; t < (int)len; ++t) {
+                const int32_t x = __builtin_amdgcn_readlane(col, t);
                 rank += x < col;
-                dup |= (x == col) && (c0 + t != e);
+                dup |= x == col && t != lane && col != INT_MAX;
+            }
+            if (col != INT_MAX) {
+                indices[out0 + rank] = col;
+                data[out0 + rank] = val;
+            }
+        } else {
+            for (int64_t e0 = 0; e0 < len; e0 += kWave) {
+                const int64_t e = e0 + lane;
+                int32_t col = INT_MAX;
+                float val = 0.f;
+                if (e < len) row_entry(idx, wf, rev, i, k, m, rb, e, &col, &val);
+                int64_t rank = 0;
+                for (int64_t c0 = 0; c0 < len; c0 += kWave) {
+                    int32_t oc = INT_MAX;
+                    float ov;
+                    if (c0 + lane < len) row_entry(idx, wf, rev, i, k, m, rb, c0 + lane, &oc, &ov);
+                    const int lim = (int)((len - c0) < kWave ? (len - c0) : kWave);
+                    for (int t = 0; t < lim; ++t) {
+                        const int32_t x = __builtin_amdgcn_readlane(oc, t);
+                        rank += x < col;
+                        dup |= x == col && c0 + t != e && col != INT_MAX;
+                    }
+                }
+                if (col != INT_MAX) {
+                    indices[out0 + rank] = col;
+                    data[out0 + rank] = val;
+                }
             }
         }
-        if (e < len) {
-            indices[beg + rank] = col;
-            data[beg + rank] = val;
-            if (dup) atomicOr(&res->error, 2);
-        }
     }
+    if (dup) atomicOr(&res->error, 2);
 }
 
 struct GraphWs {
     GraphResult *res;
     double *a;
     float *wf;
-    uint8_t *mutual;
-    int32_t *own, *rev_cnt, *cursor;
-    int64_t *block_tot;
-    int32_t *tmp_col;
-    float *tmp_val;
+    int32_t *rs;
+    int32_t *own, *rev_cnt;
+    int64_t *rbase;
+    int64_t *tot;
+    int64_t *seg;
+    int2 *rev;
 };
 
-size_t carve_graph(int64_t n, int k, void *base, GraphWs *w) {
+size_t carve_graph(int64_t n, int k, int32_t S, void *base, GraphWs *w) {
     Carver cv(base);
     const size_t ne = (size_t)n * (size_t)(k - 1);
     const size_t nb = (size_t)((n + kScanTile - 1) / kScanTile) + 1;
@@ -402,28 +542,31 @@ size_t carve_graph(int64_t n, int k, void *base, GraphWs *w) {
     g.res = cv.take<GraphResult>(1);
     g.a = cv.take<double>(ne ? ne : 1);
     g.wf = cv.take<float>(ne ? ne : 1);
-    g.mutual = cv.take<uint8_t>(ne ? ne : 1);
+    g.rs = cv.take<int32_t>(ne ? ne : 1);
     g.own = cv.take<int32_t>((size_t)n + 1);
     g.rev_cnt = cv.take<int32_t>((size_t)n + 1);
-    g.cursor = cv.take<int32_t>((size_t)n + 1);
-    g.block_tot = cv.take<int64_t>(nb);
-    g.tmp_col = cv.take<int32_t>(2 * ne + 1);
-    g.tmp_val = cv.take<float>(2 * ne + 1);
+    g.rbase = cv.take<int64_t>((size_t)n + 1);
+    g.tot = cv.take<int64_t>(2 * nb);
+    g.seg = S > 0 ? cv.take<int64_t>((size_t)S + 1) : nullptr;
+    g.rev = cv.take<int2>(ne ? ne : 1);
     if (w) *w = g;
     return cv.used;
 }
 
 unsigned grid_for(int64_t n, int per_block) { return (unsigned)((n + per_block - 1) / per_block); }
 
-}  // namespace
+// Blocks of the per-edge and per-row wave loops: enough waves to fill the
+// chip several times over, no more than the work needs.
+unsigned wave_grid(int64_t wave_items) {
+    const int64_t blocks = (wave_items + kEdgeBlock / kWave - 1) / (kEdgeBlock / kWave);
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks, 256 * 64));
+}
 
-size_t graph_workspace_bytes(int64_t n, int k) { return carve_graph(n, k, nullptr, nullptr); }
-
-int graph_run(const int32_t *idx, const float *dist, int64_t n, int k, int64_t *indptr, int32_t *indices,
-              float *data, int64_t cap, int64_t *nnz, double *rho, double *sigma, void *ws, hipStream_t stream) {
-    (void)cap;
+int graph_run_impl(const int32_t *idx, const float *dist, int64_t n, int k, const int64_t *seg_host, int32_t S,
+                   int64_t *indptr, int32_t *indices, float *data, int64_t *nnz, double *rho, double *sigma,
+                   void *ws, hipStream_t stream) {
     GraphWs w;
-    carve_graph(n, k, ws, &w);
+    carve_graph(n, k, S, ws, &w);
     int st;
     const int m = k - 1;
     {
@@ -431,7 +574,12 @@ int graph_run(const int32_t *idx, const float *dist, int64_t n, int k, int64_t *
         hipLaunchKernelGGL(k_init_result, dim3(1), dim3(64), 0, stream, w.res);
         const unsigned g = std::min<unsigned>(grid_for(n + 1, 256), 4096u);
         hipLaunchKernelGGL(k_fill_i32, dim3(g), dim3(256), 0, stream, w.rev_cnt, n + 1, 0);
-        hipLaunchKernelGGL(k_fill_i32, dim3(g), dim3(256), 0, stream, w.cursor, n + 1, 0);
+        if (w.seg) {
+            st = hip_status(hipMemcpyAsync(w.seg, seg_host, sizeof(int64_t) * ((size_t)S + 1), hipMemcpyHostToDevice,
+                                           stream),
+                            "upload sample offsets");
+            if (st != RSC_OK) return st;
+        }
         if ((st = launch_status("graph_init")) != RSC_OK) return st;
     }
     if (m > 0) {
@@ -453,11 +601,13 @@ int graph_run(const int32_t *idx, const float *dist, int64_t n, int k, int64_t *
         if (sigma) hipLaunchKernelGGL(k_fill_f64, dim3(g), dim3(256), 0, stream, sigma, n, 0.0);
         if ((st = launch_status("rho_sigma_fill")) != RSC_OK) return st;
     }
+    const int R = m >= 1 && m <= 32 ? kWave / m : 1;
+    const int64_t groups = (n + R - 1) / R;
     {
         ScopedTimer t("union_count", stream);
         if (m > 0)
-            hipLaunchKernelGGL(k_union_count, dim3(grid_for(n, 256)), dim3(256), 0, stream, idx, w.a, n, k, w.wf,
-                               w.mutual, w.own, w.rev_cnt, w.res);
+            hipLaunchKernelGGL(k_union_probe, dim3(wave_grid(groups)), dim3(kEdgeBlock), 0, stream, idx, w.a, n, k,
+                               w.seg, S, w.wf, w.rs, w.own, w.rev_cnt, w.res);
         else
             hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, 256)), dim3(256), 0, stream, w.own, n, 0);
         if ((st = launch_status("union_count")) != RSC_OK) return st;
@@ -466,23 +616,23 @@ int graph_run(const int32_t *idx, const float *dist, int64_t n, int k, int64_t *
         ScopedTimer t("csr_scan", stream);
         const int64_t nb = (n + kScanTile - 1) / kScanTile;
         hipLaunchKernelGGL(k_scan_local, dim3((unsigned)std::max<int64_t>(nb, 1)), dim3(kScanThreads), 0, stream,
-                           w.own, w.rev_cnt, n, indptr, w.block_tot);
-        hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kScanThreads), 0, stream, w.block_tot,
-                           std::max<int64_t>(nb, 1), w.res);
-        hipLaunchKernelGGL(k_scan_add, dim3(grid_for(n + 1, 256)), dim3(256), 0, stream, indptr, n, w.block_tot,
+                           w.own, w.rev_cnt, n, indptr, w.rbase, w.tot);
+        hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kScanThreads), 0, stream, w.tot, std::max<int64_t>(nb, 1),
+                           w.res);
+        hipLaunchKernelGGL(k_scan_add, dim3(grid_for(n + 1, 256)), dim3(256), 0, stream, indptr, w.rbase, n, w.tot,
                            w.res);
         if ((st = launch_status("csr_scan")) != RSC_OK) return st;
     }
     if (m > 0) {
         ScopedTimer t("union_fill", stream);
-        hipLaunchKernelGGL(k_union_fill, dim3(grid_for(n, 256)), dim3(256), 0, stream, idx, n, k, w.wf, w.mutual,
-                           w.own, indptr, w.cursor, w.tmp_col, w.tmp_val);
+        hipLaunchKernelGGL(k_rev_fill, dim3(wave_grid(groups)), dim3(kEdgeBlock), 0, stream, idx, n, k, w.wf, w.rs,
+                           w.rbase, w.rev);
         if ((st = launch_status("union_fill")) != RSC_OK) return st;
     }
     if (m > 0) {
         ScopedTimer t("row_sort", stream);
-        hipLaunchKernelGGL(k_row_sort, dim3(grid_for(n, 4)), dim3(256), 0, stream, indptr, n, w.tmp_col, w.tmp_val,
-                           indices, data, w.res);
+        hipLaunchKernelGGL(k_row_sort, dim3(wave_grid(n)), dim3(256), 0, stream, idx, w.wf, w.rev, w.rev_cnt,
+                           w.rbase, indptr, n, k, indices, data, w.res);
         if ((st = launch_status("row_sort")) != RSC_OK) return st;
     }
     GraphResult host;
@@ -492,11 +642,26 @@ int graph_run(const int32_t *idx, const float *dist, int64_t n, int k, int64_t *
     if ((st = hip_status(hipStreamSynchronize(stream), "synchronise")) != RSC_OK) return st;
     *nnz = host.nnz;
     if (host.error) {
-        set_error(host.error & 1 ? "kNN lists hold an index out of range or the row itself in columns 1..k-1"
-                                 : "kNN lists repeat a neighbour within a row");
+        set_error(host.error & 1   ? "kNN lists hold an index out of range or the row itself in columns 1..k-1"
+                  : host.error & 4 ? "kNN lists hold an edge to a row of another sample"
+                                   : "kNN lists repeat a neighbour within a row");
         return RSC_ERR_BAD_GRAPH;
     }
     return RSC_OK;
+}
+
+}  // namespace
+
+size_t graph_workspace_bytes(int64_t n, int k, int32_t S) { return carve_graph(n, k, S, nullptr, nullptr); }
+
+int graph_run(const int32_t *idx, const float *dist, int64_t n, int k, int64_t *indptr, int32_t *indices,
+              float *data, int64_t *nnz, double *rho, double *sigma, void *ws, hipStream_t stream) {
+    return graph_run_impl(idx, dist, n, k, nullptr, 0, indptr, indices, data, nnz, rho, sigma, ws, stream);
+}
+
+int graph_run_batched(const int32_t *idx, const float *dist, int64_t n, int k, const int64_t *seg_host, int32_t S,
+                      int64_t *indptr, int32_t *indices, float *data, int64_t *nnz, void *ws, hipStream_t stream) {
+    return graph_run_impl(idx, dist, n, k, seg_host, S, indptr, indices, data, nnz, nullptr, nullptr, ws, stream);
 }
 
 }  // namespace rsc

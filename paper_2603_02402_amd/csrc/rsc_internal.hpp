@@ -233,8 +233,14 @@ int umap_layout(const int64_t *indptr, const int32_t *indices, const float *weig
 
 // ---- graph stages (graph.hip) --------------------------------------------
 
-size_t graph_workspace_bytes(int64_t n, int k);
+// Workspace of a graph build over n rows of k slots; S > 0 adds room for
+// the offsets of S samples (the batched form).
+size_t graph_workspace_bytes(int64_t n, int k, int32_t S = 0);
 int graph_run(const int32_t *idx, const float *dist, int64_t n, int k, int64_t *indptr, int32_t *indices,
-              float *data, int64_t cap, int64_t *nnz, double *rho, double *sigma, void *ws, hipStream_t stream);
+              float *data, int64_t *nnz, double *rho, double *sigma, void *ws, hipStream_t stream);
+// As graph_run, with every edge checked to stay inside its row's sample
+// (seg_host: HOST int64 [S + 1] sample offsets, validated by the caller).
+int graph_run_batched(const int32_t *idx, const float *dist, int64_t n, int k, const int64_t *seg_host, int32_t S,
+                      int64_t *indptr, int32_t *indices, float *data, int64_t *nnz, void *ws, hipStream_t stream);
 
 }  // namespace rsc

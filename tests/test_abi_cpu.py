@@ -65,7 +65,8 @@ def test_workspace_sizes(lib):
     assert lib.rsc_knn_workspace_bytes(n, n, 0, k, None) == 0
     assert lib.rsc_knn_workspace_bytes(5, 5, d, 6, None) == 0
     g = lib.rsc_connectivities_workspace_bytes(n, k)
-    assert g >= n * (k - 1) * (8 + 4 + 1) + 2 * n * (k - 1) * 8
+    # per edge: float64 weight, float32 union weight, int32 slot, 8-byte reverse record
+    assert g >= n * (k - 1) * (8 + 4 + 4 + 8)
     assert lib.rsc_connectivities_workspace_bytes(0, k) == 0
 
 
@@ -138,6 +139,35 @@ def test_connectivities_validation(lib):
     assert call(ws_bytes=100) == -7
     assert call(idx=None) == -1
     assert call(nnz_p=None) == -1
+
+
+def test_connectivities_batched_validation(lib):
+    import numpy as np
+
+    nnz = ctypes.c_int64(0)
+
+    def call(off, k=15, cap=None, ws_bytes=1 << 40, nnz_p=ctypes.byref(nnz)):
+        off = np.ascontiguousarray(np.asarray(off, dtype=np.int64))
+        n = int(off[-1])
+        cap = 2 * n * (k - 1) if cap is None else cap
+        return lib.rsc_connectivities_batched(FAKE, FAKE, off.ctypes.data_as(ctypes.c_void_p), len(off) - 1, k, FAKE,
+                                              FAKE, FAKE, cap, nnz_p, ctypes.c_void_p(0x100000), ws_bytes, None)
+
+    assert call([1, 100]) == -1 and "offsets" in _err(lib)
+    assert call([0, 100, 110]) == -1 and "at least k" in _err(lib)
+    assert call([0, 100], k=0) == -1
+    assert call([0, 400], k=300) == -6
+    assert call([0, 100, 300], cap=2 * 300 * 14 - 1) == -4
+    assert call([0, 100, 300], ws_bytes=100) == -7
+    assert call([0, 100, 300], nnz_p=None) == -1
+    assert lib.rsc_connectivities_batched(FAKE, FAKE, None, 1, 15, FAKE, FAKE, FAKE, 1 << 20, ctypes.byref(nnz),
+                                          FAKE, 1 << 40, None) == -1
+    off = np.array([0, 100, 300], dtype=np.int64)
+    p = off.ctypes.data_as(ctypes.c_void_p)
+    # the batched workspace holds the single-graph one plus the offsets
+    assert lib.rsc_connectivities_batched_workspace_bytes(p, 2, 15) >= lib.rsc_connectivities_workspace_bytes(300, 15)
+    bad = np.array([0, 100, 105], dtype=np.int64)
+    assert lib.rsc_connectivities_batched_workspace_bytes(bad.ctypes.data_as(ctypes.c_void_p), 2, 15) == 0
 
 
 def test_error_is_thread_local_and_cleared(lib):

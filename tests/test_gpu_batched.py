@@ -119,3 +119,83 @@ def test_batched_64_samples_sampled_parity(rsc, oracle_mod):
     idx, dist, stats, _ = run_batched(rsc, X, off, 15)
     log(f"[batched] stats {stats}")
     check_against_oracle(oracle_mod, X, off, idx, dist, 15, rows_per_sample=3)
+
+
+def _oracle_batched_lists(oracle_mod, X, off, k):
+    """Exact per-sample kNN lists from the oracle, in global row ids."""
+    idx = np.empty((X.shape[0], k), dtype=np.int32)
+    dist = np.empty((X.shape[0], k), dtype=np.float32)
+    for s in range(len(off) - 1):
+        a, b = int(off[s]), int(off[s + 1])
+        io, _, do = oracle_mod.knn(X[a:b], k)
+        idx[a:b] = io + a
+        dist[a:b] = do
+    return idx, dist
+
+
+def test_connectivities_batched_per_sample_parity(rsc, oracle_mod):
+    """rsc_connectivities_batched on exact per-sample lists: each diagonal block
+    equals the oracle's connectivities of that sample alone."""
+    import torch
+
+    from tests.parity import compare_csr
+
+    sizes = [15, 16, 64, 300, 1000, 45, 2000]
+    k = 15
+    X, off = small_batch(sizes, seed=29)
+    idx, dist = _oracle_batched_lists(oracle_mod, X, off, k)
+    g = rsc.connectivities_batched(torch.from_numpy(idx).cuda(), torch.from_numpy(dist).cuda(), off)
+    torch.cuda.synchronize()
+    gp, gx, gd = g.indptr.cpu().numpy(), g.indices.cpu().numpy(), g.data.cpu().numpy()
+    log(f"[batched graph] {len(sizes)} samples, nnz={gp[-1]}")
+    for s in range(len(sizes)):
+        a, b = int(off[s]), int(off[s + 1])
+        op, ox, od, _, _ = oracle_mod.connectivities(idx[a:b] - a, dist[a:b])
+        sp = gp[a:b + 1] - gp[a]
+        sx = gx[gp[a]:gp[b]]
+        assert ((sx >= a) & (sx < b)).all(), f"sample {s}: column outside the sample"
+        compare_csr((sp, sx - a, gd[gp[a]:gp[b]]), (op, ox, od))
+    # the same graph as the single-graph call on the whole batch, bit for bit
+    g1 = rsc.connectivities(torch.from_numpy(idx).cuda(), torch.from_numpy(dist).cuda())
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(gp, g1.indptr.cpu().numpy())
+    np.testing.assert_array_equal(gx, g1.indices.cpu().numpy())
+    np.testing.assert_array_equal(gd.view(np.uint32), g1.data.cpu().numpy().view(np.uint32))
+
+
+def test_connectivities_batched_of_the_batched_knn(rsc, oracle_mod):
+    """The batched kNN followed by the batched connectivities (the whole batched
+    step), checked against the graph invariants and the single-graph call."""
+    import torch
+
+    sizes = [300, 1000, 45, 2000, 15]
+    X, off = small_batch(sizes, seed=31)
+    Xt = torch.from_numpy(X).cuda()
+    idx, dist = rsc.knn_batched(Xt, off, 15)
+    g = rsc.connectivities_batched(idx, dist, off)
+    g1 = rsc.connectivities(idx, dist)
+    torch.cuda.synchronize()
+    indptr, indices, data = g.indptr.cpu().numpy(), g.indices.cpu().numpy(), g.data.cpu().numpy()
+    check_graph_properties(indptr, indices, data, X.shape[0], 15, g1.rho.cpu().numpy(), g1.sigma.cpu().numpy(),
+                           dist.cpu().numpy())
+    np.testing.assert_array_equal(indices, g1.indices.cpu().numpy())
+    np.testing.assert_array_equal(data.view(np.uint32), g1.data.cpu().numpy().view(np.uint32))
+
+
+def test_connectivities_batched_rejects_an_edge_across_samples(rsc, oracle_mod):
+    import torch
+
+    from paper_2603_02402_amd import RscError
+
+    sizes = [40, 60, 50]
+    X, off = small_batch(sizes, seed=37)
+    idx, dist = _oracle_batched_lists(oracle_mod, X, off, 5)
+    bad = idx.copy()
+    bad[45, 3] = 5  # row 45 (sample 1) lists row 5 (sample 0); row 5 is not otherwise in its list
+    assert 5 not in idx[45]
+    with pytest.raises(RscError) as e:
+        rsc.connectivities_batched(torch.from_numpy(bad).cuda(), torch.from_numpy(dist).cuda(), off)
+    assert "RSC_ERR_BAD_GRAPH" in str(e.value) and "sample" in str(e.value)
+    # the single-graph call accepts the same lists (the edge is a valid row id)
+    rsc.connectivities(torch.from_numpy(bad).cuda(), torch.from_numpy(dist).cuda())
+    torch.cuda.synchronize()
