@@ -125,7 +125,9 @@ static int64_t local_moving(const lgraph *g, const int64_t *k, int64_t two_m, do
                 if (K[c] == 0) touched[nt++] = c;
                 K[c] += g->w[e];
             }
-            /* zero-weight edges leave K at 0: such a community is no candidate */
+            /* a community reached only through zero-weight edges is still a
+               candidate, with K = 0 (it may enter the list more than once;
+               repeats change nothing) */
             double best_h = gain(K[a], gamma, k[v], tot[a] - k[v], two_m);
             int64_t best = a;
             qsort(touched, (size_t)nt, sizeof(int64_t), cmp_i64);
