@@ -72,6 +72,46 @@ def cpu_baseline(X: np.ndarray, k: int, budget_s: float) -> dict:
                       f"(FP64 brute-force kNN + smooth-kNN on their lists); {secs:.1f} s"}
 
 
+def graph_gbs(kernels: dict, n: int, k: int, nnz: int) -> dict:
+    """Achieved HBM GB/s of the connectivities kernels (HIP-event durations).
+
+    ``stage`` uses the compulsory bytes of the whole graph step: the kNN
+    lists read once (idx int32 + dist float32, n k entries) and the CSR
+    written once (int64 row pointers, int32 column + float32 weight per
+    entry).  Each kernel's ``bytes`` counts every array it reads or writes
+    exactly once by its design (E = n (k - 1) directed edges, of which
+    nnz - E are one-way and 2E - nnz mutual), so ``gbs`` is a lower bound on
+    its bandwidth; the PMC bytes of the same kernels sit in profiles/."""
+    m = k - 1
+    E = n * m
+    one_way = max(nnz - E, 0)
+    mutual = max(2 * E - nnz, 0)
+    nk = n * k
+    design = {
+        "smooth_knn": 4 * nk + 8 * E + 16 * n,                                    # dist in; a, rho, sigma out
+        "union_count": 4 * nk + 8 * E + 8 * mutual + 4 * E + 4 * E + 8 * n,       # idx, a (own + reverse) in; wf, rs, counts out
+        "csr_scan": 8 * n + 16 * n + 8 * (n + 1),                                 # counts in; indptr, reverse bases out
+        "union_fill": 4 * E + 4 * E + 4 * nk + 8 * one_way + 8 * one_way,         # rs, wf, idx, bases in; reverse records out
+        "row_sort": 20 * n + 4 * E + 4 * nk + 8 * one_way + 8 * nnz,              # bases, counts, indptr, wf, idx, records in; CSR out
+    }
+    out = {}
+    total_ms = 0.0
+    for name, b in design.items():
+        ms = kernels.get(name)
+        if not ms:
+            continue
+        total_ms += ms
+        out[name] = {"ms": ms, "bytes": b, "gbs": round(b / (ms / 1e3) / 1e9, 1),
+                     "frac_of_hbm": round(b / (ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4)}
+    compulsory = 8 * nk + 8 * (n + 1) + 8 * nnz
+    for extra in ("graph_init",):
+        total_ms += kernels.get(extra, 0.0)
+    stage = {"ms": round(total_ms, 4), "compulsory_bytes": compulsory,
+             "gbs": round(compulsory / (total_ms / 1e3) / 1e9, 1) if total_ms else None,
+             "frac_of_hbm": round(compulsory / (total_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4) if total_ms else None}
+    return {"stage": stage, "kernels": out}
+
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "screen_fp32_plain_1m_traffic.json")
 # the sources that define the screen kernel (and so its traffic)
 SCREEN_SOURCES = [os.path.join(ROOT, "paper_2603_02402_amd", "csrc", f)
@@ -849,6 +889,8 @@ def main() -> int:
                     "kernel": "k_screen_fp32 (FP32 MFMA 32x32x2 distance screen + per-query top-32 heap)",
                     "work_per_launch": f"2*d*n^2 = {flops:.3e} flop (d={d}, n={n})"}
 
+    graph = graph_gbs(kernels, n, k, int(g.nnz))
+
     forms = None
     if not args.no_forms:
         forms = {"cosine_fp32": cosine_form(args, rsc, Xt, ws, (idx, dist, csr))}
@@ -895,6 +937,7 @@ def main() -> int:
                    "rescanned_rows": stats["rescanned_rows"],
                    "max_err_ratio": round(stats["max_err_ratio"], 4)},
         "kernel_ms": kernels,
+        "graph_gbs": graph,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "forms": forms,

@@ -160,6 +160,16 @@ int rsc_knn_ex(const float *Q, int64_t n_query, const float *R, int64_t n_ref, i
  * memory `out`.  Synchronises `stream`. */
 int rsc_knn_read_stats(const void *workspace, size_t workspace_bytes, rsc_knn_stats *out, void *stream);
 
+/* Rows of the last kNN call on `workspace` whose first certificate failed
+ * (the escalated rows of rsc_knn_stats), in no particular order.  The sizes
+ * and options must be those of that call (square = 1 for rsc_knn /
+ * rsc_knn_opt, 0 for rsc_knn_ex).  rows: HOST int32 [cap]; the first
+ * min(*count, cap) entries are written; *count (HOST) receives the number of
+ * escalated rows.  Synchronises `stream`. */
+int rsc_knn_read_escalated(const void *workspace, size_t workspace_bytes, int64_t n_query, int64_t n_ref, int32_t d,
+                           int32_t k, const rsc_knn_opts *opts, int32_t square, int32_t *rows, int64_t cap,
+                           int64_t *count, void *stream);
+
 /* ---------------------------------------------------------------------- */
 /* Batched exact kNN (many independent samples, one persistent launch)     */
 /* ---------------------------------------------------------------------- */
@@ -597,6 +607,62 @@ size_t rsc_umap_workspace_bytes(int64_t n, int64_t nnz, int32_t dim, int32_t neg
 int rsc_umap_layout(const int64_t *indptr, const int32_t *indices, const float *weights, int64_t n, int64_t nnz,
                     int32_t dim, float *Y, int32_t n_epochs, double a, double b, double gamma, double alpha0,
                     int32_t neg, uint64_t seed, void *workspace, size_t workspace_bytes, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Leiden communities of the graph                                         */
+/* ---------------------------------------------------------------------- */
+/*
+ * Community detection on the neighbourhood graph (the paper clusters cells
+ * by Leiden: Technical architecture; Methods, "Dimensionality reduction and
+ * graph analysis"; it validates the clustering by the agreement of
+ * partitions, Methods, "Numerical validation").  One deterministic reading of
+ * Traag, Waltman and van Eck's algorithm, so that the labels are a function
+ * of the graph alone:
+ *   quality   modularity with resolution gamma; the gain of moving v into c
+ *             is h = K(v, c) - ((gamma k_v) T(c)) / 2m in float64, each
+ *             operation rounded as written (K: weight from v to c's other
+ *             vertices, T: total degree of c without v, 2m: sum of degrees);
+ *   weights   fixed point W = rint(w 2^S), S = 62 - ceil(log2 nnz) - e with
+ *             w_max <= 2^e, so every sum of weights is an exact int64;
+ *   moving    synchronous sweeps from the labels at the sweep start: a
+ *             vertex takes the neighbouring community of largest gain if it
+ *             is strictly above staying (ties: lowest label); odd sweeps
+ *             move only to higher labels, even sweeps only to lower ones;
+ *             two quiet sweeps in a row (or 64 sweeps) end the phase;
+ *   refining  rounds inside each community C from singletons: a singleton
+ *             v with K(v, C - v) >= gamma k_v (Tot(C) - k_v) / 2m may join
+ *             the refined community R of a neighbour in C with a smaller
+ *             label if E(R, C - R) >= gamma Tot(R) (Tot(C) - Tot(R)) / 2m and
+ *             the gain is >= 0 (largest gain, ties: lowest label); a join
+ *             into a singleton that moves in the same round is cancelled; a
+ *             round without joins (or 64 rounds) ends the phase;
+ *   aggregating  refined communities become the next level's vertices
+ *             (numbered by their smallest vertex) with summed weights, each
+ *             starting in the community that holds it, labelled by its
+ *             smallest new id.
+ * Levels end when moving moves nothing (or after 32 levels).
+ *   indptr, indices, weights  DEVICE CSR (int64 [n + 1], int32 [nnz],
+ *            float32 [nnz]) of a symmetric graph with weights >= 0 and
+ *            finite (the rsc_connectivities output; a diagonal entry counts
+ *            once in its vertex's degree); indices and weights may be NULL
+ *            when nnz = 0.  Malformed input (row pointers not from 0 to nnz
+ *            or decreasing, a column outside [0, n), a negative or
+ *            non-finite weight) gives RSC_ERR_INVALID_ARG.
+ *   gamma    resolution, finite and > 0 (1 = plain modularity).
+ *   labels   DEVICE int32 [n]: community of each vertex, numbered from 0 in
+ *            order of first appearance (vertex 0 is in community 0).
+ *   quality  HOST float64 or NULL: modularity of the labels on the input
+ *            graph (from the exact integer sums, communities in label order).
+ *   levels   HOST int32 or NULL: local-moving phases run.
+ *   n_communities  HOST int64 or NULL: number of communities.
+ * Synchronises `stream` (once per sweep, refinement round and level).
+ * Workspace: rsc_leiden_workspace_bytes (about 100 nnz + 100 n bytes; 0 for
+ * unsupported sizes: n outside [1, 2^31 - 2], nnz outside [0, 2^40]).
+ */
+size_t rsc_leiden_workspace_bytes(int64_t n, int64_t nnz);
+int rsc_leiden(const int64_t *indptr, const int32_t *indices, const float *weights, int64_t n, int64_t nnz,
+               double gamma, int32_t *labels, double *quality, int32_t *levels, int64_t *n_communities,
+               void *workspace, size_t workspace_bytes, void *stream);
 
 /* ---------------------------------------------------------------------- */
 /* Kernel timing (off by default)                                          */

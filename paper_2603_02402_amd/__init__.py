@@ -17,6 +17,7 @@ torch's current stream.  Functions mirror the C calls:
 * :mod:`.pca`             -> the sparse PCA that produces the embedding
   (``rsc_pca``, ``rsc_pca_covariance``)
 * :mod:`.umap`            -> the UMAP layout of the graph (``rsc_umap_layout``)
+* :mod:`.leiden`          -> Leiden communities of the graph (``rsc_leiden``)
 """
 
 from __future__ import annotations
@@ -34,7 +35,7 @@ __all__ = [
     "RSC_FP32", "RSC_BF16", "RSC_FP8_E4M3", "RSC_EUCLIDEAN", "RSC_COSINE", "abi_version", "knn_batched", "knn_batched_autotune",
     "knn_batched_workspace_bytes", "connectivities_batched", "Router", "partition_kmeans", "partition_lists", "partition_labels",
     "knn_probed", "knn_routed", "edistance_groups", "edistance_sums", "edistance_pairwise", "edistance_onesided",
-    "pca", "pca_covariance", "umap_layout", "UMAP_A", "UMAP_B",
+    "pca", "pca_covariance", "umap_layout", "UMAP_A", "UMAP_B", "leiden",
 ]
 
 
@@ -144,6 +145,25 @@ def read_knn_stats(workspace: Workspace) -> dict:
     return {"escalated_rows": int(s.escalated_rows), "rescanned_rows": int(s.rescanned_rows),
             "max_err_ratio": float(s.max_err_ratio),
             "max_ref_norm": float(s.max_ref_norm)}
+
+
+def read_knn_escalated(workspace: Workspace, n_query: int, n_ref: int, d: int, k: int, opts=None,
+                       square: bool = True):
+    """Sorted rows whose first certificate failed in the last kNN call on
+    ``workspace`` (``rsc_knn_read_escalated``); sizes and options as in that call."""
+    import numpy as np
+
+    ws = workspace.buf
+    count = ctypes.c_int64(0)
+    o = ctypes.byref(opts) if opts is not None else None
+    lib = load()
+    check(lib.rsc_knn_read_escalated(_ptr(ws), ws.numel(), n_query, n_ref, d, k, o, int(square), None, 0,
+                                     ctypes.byref(count), _stream()))
+    rows = np.zeros(max(int(count.value), 1), dtype=np.int32)
+    check(lib.rsc_knn_read_escalated(_ptr(ws), ws.numel(), n_query, n_ref, d, k, o, int(square),
+                                     rows.ctypes.data_as(ctypes.c_void_p), rows.size, ctypes.byref(count),
+                                     _stream()))
+    return np.sort(rows[: int(count.value)])
 
 
 @dataclass
@@ -296,3 +316,4 @@ from .edistance import (edistance_groups, edistance_onesided, edistance_pairwise
                         edistance_sums)
 from .pca import pca, pca_covariance  # noqa: E402
 from .umap import UMAP_A, UMAP_B, umap_layout  # noqa: E402
+from .leiden import leiden  # noqa: E402

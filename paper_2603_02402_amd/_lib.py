@@ -66,6 +66,7 @@ SIGNATURES = {
     "rsc_knn": (ctypes.c_int, [_P, _I64, _I32, _I32, _P, _P, _P, _SZ, _P]),
     "rsc_knn_opt": (ctypes.c_int, [_P, _I64, _I32, _I32, _P, _P, _P, _P, _SZ, _P]),
     "rsc_knn_ex": (ctypes.c_int, [_P, _I64, _P, _I64, _I32, _I32, _P, _P, _P, _P, _SZ, _P]),
+    "rsc_knn_read_escalated": (ctypes.c_int, [_P, _SZ, _I64, _I64, _I32, _I32, _P, _I32, _P, _I64, _P, _P]),
     "rsc_knn_read_stats": (ctypes.c_int, [_P, _SZ, _P, _P]),
     "rsc_knn_batched_workspace_bytes": (_SZ, [_P, _I32, _I32, _I32]),
     "rsc_knn_batched": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, _P, _P, _P, _SZ, _P]),
@@ -109,6 +110,8 @@ SIGNATURES = {
     "rsc_pca_workspace_bytes": (_SZ, [_I64, _I32, _I32]),
     "rsc_pca_covariance": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _P, _SZ, _P]),
     "rsc_pca": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _I32, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    "rsc_leiden_workspace_bytes": (_SZ, [_I64, _I64]),
+    "rsc_leiden": (ctypes.c_int, [_P, _P, _P, _I64, _I64, ctypes.c_double, _P, _P, _P, _P, _P, _SZ, _P]),
     "rsc_umap_workspace_bytes": (_SZ, [_I64, _I64, _I32, _I32]),
     "rsc_umap_layout": (ctypes.c_int, [_P, _P, _P, _I64, _I64, _I32, _P, _I32, ctypes.c_double, ctypes.c_double,
                                        ctypes.c_double, ctypes.c_double, _I32, _U64, _P, _SZ, _P]),

@@ -42,10 +42,10 @@ COMMON = [
 
 
 # Sources whose arithmetic must round every product and sum on its own: the
-# UMAP layout reproduces a sequential float64 evaluation bit for bit, and the
-# header definitions of the rounded intrinsics would otherwise be contracted
-# into fused multiply-adds after inlining.
-PER_FILE = {"umap.hip": ["-ffp-contract=off"]}
+# UMAP layout and the Leiden gains reproduce a sequential float64 evaluation
+# bit for bit, and the header definitions of the rounded intrinsics would
+# otherwise be contracted into fused multiply-adds after inlining.
+PER_FILE = {"umap.hip": ["-ffp-contract=off"], "leiden.hip": ["-ffp-contract=off"]}
 
 
 def _compile(src: str) -> str:

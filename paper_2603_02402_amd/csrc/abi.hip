@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -180,6 +182,41 @@ int rsc_knn_read_stats(const void *workspace, size_t workspace_bytes, rsc_knn_st
     return RSC_OK;
 }
 
+int rsc_knn_read_escalated(const void *workspace, size_t workspace_bytes, int64_t n_query, int64_t n_ref, int32_t d,
+                           int32_t k, const rsc_knn_opts *opts, int32_t square, int32_t *rows, int64_t cap,
+                           int64_t *count, void *stream) {
+    clear_error();
+    KnnPlan p;
+    int st = knn_plan(n_query, n_ref, d, k, opts, square != 0, &p);
+    if (st != RSC_OK) return st;
+    if (!workspace || !count || (cap > 0 && !rows) || cap < 0) {
+        set_error("need a kNN workspace, a count and a host row array of cap entries");
+        return RSC_ERR_INVALID_ARG;
+    }
+    if (workspace_bytes < knn_workspace(p, nullptr, nullptr)) {
+        set_error("workspace smaller than the plan of these sizes");
+        return RSC_ERR_WORKSPACE;
+    }
+    KnnBuffers b;
+    knn_workspace(p, const_cast<void *>(workspace), &b);
+    KnnCounters c;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((st = hip_status(hipMemcpyAsync(&c, b.counters, sizeof(c), hipMemcpyDeviceToHost, s), "read counters")) !=
+        RSC_OK)
+        return st;
+    if ((st = hip_status(hipStreamSynchronize(s), "synchronise")) != RSC_OK) return st;
+    const int64_t flagged = std::min<int64_t>(c.flagged, p.nq);
+    const int64_t take = std::min<int64_t>(flagged, cap);
+    if (take > 0) {
+        if ((st = hip_status(hipMemcpyAsync(rows, b.flag1, sizeof(int32_t) * (size_t)take, hipMemcpyDeviceToHost, s),
+                             "read escalated rows")) != RSC_OK)
+            return st;
+        if ((st = hip_status(hipStreamSynchronize(s), "synchronise")) != RSC_OK) return st;
+    }
+    *count = flagged;
+    return RSC_OK;
+}
+
 size_t rsc_knn_batched_workspace_bytes(const int64_t *offsets, int32_t S, int32_t d, int32_t k) {
     if (d < 1 || d > 128 || k < 1 || k > 63) return 0;
     return batched_workspace_bytes(offsets, S, d, k);
@@ -308,6 +345,50 @@ int rsc_connectivities_batched(const int32_t *idx, const float *dist, const int6
     if (st != RSC_OK) return st;
     return graph_run_batched(idx, dist, n, k, offsets, S, indptr, indices, data, nnz, workspace,
                              static_cast<hipStream_t>(stream));
+}
+
+size_t rsc_leiden_workspace_bytes(int64_t n, int64_t nnz) {
+    if (n < 1 || n > INT32_MAX - 1 || nnz < 0 || nnz > ((int64_t)1 << 40)) return 0;
+    return leiden_workspace_bytes(n, nnz);
+}
+
+int rsc_leiden(const int64_t *indptr, const int32_t *indices, const float *weights, int64_t n, int64_t nnz,
+               double gamma, int32_t *labels, double *quality, int32_t *levels, int64_t *n_communities,
+               void *workspace, size_t workspace_bytes, void *stream) {
+    clear_error();
+    if (n < 1 || nnz < 0) {
+        set_error("need n >= 1 and nnz >= 0");
+        return RSC_ERR_INVALID_ARG;
+    }
+    if (n > INT32_MAX - 1) {
+        set_error("n above 2^31-2 cannot be indexed by int32");
+        return RSC_ERR_OVERFLOW;
+    }
+    if (nnz > ((int64_t)1 << 40)) {
+        set_error("nnz above 2^40 is not supported");
+        return RSC_ERR_UNSUPPORTED;
+    }
+    if (!(gamma > 0.0) || !std::isfinite(gamma)) {
+        set_error("the resolution gamma must be finite and > 0");
+        return RSC_ERR_INVALID_ARG;
+    }
+    if (!indptr || !labels || (nnz > 0 && (!indices || !weights))) {
+        set_error("null pointer");
+        return RSC_ERR_INVALID_ARG;
+    }
+    if (!aligned(indptr, 8) || !aligned(indices, 4) || !aligned(weights, 4) || !aligned(labels, 4)) {
+        set_error("misaligned array");
+        return RSC_ERR_INVALID_ARG;
+    }
+    const size_t need = leiden_workspace_bytes(n, nnz);
+    if (need == 0) {
+        set_error("leiden: workspace size query failed");
+        return RSC_ERR_HIP;
+    }
+    int st = check_ws(workspace, workspace_bytes, need);
+    if (st != RSC_OK) return st;
+    return leiden_run(indptr, indices, weights, n, nnz, gamma, labels, quality, levels, n_communities, workspace,
+                      static_cast<hipStream_t>(stream));
 }
 
 size_t rsc_partition_kmeans_workspace_bytes(int64_t n, int32_t d, int32_t parts) {

@@ -243,4 +243,11 @@ int graph_run(const int32_t *idx, const float *dist, int64_t n, int k, int64_t *
 int graph_run_batched(const int32_t *idx, const float *dist, int64_t n, int k, const int64_t *seg_host, int32_t S,
                       int64_t *indptr, int32_t *indices, float *data, int64_t *nnz, void *ws, hipStream_t stream);
 
+// ---- Leiden communities (leiden.hip) ----------------------------------------
+
+size_t leiden_workspace_bytes(int64_t n, int64_t nnz);
+int leiden_run(const int64_t *indptr, const int32_t *indices, const float *weights, int64_t n, int64_t nnz,
+               double gamma, int32_t *labels, double *quality, int32_t *levels_out, int64_t *ncomm_out, void *ws,
+               hipStream_t s);
+
 }  // namespace rsc

@@ -141,6 +141,26 @@ def test_connectivities_validation(lib):
     assert call(nnz_p=None) == -1
 
 
+def test_leiden_validation(lib):
+    q = ctypes.c_double(0)
+
+    def call(n=100, nnz=1000, gamma=1.0, ptr=FAKE, idx=FAKE, w=FAKE, lab=FAKE, ws=FAKE, ws_bytes=1 << 30):
+        return lib.rsc_leiden(ptr, idx, w, n, nnz, gamma, lab, ctypes.byref(q), None, None, ws, ws_bytes, None)
+
+    assert call(n=0) == -1
+    assert call(nnz=-1) == -1
+    assert call(n=1 << 31) == -5  # RSC_ERR_OVERFLOW
+    assert call(gamma=0.0) == -1 and "gamma" in _err(lib)
+    assert call(gamma=float("inf")) == -1
+    assert call(gamma=float("nan")) == -1
+    assert call(ptr=None) == -1
+    assert call(idx=None) == -1
+    assert call(lab=None) == -1
+    assert call(w=ctypes.c_void_p(0x10002)) == -1 and "misaligned" in _err(lib)
+    assert lib.rsc_leiden_workspace_bytes(0, 10) == 0
+    assert lib.rsc_leiden_workspace_bytes(10, -1) == 0
+
+
 def test_connectivities_batched_validation(lib):
     import numpy as np
 

@@ -130,8 +130,13 @@ def test_plain_1m_sampled_parity(rsc, oracle_mod):
     torch.cuda.synchronize()
     stats = rsc.read_knn_stats(ws)
     log(f"  stats {stats}")
+    # every row the first certificate failed (escalated to the wider screen)
+    # plus a seeded sample of the others
+    esc = rsc.read_knn_escalated(ws, X.shape[0], X.shape[0], X.shape[1], 15)
+    log(f"  escalated rows read back: {len(esc)}")
+    assert len(esc) == stats["escalated_rows"] > 0
     rows = synth.sample_rows(X.shape[0], 96, seed=123)
-    rows = np.unique(np.concatenate([rows, [0, X.shape[0] - 1]]))
+    rows = np.unique(np.concatenate([rows, [0, X.shape[0] - 1], esc]))
     idx_g = idx[torch.from_numpy(rows).cuda()].cpu().numpy()
     dist_g = dist[torch.from_numpy(rows).cuda()].cpu().numpy()
     log(f"  oracle on {len(rows)} sampled rows")
