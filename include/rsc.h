@@ -243,6 +243,26 @@ int rsc_connectivities(const int32_t *idx, const float *dist, int64_t n, int32_t
                        void *workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * rsc_connectivities for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same computation and output, bitwise, without a
+ * workspace argument.  Its scratch is a fixed device array of
+ * rsc_connectivities_noalloc_max_bytes() bytes (64 MiB) inside the library,
+ * which every GPU the library runs on holds until the process ends; the
+ * call allocates nothing.  A problem whose workspace
+ * (rsc_connectivities_workspace_bytes(n, k)) exceeds it is rejected with
+ * RSC_ERR_CAPACITY before anything is enqueued (at k = 15 about 190,000
+ * rows fit).  Every call on one GPU shares that GPU's array: calls that
+ * overlap in time on one GPU (two streams, two host threads) race and must
+ * be serialised by the caller.  Arguments, output, validation and
+ * synchronisation as for rsc_connectivities.
+ */
+size_t rsc_connectivities_noalloc_max_bytes(void);
+int rsc_connectivities_noalloc(const int32_t *idx, const float *dist, int64_t n, int32_t k, int64_t *indptr,
+                               int32_t *indices, float *data, int64_t cap, int64_t *nnz, double *rho, double *sigma,
+                               void *stream);
+
+/*
  * Connectivities of a batch of samples (the output of rsc_knn_batched):
  * each sample's fuzzy simplicial set on its own rows, the samples' graphs
  * side by side in one block-diagonal CSR with global row ids (the paper

@@ -9,6 +9,7 @@ torch's current stream.  Functions mirror the C calls:
 * :func:`knn_graph`       -> both, the whole neighbourhood-graph step
 * :func:`knn_batched`     -> ``rsc_knn_batched`` (many samples, one launch)
 * :func:`connectivities_batched` -> ``rsc_connectivities_batched``
+* :func:`connectivities_noalloc` -> ``rsc_connectivities_noalloc``
 * :mod:`.routed`          -> partitions, the router network, probed and
   routed kNN (``rsc_partition_*``, ``rsc_router_*``, ``rsc_knn_probed``,
   ``rsc_knn_routed``)
@@ -205,6 +206,24 @@ def connectivities(idx, dist, want_rho_sigma: bool = True, workspace: Workspace 
     check(st)
     m = int(nnz.value)
     return Graph(indptr, indices[:m], data[:m], rho, sigma)
+
+
+def connectivities_noalloc(idx, dist, out, rho=None, sigma=None):
+    """``rsc_connectivities_noalloc``: the same CSR as :func:`connectivities`,
+    written into the caller's ``out = (indptr, indices, data)`` with the
+    library's fixed scratch instead of a workspace; ``rho`` / ``sigma`` are
+    optional float64 outputs.  Returns the nnz."""
+    torch = _torch()
+    _check_dev(idx, dist)
+    if idx.dtype != torch.int32 or dist.dtype != torch.float32 or idx.shape != dist.shape or idx.dim() != 2:
+        raise ValueError("idx (int32) and dist (float32) must be n x k")
+    n, k = idx.shape
+    indptr, indices, data = out
+    nnz = ctypes.c_int64(0)
+    st = load().rsc_connectivities_noalloc(_ptr(idx), _ptr(dist), n, k, _ptr(indptr), _ptr(indices), _ptr(data),
+                                           indices.numel(), ctypes.byref(nnz), _ptr(rho), _ptr(sigma), _stream())
+    check(st)
+    return int(nnz.value)
 
 
 def knn_graph(X, k: int, workspace: Workspace | None = None, metric: int = RSC_EUCLIDEAN):

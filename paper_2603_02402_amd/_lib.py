@@ -74,6 +74,8 @@ SIGNATURES = {
     "rsc_batch_policy_name": (ctypes.c_char_p, [_I32]),
     "rsc_connectivities_workspace_bytes": (_SZ, [_I64, _I32]),
     "rsc_connectivities": (ctypes.c_int, [_P, _P, _I64, _I32, _P, _P, _P, _I64, _P, _P, _P, _P, _SZ, _P]),
+    "rsc_connectivities_noalloc_max_bytes": (_SZ, []),
+    "rsc_connectivities_noalloc": (ctypes.c_int, [_P, _P, _I64, _I32, _P, _P, _P, _I64, _P, _P, _P, _P]),
     "rsc_connectivities_batched_workspace_bytes": (_SZ, [_P, _I32, _I32]),
     "rsc_connectivities_batched": (ctypes.c_int, [_P, _P, _P, _I32, _I32, _P, _P, _P, _I64, _P, _P, _SZ, _P]),
     "rsc_partition_kmeans_workspace_bytes": (_SZ, [_I64, _I32, _I32]),

@@ -310,6 +310,18 @@ int rsc_connectivities(const int32_t *idx, const float *dist, int64_t n, int32_t
                      static_cast<hipStream_t>(stream));
 }
 
+size_t rsc_connectivities_noalloc_max_bytes(void) { return graph_noalloc_max_bytes(); }
+
+int rsc_connectivities_noalloc(const int32_t *idx, const float *dist, int64_t n, int32_t k, int64_t *indptr,
+                               int32_t *indices, float *data, int64_t cap, int64_t *nnz, double *rho, double *sigma,
+                               void *stream) {
+    clear_error();
+    const int st = check_conn_args(idx, dist, n, k, indptr, indices, data, cap, nnz, rho, sigma);
+    if (st != RSC_OK) return st;
+    return graph_run_noalloc(idx, dist, n, k, indptr, indices, data, nnz, rho, sigma,
+                             static_cast<hipStream_t>(stream));
+}
+
 // Sample offsets of the batched calls: S >= 1, offsets[0] = 0, each sample at
 // least k rows, total <= 2^31 - 2.  Returns the total row count or -1.
 static int64_t check_batch_offsets(const int64_t *offsets, int32_t S, int32_t k) {

@@ -40,6 +40,8 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <mutex>
+#include <string>
 
 #include "rsc_internal.hpp"
 
@@ -650,9 +652,63 @@ int graph_run_impl(const int32_t *idx, const float *dist, int64_t n, int k, cons
     return RSC_OK;
 }
 
+// Scratch of the allocation-free entry point: a file-scope device array
+// that every GPU the library runs on holds until the process ends.  Host
+// code never passes the array's name to a kernel (on the host it is only a
+// stand-in for the symbol); it uses the device address looked up once per
+// device below.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array, looked up on the first
+// call made with the device current.
+int scratch_address(void **out) {
+    int dev = -1;
+    int st = hip_status(hipGetDevice(&dev), "current device");
+    if (st != RSC_OK) return st;
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device ordinal beyond the scratch table");
+        return RSC_ERR_UNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        st = hip_status(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "scratch symbol address");
+        if (st != RSC_OK) return st;
+        if (!p) {
+            set_error("scratch symbol address: null");
+            return RSC_ERR_HIP;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return RSC_OK;
+}
+
 }  // namespace
 
 size_t graph_workspace_bytes(int64_t n, int k, int32_t S) { return carve_graph(n, k, S, nullptr, nullptr); }
+
+size_t graph_noalloc_max_bytes() { return kNoAllocScratchBytes; }
+
+int graph_run_noalloc(const int32_t *idx, const float *dist, int64_t n, int k, int64_t *indptr, int32_t *indices,
+                      float *data, int64_t *nnz, double *rho, double *sigma, hipStream_t stream) {
+    const size_t need = graph_workspace_bytes(n, k);
+    if (need > kNoAllocScratchBytes) {
+        set_error("allocation-free connectivities: n = " + std::to_string(n) + ", k = " + std::to_string(k) +
+                  " need " + std::to_string(need) + " bytes of scratch, above the fixed " +
+                  std::to_string(kNoAllocScratchBytes));
+        return RSC_ERR_CAPACITY;
+    }
+    void *ws = nullptr;
+    const int st = scratch_address(&ws);
+    if (st != RSC_OK) return st;
+    return graph_run_impl(idx, dist, n, k, nullptr, 0, indptr, indices, data, nnz, rho, sigma, ws, stream);
+}
 
 int graph_run(const int32_t *idx, const float *dist, int64_t n, int k, int64_t *indptr, int32_t *indices,
               float *data, int64_t *nnz, double *rho, double *sigma, void *ws, hipStream_t stream) {

@@ -242,6 +242,12 @@ int graph_run(const int32_t *idx, const float *dist, int64_t n, int k, int64_t *
 // (seg_host: HOST int64 [S + 1] sample offsets, validated by the caller).
 int graph_run_batched(const int32_t *idx, const float *dist, int64_t n, int k, const int64_t *seg_host, int32_t S,
                       int64_t *indptr, int32_t *indices, float *data, int64_t *nnz, void *ws, hipStream_t stream);
+// As graph_run, with the workspace taken from a fixed device array of
+// graph_noalloc_max_bytes() bytes instead of the caller (RSC_ERR_CAPACITY
+// when the problem needs more).
+size_t graph_noalloc_max_bytes();
+int graph_run_noalloc(const int32_t *idx, const float *dist, int64_t n, int k, int64_t *indptr, int32_t *indices,
+                      float *data, int64_t *nnz, double *rho, double *sigma, hipStream_t stream);
 
 // ---- Leiden communities (leiden.hip) ----------------------------------------
 

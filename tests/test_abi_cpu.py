@@ -141,6 +141,31 @@ def test_connectivities_validation(lib):
     assert call(nnz_p=None) == -1
 
 
+def test_connectivities_noalloc_validation(lib):
+    """The allocation-free call checks its arguments like rsc_connectivities
+    and rejects a problem whose workspace exceeds its fixed scratch before
+    touching the GPU."""
+    cap_bytes = lib.rsc_connectivities_noalloc_max_bytes()
+    assert cap_bytes == 64 << 20
+    k = 15
+    fits = 1000
+    assert lib.rsc_connectivities_workspace_bytes(fits, k) <= cap_bytes
+    big = 300000
+    assert lib.rsc_connectivities_workspace_bytes(big, k) > cap_bytes
+    nnz = ctypes.c_int64(0)
+
+    def call(n, cap, idx=FAKE):
+        return lib.rsc_connectivities_noalloc(idx, FAKE, n, k, FAKE, FAKE, FAKE, cap, ctypes.byref(nnz), None, None,
+                                              None)
+
+    assert call(big, 2 * big * (k - 1)) == -4  # RSC_ERR_CAPACITY: beyond the scratch
+    assert "scratch" in _err(lib)
+    assert call(fits, 2 * fits * (k - 1) - 1) == -4  # CSR capacity too small
+    assert "capacity" in _err(lib)
+    assert call(fits, 2 * fits * (k - 1), idx=None) == -1
+    assert call(0, 1) == -1
+
+
 def test_leiden_validation(lib):
     q = ctypes.c_double(0)
 
