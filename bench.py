@@ -17,6 +17,7 @@ the FP64 CPU oracle on a bounded sample of query rows of the same workload.
 from __future__ import annotations
 
 import argparse
+import math
 import json
 import os
 import sys
@@ -163,6 +164,24 @@ def traffic_probe() -> int:
     return 0
 
 
+def precision_probe() -> int:
+    """Program for the MFMA counter runs of the reduced-precision screens: one
+    BF16 and one FP8-e4m3 kNN call on the 2M-cell precision workload."""
+    import torch
+
+    import paper_2603_02402_amd as rsc
+    import synth
+
+    X = torch.from_numpy(synth.workload("precision_2m")).cuda()
+    ws = rsc.Workspace()
+    for name, prec in (("bf16", rsc.RSC_BF16), ("fp8", rsc.RSC_FP8_E4M3)):
+        print(f"precision probe: {name}", flush=True)
+        rsc.knn(X, 15, workspace=ws, precision=prec)
+        torch.cuda.synchronize()
+    print("precision probe: done", flush=True)
+    return 0
+
+
 def recall_at_k(dist_form, dist_exact, k: int) -> float:
     """Tie-aware recall@k of a form whose returned distances are exact
     (float64 rerank): a returned neighbour is a hit when its distance is
@@ -191,25 +210,32 @@ def weight_error(g_form, g_exact, n: int) -> dict:
             "p99_rel": float(torch.quantile(rel[:1 << 24].float(), 0.99).item()) if rel.numel() else 0.0}
 
 
-def timed_form(rsc, Xt, k, precision, steps, warmup, ws, out):
+def timed_form(rsc, Xt, k, precision, steps, warmup, ws, out, fp8_residual=0, kernels=None):
     import torch
 
     idx, dist, csr = out
     for _ in range(warmup):
-        rsc.knn(Xt, k, precision=precision, out=(idx, dist), workspace=ws)
+        rsc.knn(Xt, k, precision=precision, out=(idx, dist), workspace=ws, fp8_residual=fp8_residual)
         g = rsc.connectivities(idx, dist, workspace=ws, out=csr)
     torch.cuda.synchronize()
     rsc.profile_reset()
     rsc.profile_enable(True)
     t0 = time.perf_counter()
     for _ in range(steps):
-        rsc.knn(Xt, k, precision=precision, out=(idx, dist), workspace=ws)
+        rsc.knn(Xt, k, precision=precision, out=(idx, dist), workspace=ws, fp8_residual=fp8_residual)
         g = rsc.connectivities(idx, dist, workspace=ws, out=csr)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     rsc.profile_enable(False)
     names = {rsc.RSC_FP32: "screen_fp32", rsc.RSC_BF16: "screen_bf16", rsc.RSC_FP8_E4M3: "screen_fp8"}
-    tot, cnt = rsc.profile_get(names[precision])
+    name = "screen_fp8_resid" if fp8_residual else names[precision]
+    tot, cnt = rsc.profile_get(name)
+    if kernels is not None:
+        for kn in ("resid_partition", "prep_pack", name, "rerank", "smooth_knn", "union_count", "union_fill",
+                   "row_sort"):
+            t, c = rsc.profile_get(kn)
+            if c:
+                kernels[kn] = round(t / steps, 3)
     return (t1 - t0) * 1e3 / steps, (tot / cnt if cnt else None), g
 
 
@@ -229,6 +255,7 @@ def precision_forms(args, rsc) -> dict:
     del X
     ws = rsc.Workspace(dev)
     ws.get(max(rsc.knn_workspace_bytes(n, n, d, k), rsc.knn_workspace_bytes(n, n, d, k, precision=rsc.RSC_BF16),
+               rsc.knn_workspace_bytes(n, n, d, k, precision=rsc.RSC_FP8_E4M3, fp8_residual=256),
                rsc.connectivities_workspace_bytes(n, k)))
     cap = 2 * n * (k - 1)
 
@@ -256,6 +283,20 @@ def precision_forms(args, rsc) -> dict:
                      "screen_frac_of_peak": round(2 * d * n * n / (scr / 1e3) / 1e12 / peak, 4),
                      "weight_error_on_common_entries": we,
                      "meets_recall_0.99": rec >= 0.99}
+    # the FP8 residual variant (a separately labelled form): 256 k-means
+    # partitions of the cells, residual coding on both sides; the partitioning
+    # is part of every timed call
+    log("[bench] precision forms: fp8_e4m3_residual_rerank")
+    kern = {}
+    ms, scr, g = timed_form(rsc, Xt, k, rsc.RSC_FP8_E4M3, args.form_steps, 1, ws, fo, fp8_residual=256, kernels=kern)
+    rec = recall_at_k(fo[1], ex[1], k)
+    we = weight_error(g, g_exact, n)
+    res["fp8_e4m3_residual_rerank"] = {
+        "partitions": 256, "cells_per_s": round(n / (ms / 1e3), 1), "ms_per_step": round(ms, 2),
+        "screen_ms": round(scr, 2), "kernel_ms": kern, "recall@15": round(rec, 5),
+        "screen_tflops_algorithmic": round(2 * d * n * n / (scr / 1e3) / 1e12, 2),
+        "screen_frac_of_peak": round(2 * d * n * n / (scr / 1e3) / 1e12 / 5000.0, 4),
+        "weight_error_on_common_entries": we, "meets_recall_0.99": rec >= 0.99}
     return res
 
 
@@ -503,6 +544,76 @@ def umap_samples(w: np.ndarray, n_epochs: int) -> int:
     return int(np.floor((n_epochs - 1) / eps + 1e-9).sum())
 
 
+def leiden_form(args, rsc, csr=None) -> dict:
+    """Leiden communities of the 1M-cell kNN graph (the clustering step the
+    paper runs on this graph), modularity at resolution 1.  ``cpu_baseline``
+    runs the oracle on the graph of a 30,000-cell mixture (the oracle is
+    sequential; the whole 1M graph would take minutes)."""
+    import torch
+
+    import synth
+
+    if csr is None:
+        w = WORKLOADS["plain_1m"]
+        log("[bench] leiden: building the 1M-cell graph")
+        X = torch.from_numpy(synth.mixture(w["n"], d=50, n_clusters=w["clusters"], law=w["law"],
+                                           seed=w["seed"])).cuda()
+        ws0 = rsc.Workspace()
+        idx, dist = rsc.knn(X, args.k, workspace=ws0)
+        g = rsc.connectivities(idx, dist, workspace=ws0)
+        csr = (g.indptr, g.indices, g.data)
+        del X, idx, dist, ws0
+    indptr, indices, data = csr
+    n = indptr.numel() - 1
+    nnz = int(indptr[-1].item())
+    graph = (indptr, indices[:nnz], data[:nnz])
+    ws = rsc.Workspace()
+    log("[bench] leiden: warmup")
+    rsc.leiden(graph, workspace=ws)
+    torch.cuda.synchronize()
+    steps = max(1, args.form_steps)
+    rsc.profile_reset()
+    rsc.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        labels, st = rsc.leiden(graph, workspace=ws)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    rsc.profile_enable(False)
+    kern = {}
+    for name in ["leiden", "leiden_move", "leiden_refine", "leiden_aggregate"]:
+        tot, cnt = rsc.profile_get(name)
+        if cnt:
+            kern[name] = round(tot / steps, 3)
+    move = None
+    if kern.get("leiden_move"):
+        # local moving is bound by HBM and L2 gathers: per sweep, every CSR
+        # entry's column and fixed-point weight (12 B) and its neighbour's
+        # label (4 B); per vertex its row pointer, degree, label in and out
+        # (24 B); the library sums these algorithmic bytes over all sweeps
+        gbs = st["move_bytes"] / (kern["leiden_move"] / 1e3) / 1e9
+        move = {"bound": "hbm", "kernel": "k_lv_move", "unit": "GB/s", "bytes_per_call": st["move_bytes"],
+                "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "frac": round(gbs / PEAK_HBM_GBS, 4)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import leiden as ol
+
+        Xs = synth.mixture(30000, d=50, n_clusters=25, law="zipf", seed=64)
+        _, _, gs = rsc.knn_graph(torch.from_numpy(Xs).cuda(), args.k)
+        p_, x_, d_ = (t.cpu().numpy() for t in (gs.indptr, gs.indices, gs.data))
+        t1 = time.perf_counter()
+        ol.leiden(p_, x_, d_)
+        secs = time.perf_counter() - t1
+        cpu = {"value": round(30000 / secs, 1), "unit": "cells/s", "cores": 1, "kind": "oracle",
+               "sample": f"the kNN graph of a 30,000-cell mixture ({len(x_)} entries), whole ({secs:.2f} s)"}
+    return {"workload": f"fuzzy kNN graph of the 1M-cell plain workload: {n} vertices, {nnz} stored edges; "
+                        "modularity, resolution 1",
+            "ms_per_call": round(ms, 2), "cells_per_s": round(n / (ms / 1e3), 1), "kernel_ms": kern,
+            "levels": st["levels"], "sweeps": st["sweeps"], "refinement_rounds": st["rounds"],
+            "communities": st["n_communities"], "modularity": round(st["quality"], 6),
+            "move_roofline": move, "cpu_baseline": cpu}
+
+
 def umap_form(args, rsc, csr=None) -> dict:
     """UMAP layout of the 1M-cell kNN graph (the embedding step the paper
     runs on this graph): 200 epochs of edge-sampled SGD, 5 negatives per
@@ -636,7 +747,8 @@ def batched_form(args, rsc) -> dict:
             "cells_per_s": round(n / (ms / 1e3), 1), "ms_per_step": round(ms, 2), "screen_ms": round(scr, 2),
             "screen_tflops": round(flops / (scr / 1e3) / 1e12, 2),
             "screen_frac_of_fp32_peak": round(flops / (scr / 1e3) / 1e12 / PEAK_FP32_TFLOPS, 4),
-            "autotune_choice": chosen, "autotune_screen_ms": {kk: round(v, 2) for kk, v in table.items()},
+            "autotune_choice": list(table)[chosen] if 0 <= chosen < len(table) else None,
+            "autotune_screen_ms": {kk: round(v, 2) for kk, v in table.items()},
             "escalated_rows": stats["escalated_rows"], "rescanned_rows": stats["rescanned_rows"], "nnz": int(g.nnz),
             "exact": True}
 
@@ -683,8 +795,17 @@ def routed_form(args, rsc) -> dict:
     labels = rsc.partition_labels(tidx, assign)
     del tidx
     router = rsc.Router(d, 256, P, seed=1)
-    losses = clock("train_s", lambda: router.train(Xt, labels, epochs=args.routed_epochs, batch=4096, lr=1e-3,
-                                                   workspace=ws))
+
+    def train_schedule():
+        # Adam, learning rate decayed per epoch along a half cosine from 1e-3
+        # (one library call per epoch; the optimiser state carries over)
+        out = []
+        for e in range(args.routed_epochs):
+            lr = 1e-3 * 0.5 * (1.0 + math.cos(math.pi * e / args.routed_epochs))
+            out += router.train(Xt, labels, epochs=1, batch=4096, lr=lr, workspace=ws)
+        return out
+
+    losses = clock("train_s", train_schedule)
     del labels, Xt
     torch.cuda.empty_cache()
 
@@ -744,14 +865,52 @@ def routed_form(args, rsc) -> dict:
         return hits / (n * (k - 1))
 
     rec = recall(routed_idx)
-    # the method without the router: nearest centroids, same probe count, no fallback
-    nc_parts, _ = rsc.knn(C, probes, Q=Xb, workspace=ws)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    nc_idx, _, _, st_nc = rsc.knn_probed(Xb, k, off, perm, nc_parts, workspace=rws)
-    torch.cuda.synchronize()
-    ms_nc = (time.perf_counter() - t0) * 1e3
-    rec_nc = recall(nc_idx)
+    low_mass = int(st["low_mass_rows"])
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, (time.perf_counter() - t0) * 1e3
+
+    # the network alone: the same probes, no fallback
+    (ro_idx, _, _, st_ro), ms_ro = timed(lambda: rsc.knn_routed(router, Xb, k, off, perm, probes=probes,
+                                                                mass_threshold=0.0, workspace=rws))
+    rec_ro = recall(ro_idx)
+    del ro_idx
+    # the method without the router: the nearest centroids (IVF probing), no
+    # fallback, at several probe counts; the centroid kNN is part of each step
+    nc_probes = sorted({probes, 48, 64})  # the probed search supports up to 64 probes
+    nc = {}
+    nc_dist = None
+    for pr in nc_probes:
+        def nc_step(pr=pr):
+            parts_, dist_ = rsc.knn(C, pr, Q=Xb, workspace=ws)
+            return parts_, dist_, rsc.knn_probed(Xb, k, off, perm, parts_, workspace=rws)
+        (parts_, dist_, (nc_idx, _, _, st_nc)), ms_nc = timed(nc_step)
+        nc[pr] = {"recall@15": round(recall(nc_idx), 5), "ms_per_step": round(ms_nc, 2),
+                  "cells_per_s": round(n / (ms_nc / 1e3), 1), "mean_probed_rows": round(st_nc["mean_probed_rows"], 1)}
+        if pr == probes:
+            nc_parts = parts_
+        if pr == max(nc_probes):
+            nc_dist = dist_
+        del nc_idx
+    reach = [pr for pr in nc_probes if nc[pr]["recall@15"] >= 0.99]
+    # nearest centroids + exact search for as many rows as the router sent to
+    # exact search, chosen as the rows whose probe boundary is least clear:
+    # smallest gap between the squared distances of the (probes+1)-th and the
+    # probes-th nearest centroid, or between the (probes+1)-th and the nearest
+    gaps = {}
+    for name, (a, b) in {"gap_next": (probes, probes - 1), "gap_first": (probes, 0)}.items():
+        g2 = nc_dist[:, a].double() ** 2 - nc_dist[:, b].double() ** 2
+        mask = torch.zeros(n, dtype=torch.uint8, device=dev)
+        if low_mass:
+            mask[torch.argsort(g2)[:low_mass]] = 1
+        (m_idx, _, _, _), ms_m = timed(lambda: rsc.knn_probed(Xb, k, off, perm, nc_parts, exact_rows=mask,
+                                                              workspace=rws))
+        gaps[name] = {"recall@15": round(recall(m_idx), 5), "knn_ms": round(ms_m, 2), "exact_rows": low_mass}
+        del m_idx, mask
     router.close()
     return {"workload": f"base n={n}, d=50, k=15, 500-cluster Zipf(1.1) mixture (centres seed 5, base seed 50), "
                         f"router trained on {args.routed_train} held-out cells (seed 51)",
@@ -765,8 +924,13 @@ def routed_form(args, rsc) -> dict:
             "parts": P, "probes": probes, "mass_threshold": thr, "stats": st, "nnz": int(g.nnz),
             "index_build_s": build, "kmeans_iters": args.routed_iters, "kmeans_relocated": relocated,
             "train_epochs": args.routed_epochs, "train_loss_per_epoch": [round(v, 4) for v in losses],
-            "nearest_centroid_probing": {"recall@15": round(rec_nc, 5), "knn_ms": round(ms_nc, 2),
-                                         "mean_probed_rows": round(st_nc["mean_probed_rows"], 1)}}
+            "ablation": {
+                "router_plus_fallback": {"recall@15": round(rec, 5), "exact_rows": low_mass,
+                                         "cells_per_s": round(n / (ms / 1e3), 1)},
+                "router_only": {"recall@15": round(rec_ro, 5), "knn_ms": round(ms_ro, 2)},
+                "nearest_centroids": nc,
+                "nearest_centroid_probes_reaching_0.99": min(reach) if reach else None,
+                "nearest_centroids_plus_fallback_same_rows": gaps}}
 
 
 def main() -> int:
@@ -779,23 +943,27 @@ def main() -> int:
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-probe", action="store_true", help="run the PMC calibration program and exit")
+    ap.add_argument("--precision-probe", action="store_true",
+                    help="run one BF16 and one FP8 kNN call on the 2M workload (for counter runs) and exit")
     ap.add_argument("--no-forms", action="store_true", help="skip the 2M-cell precision forms")
     ap.add_argument("--form-steps", type=int, default=3)
     ap.add_argument("--no-routed", action="store_true", help="skip the learned-router form")
     ap.add_argument("--pca-n", type=int, default=1_000_000, help="cells of the sparse-PCA form")
     ap.add_argument("--umap-epochs", type=int, default=200)
-    ap.add_argument("--only", choices=["cosine", "edistance", "large_k", "pca", "precision", "batched", "routed",
+    ap.add_argument("--only", choices=["cosine", "edistance", "large_k", "pca", "precision", "batched", "routed", "leiden",
                                        "umap"],
                     help="run one form alone and print its record (no benchmark line)")
     ap.add_argument("--routed-n", type=int, default=5_000_000)
     ap.add_argument("--routed-train", type=int, default=1_000_000)
     ap.add_argument("--routed-iters", type=int, default=10, help="k-means iterations")
-    ap.add_argument("--routed-epochs", type=int, default=4)
+    ap.add_argument("--routed-epochs", type=int, default=16)
     ap.add_argument("--routed-probes", type=int, default=32)
     ap.add_argument("--routed-threshold", type=float, default=0.9)
     args = ap.parse_args()
     if args.traffic_probe:
         return traffic_probe()
+    if args.precision_probe:
+        return precision_probe()
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported (the kNN graph here runs "
@@ -826,7 +994,8 @@ def main() -> int:
         return 0
     if args.only:
         fn = {"precision": precision_forms, "batched": batched_form, "routed": routed_form,
-              "edistance": edistance_form, "large_k": large_k_form, "pca": pca_form, "umap": umap_form}[args.only]
+              "edistance": edistance_form, "large_k": large_k_form, "pca": pca_form, "umap": umap_form,
+              "leiden": leiden_form}[args.only]
         print(json.dumps({args.only: fn(args, rsc)}), flush=True)
         return 0
 
@@ -900,6 +1069,7 @@ def main() -> int:
         ws.buf = None
         torch.cuda.empty_cache()
         forms["umap_layout"] = umap_form(args, rsc, csr)
+        forms["leiden"] = leiden_form(args, rsc, csr)
         del csr
         ws.buf = None
         torch.cuda.empty_cache()

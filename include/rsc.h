@@ -103,12 +103,23 @@ typedef enum { RSC_EUCLIDEAN = 0, RSC_COSINE = 1 } rsc_metric;
  *              0 = default.
  *   metric     rsc_metric (0 = Euclidean).  The exactness guarantee of
  *              RSC_FP32 holds for both metrics.
+ *   fp8_residual  0: the FP8 screen codes the rows themselves (the
+ *              per-dimension absmax scaling above).  P in [2, 4096] (at most
+ *              the reference count): the residual variant, a separate form --
+ *              the references are split into P k-means partitions (4 Lloyd
+ *              iterations from P evenly spaced rows, exact assignment) and
+ *              each is coded as its residual y - c_p, scaled per dimension
+ *              by the absmax of the residuals; a query is coded against each
+ *              partition it meets as x - c_p, so the screen ranks by
+ *              |x - c_p|^2 + |r~|^2 - 2 (x - c_p)~ . r~.  The partitioning is
+ *              part of the call.  Only with RSC_FP8_E4M3 and the Euclidean
+ *              metric (RSC_ERR_INVALID_ARG otherwise).
  */
 typedef struct {
     int32_t precision;
     int32_t screen;
     int32_t metric;
-    int32_t reserved1;
+    int32_t fp8_residual;
 } rsc_knn_opts;
 
 /* Counters a kNN call leaves in its workspace (read with rsc_knn_read_stats). */
@@ -176,6 +187,9 @@ int rsc_knn_read_escalated(const void *workspace, size_t workspace_bytes, int64_
 
 /* Number of scheduling policies the batched autotuner measures. */
 #define RSC_BATCH_POLICIES 6
+/* Largest number of tile shapes one autotune call measures (the size of its
+ * times_ms array). */
+#define RSC_BATCH_TRIALS 32
 
 /*
  * A batch is S samples stored back to back in one matrix X: sample s is rows
@@ -197,18 +211,32 @@ size_t rsc_knn_batched_workspace_bytes(const int64_t *offsets, int32_t S, int32_
 int rsc_knn_batched(const float *X, const int64_t *offsets, int32_t S, int32_t d, int32_t k, int32_t *out_idx,
                     float *out_dist, void *workspace, size_t workspace_bytes, void *stream);
 
-/* Time every scheduling policy on this batch (screen only, HIP events) and
- * remember the fastest for batches of the same shape (device, d, k and the
- * histogram of log2 sample sizes); with RSC_AUTOTUNE_CACHE=<file> in the
- * environment the choice is also read from / written to that file.
- * chosen (host, may be NULL): the policy index; times_ms (host, may be NULL):
- * RSC_BATCH_POLICIES measured times.  Synchronises `stream`. */
+/* Choose the tile shape and schedule of this batch by timing its screen
+ * (HIP events) and remember the choice for batches of the same shape
+ * (device, d, k and the histogram of log2 sample sizes); with
+ * RSC_AUTOTUNE_CACHE=<file> in the environment the choice is also read from
+ * / written to that file.  Trials, in order: every scheduling policy
+ * (RSC_BATCH_POLICIES: item order and a default rule for cutting large
+ * samples' references into 2 ranges); the best of them with the wider
+ * screen tile (32 instead of 16 keys kept per query and contraction half,
+ * when k <= 16); then, for each log2 sample-size class holding at least 5%
+ * of the work (heaviest first), the tile's depth along the references: the
+ * class's samples cut into 1, 2 or 4 reference ranges, on top of the best so
+ * far.  chosen (host, may be NULL): the index of the chosen trial;
+ * times_ms (host, may be NULL): RSC_BATCH_TRIALS entries, the measured
+ * screen time of each trial (NaN past the last); rsc_batch_trial_name
+ * describes each.  Synchronises `stream`. */
 int rsc_knn_batched_autotune(const float *X, const int64_t *offsets, int32_t S, int32_t d, int32_t k,
                              void *workspace, size_t workspace_bytes, void *stream, int32_t *chosen,
                              float *times_ms);
 
 /* Human-readable description of a policy index ("" if out of range). */
 const char *rsc_batch_policy_name(int32_t policy);
+
+/* Description of trial t of the last rsc_knn_batched_autotune call in this
+ * process ("" if out of range); the chosen trial ends with its shape.  Valid
+ * until the next autotune call. */
+const char *rsc_batch_trial_name(int32_t trial);
 
 /* ---------------------------------------------------------------------- */
 /* Connectivities (fuzzy simplicial set)                                   */
@@ -671,18 +699,30 @@ int rsc_umap_layout(const int64_t *indptr, const int32_t *indices, const float *
  *   gamma    resolution, finite and > 0 (1 = plain modularity).
  *   labels   DEVICE int32 [n]: community of each vertex, numbered from 0 in
  *            order of first appearance (vertex 0 is in community 0).
- *   quality  HOST float64 or NULL: modularity of the labels on the input
- *            graph (from the exact integer sums, communities in label order).
- *   levels   HOST int32 or NULL: local-moving phases run.
- *   n_communities  HOST int64 or NULL: number of communities.
+ *   stats    HOST rsc_leiden_stats or NULL: the modularity of the labels on
+ *            the input graph (from the exact integer sums, communities in
+ *            label order), the community count and the work done.
  * Synchronises `stream` (once per sweep, refinement round and level).
  * Workspace: rsc_leiden_workspace_bytes (about 100 nnz + 100 n bytes; 0 for
  * unsupported sizes: n outside [1, 2^31 - 2], nnz outside [0, 2^40]).
  */
+typedef struct {
+    double quality;        /* modularity of the labels on the input graph */
+    int64_t n_communities; /* number of communities */
+    int32_t levels;        /* local-moving phases run */
+    int32_t sweeps;        /* local-moving sweeps, all levels */
+    int32_t rounds;        /* refinement rounds, all levels */
+    int32_t reserved;
+    int64_t move_bytes;    /* algorithmic bytes of all sweeps: per sweep of a level with
+                              N vertices and M entries, 16 M (column, fixed-point weight,
+                              the neighbour's label) + 24 N (row pointer, degree, label
+                              in and out) */
+} rsc_leiden_stats;
+
 size_t rsc_leiden_workspace_bytes(int64_t n, int64_t nnz);
 int rsc_leiden(const int64_t *indptr, const int32_t *indices, const float *weights, int64_t n, int64_t nnz,
-               double gamma, int32_t *labels, double *quality, int32_t *levels, int64_t *n_communities,
-               void *workspace, size_t workspace_bytes, void *stream);
+               double gamma, int32_t *labels, rsc_leiden_stats *stats, void *workspace, size_t workspace_bytes,
+               void *stream);
 
 /* ---------------------------------------------------------------------- */
 /* Kernel timing (off by default)                                          */

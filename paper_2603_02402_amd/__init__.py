@@ -67,13 +67,13 @@ def abi_version() -> int:
     return int(load().rsc_abi_version())
 
 
-def _opts(precision: int = RSC_FP32, screen: int = 0, metric: int = RSC_EUCLIDEAN):
-    return KnnOpts(precision, screen, metric, 0)
+def _opts(precision: int = RSC_FP32, screen: int = 0, metric: int = RSC_EUCLIDEAN, fp8_residual: int = 0):
+    return KnnOpts(precision, screen, metric, fp8_residual)
 
 
 def knn_workspace_bytes(n_query: int, n_ref: int, d: int, k: int, precision: int = RSC_FP32,
-                        screen: int = 0, metric: int = RSC_EUCLIDEAN) -> int:
-    o = _opts(precision, screen, metric)
+                        screen: int = 0, metric: int = RSC_EUCLIDEAN, fp8_residual: int = 0) -> int:
+    o = _opts(precision, screen, metric, fp8_residual)
     return int(load().rsc_knn_workspace_bytes(n_query, n_ref, d, k, ctypes.byref(o)))
 
 
@@ -97,14 +97,15 @@ class Workspace:
 
 
 def knn(X, k: int, Q=None, precision: int = RSC_FP32, screen: int = 0, out=None, workspace: Workspace | None = None,
-        metric: int = RSC_EUCLIDEAN):
+        metric: int = RSC_EUCLIDEAN, fp8_residual: int = 0):
     """k nearest neighbours.
 
     ``knn(X, k)``: every row of ``X`` (n x d float32) among the rows of ``X``;
     column 0 is the row itself.  ``knn(X, k, Q=Q)``: rows of ``Q`` among
     the rows of ``X`` (all k columns from ``X``).  ``precision`` selects the
     screen (``RSC_FP32`` exact; ``RSC_BF16`` / ``RSC_FP8_E4M3`` approximate,
-    re-ranked in float64).  Returns ``(idx int32, dist float32)``, each
+    re-ranked in float64; ``fp8_residual`` = P selects the FP8 screen's
+    residual variant over P partitions).  Returns ``(idx int32, dist float32)``, each
     ``n_query x k``.
     """
     torch = _torch()
@@ -116,7 +117,7 @@ def knn(X, k: int, Q=None, precision: int = RSC_FP32, screen: int = 0, out=None,
     if Q is not None and (Q.dtype != torch.float32 or Q.dim() != 2 or Q.shape[1] != d):
         raise ValueError("Q must be a float32 tensor with X's column count")
     lib = load()
-    o = _opts(precision, screen, metric)
+    o = _opts(precision, screen, metric, fp8_residual)
     need = lib.rsc_knn_workspace_bytes(nq, n, d, k, ctypes.byref(o))
     if need == 0:
         # invalid sizes: let the call itself report the reason
@@ -127,7 +128,7 @@ def knn(X, k: int, Q=None, precision: int = RSC_FP32, screen: int = 0, out=None,
         dist = torch.empty((nq, k), dtype=torch.float32, device=X.device)
     else:
         idx, dist = out
-    if Q is None and precision == RSC_FP32 and screen == 0 and metric == RSC_EUCLIDEAN:
+    if Q is None and precision == RSC_FP32 and screen == 0 and metric == RSC_EUCLIDEAN and fp8_residual == 0:
         st = lib.rsc_knn(_ptr(X), n, d, k, _ptr(idx), _ptr(dist), _ptr(ws), ws.numel(), _stream())
     elif Q is None:
         st = lib.rsc_knn_opt(_ptr(X), n, d, k, ctypes.byref(o), _ptr(idx), _ptr(dist), _ptr(ws), ws.numel(),
@@ -297,8 +298,8 @@ def connectivities_batched(idx, dist, offsets, workspace: Workspace | None = Non
 
 
 def knn_batched_autotune(X, offsets, k: int, workspace: Workspace | None = None):
-    """Measure the batched scheduling policies on this batch; returns
-    ``(chosen_index, {policy_name: ms})``."""
+    """Choose the batched tile shape and schedule by measurement; returns
+    ``(chosen_trial, {trial_description: ms})`` (see ``rsc_knn_batched_autotune``)."""
     _check_dev(X)
     n, d = X.shape
     off, p = _host_offsets(offsets)
@@ -307,11 +308,16 @@ def knn_batched_autotune(X, offsets, k: int, workspace: Workspace | None = None)
     need = lib.rsc_knn_batched_workspace_bytes(p, S, d, k)
     ws = (workspace or Workspace(X.device)).get(need if need else 256)
     chosen = ctypes.c_int32(-1)
-    times = (ctypes.c_float * _lib.RSC_BATCH_POLICIES)()
+    times = (ctypes.c_float * _lib.RSC_BATCH_TRIALS)()
     check(lib.rsc_knn_batched_autotune(_ptr(X), p, S, d, k, _ptr(ws), ws.numel(), _stream(), ctypes.byref(chosen),
                                        times))
-    names = [lib.rsc_batch_policy_name(i).decode() for i in range(_lib.RSC_BATCH_POLICIES)]
-    return int(chosen.value), dict(zip(names, [float(t) for t in times]))
+    table = {}
+    for i in range(_lib.RSC_BATCH_TRIALS):
+        name = lib.rsc_batch_trial_name(i).decode()
+        if not name:
+            break
+        table[name] = float(times[i])
+    return int(chosen.value), table
 
 
 def profile_enable(on: bool = True) -> None:

@@ -30,6 +30,7 @@ STATUS_NAMES = {
 RSC_FP32, RSC_BF16, RSC_FP8_E4M3 = 0, 1, 2
 RSC_EUCLIDEAN, RSC_COSINE = 0, 1
 RSC_BATCH_POLICIES = 6
+RSC_BATCH_TRIALS = 32
 
 # Every symbol include/rsc.h declares, with (restype, argtypes).
 _P = ctypes.c_void_p
@@ -40,13 +41,19 @@ _SZ = ctypes.c_size_t
 
 class KnnOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("screen", ctypes.c_int32), ("metric", ctypes.c_int32),
-                ("reserved1", ctypes.c_int32)]
+                ("fp8_residual", ctypes.c_int32)]
 
 
 class KnnStats(ctypes.Structure):
     _fields_ = [("escalated_rows", ctypes.c_int64), ("rescanned_rows", ctypes.c_int64),
                 ("max_err_ratio", ctypes.c_float),
                 ("max_ref_norm", ctypes.c_float)]
+
+
+class LeidenStats(ctypes.Structure):
+    _fields_ = [("quality", ctypes.c_double), ("n_communities", ctypes.c_int64), ("levels", ctypes.c_int32),
+                ("sweeps", ctypes.c_int32), ("rounds", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("move_bytes", ctypes.c_int64)]
 
 
 class RoutedStats(ctypes.Structure):
@@ -72,6 +79,7 @@ SIGNATURES = {
     "rsc_knn_batched": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, _P, _P, _P, _SZ, _P]),
     "rsc_knn_batched_autotune": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, _P, _SZ, _P, _P, _P]),
     "rsc_batch_policy_name": (ctypes.c_char_p, [_I32]),
+    "rsc_batch_trial_name": (ctypes.c_char_p, [_I32]),
     "rsc_connectivities_workspace_bytes": (_SZ, [_I64, _I32]),
     "rsc_connectivities": (ctypes.c_int, [_P, _P, _I64, _I32, _P, _P, _P, _I64, _P, _P, _P, _P, _SZ, _P]),
     "rsc_connectivities_noalloc_max_bytes": (_SZ, []),
@@ -113,7 +121,7 @@ SIGNATURES = {
     "rsc_pca_covariance": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _P, _P, _P, _SZ, _P]),
     "rsc_pca": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _I32, _P, _P, _P, _P, _P, _P, _SZ, _P]),
     "rsc_leiden_workspace_bytes": (_SZ, [_I64, _I64]),
-    "rsc_leiden": (ctypes.c_int, [_P, _P, _P, _I64, _I64, ctypes.c_double, _P, _P, _P, _P, _P, _SZ, _P]),
+    "rsc_leiden": (ctypes.c_int, [_P, _P, _P, _I64, _I64, ctypes.c_double, _P, _P, _P, _SZ, _P]),
     "rsc_umap_workspace_bytes": (_SZ, [_I64, _I64, _I32, _I32]),
     "rsc_umap_layout": (ctypes.c_int, [_P, _P, _P, _I64, _I64, _I32, _P, _I32, ctypes.c_double, ctypes.c_double,
                                        ctypes.c_double, ctypes.c_double, _I32, _U64, _P, _SZ, _P]),

@@ -259,6 +259,8 @@ int rsc_knn_batched_autotune(const float *X, const int64_t *offsets, int32_t S, 
 
 const char *rsc_batch_policy_name(int32_t policy) { return batched_policy_name(policy); }
 
+const char *rsc_batch_trial_name(int32_t trial) { return batched_trial_name(trial); }
+
 size_t rsc_connectivities_workspace_bytes(int64_t n, int32_t k) {
     if (n < 1 || k < 1 || k > n || n > INT32_MAX - 1) return 0;
     return graph_workspace_bytes(n, k);
@@ -365,8 +367,8 @@ size_t rsc_leiden_workspace_bytes(int64_t n, int64_t nnz) {
 }
 
 int rsc_leiden(const int64_t *indptr, const int32_t *indices, const float *weights, int64_t n, int64_t nnz,
-               double gamma, int32_t *labels, double *quality, int32_t *levels, int64_t *n_communities,
-               void *workspace, size_t workspace_bytes, void *stream) {
+               double gamma, int32_t *labels, rsc_leiden_stats *stats, void *workspace, size_t workspace_bytes,
+               void *stream) {
     clear_error();
     if (n < 1 || nnz < 0) {
         set_error("need n >= 1 and nnz >= 0");
@@ -399,7 +401,7 @@ int rsc_leiden(const int64_t *indptr, const int32_t *indices, const float *weigh
     }
     int st = check_ws(workspace, workspace_bytes, need);
     if (st != RSC_OK) return st;
-    return leiden_run(indptr, indices, weights, n, nnz, gamma, labels, quality, levels, n_communities, workspace,
+    return leiden_run(indptr, indices, weights, n, nnz, gamma, labels, stats, workspace,
                       static_cast<hipStream_t>(stream));
 }
 

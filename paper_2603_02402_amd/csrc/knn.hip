@@ -750,6 +750,17 @@ int knn_plan(int64_t nq, int64_t nr, int d, int k, const rsc_knn_opts *opts, boo
             return RSC_ERR_INVALID_ARG;
         }
     }
+    const int resid = opts ? opts->fp8_residual : 0;
+    if (resid != 0) {
+        if (precision != RSC_FP8_E4M3 || metric != RSC_EUCLIDEAN) {
+            set_error("fp8_residual needs the FP8-e4m3 screen and the Euclidean metric");
+            return RSC_ERR_INVALID_ARG;
+        }
+        if (resid < 2 || resid > 4096 || resid > nr) {
+            set_error("fp8_residual: the partition count must lie in [2, min(4096, n_ref)]");
+            return RSC_ERR_INVALID_ARG;
+        }
+    }
     const int lowp_ranges = precision == RSC_FP32 ? 1 : screen_w / 64;
     if (precision != RSC_FP32) screen_w = 64;  // per reference range; the ranges multiply it
     plan->nq = nq;
@@ -760,9 +771,10 @@ int knn_plan(int64_t nq, int64_t nr, int d, int k, const rsc_knn_opts *opts, boo
     plan->half = screen_w / 2;
     plan->dh = pick_dh(d);
     plan->self_mode = self_mode;
-    plan->nblk = (nr + 31) / 32;
+    plan->nblk = (nr + 31) / 32 + resid;  // residual variant: each partition's last block padded
     plan->precision = precision;
     plan->metric = metric;
+    plan->resid = resid;
     plan->splits = pick_splits(nq, plan->nblk,
                                precision == RSC_FP32 ? kQueriesPerGroup : lowp_queries_per_group(precision, d));
     if (precision == RSC_FP32) {
@@ -802,6 +814,18 @@ size_t knn_workspace(const KnnPlan &p, void *ws, KnnBuffers *out) {
         b.rn = cv.take<float>((size_t)p.nr * p.d);
         b.qn = p.self_mode ? b.rn : cv.take<float>((size_t)std::max<int64_t>(p.nq, 1) * p.d);
     }
+    if (p.resid > 0) {
+        b.cent = cv.take<float>((size_t)p.resid * p.d);
+        b.assign = cv.take<int32_t>((size_t)p.nr);
+        b.perm = cv.take<int32_t>((size_t)p.nr);
+        b.init = cv.take<int32_t>((size_t)p.resid);
+        b.poff = cv.take<int64_t>((size_t)p.resid + 1);
+        b.pblk = cv.take<int64_t>((size_t)p.resid + 1);
+        b.blk_part = cv.take<int32_t>((size_t)p.nblk * 4);
+        b.map = cv.take<int32_t>((size_t)p.nblk * 32);
+        b.kws_bytes = kmeans_workspace_bytes(p.nr, p.d, p.resid);
+        b.kws = cv.take<char>(b.kws_bytes ? b.kws_bytes : 1);
+    }
     if (out) *out = b;
     return cv.used;
 }
@@ -833,7 +857,11 @@ int knn_run_lowp(const KnnPlan &p, const float *Q, const float *R, int32_t *out_
     const bool cosine = p.metric == RSC_COSINE;
     if (cosine && (st = normalize_inputs(p, Q, R, b, stream)) != RSC_OK) return st;
     const float *Qs = cosine ? b.qn : Q, *Rs = cosine ? b.rn : R;  // what the screen sees
-    if ((st = lowp_prepare(p, Qs, Rs, b.packed, b.norms, b.scal, b.amax, stream)) != RSC_OK) return st;
+    if (p.resid > 0)
+        st = lowp_prepare_resid(p, R, b, stream);
+    else
+        st = lowp_prepare(p, Qs, Rs, b.packed, b.norms, b.scal, b.amax, stream);
+    if (st != RSC_OK) return st;
     if (p.nq == 0) return RSC_OK;
     ScreenArgs sa{};
     sa.Q = Qs;
@@ -841,6 +869,8 @@ int knn_run_lowp(const KnnPlan &p, const float *Q, const float *R, int32_t *out_
     sa.Ap = b.packed;
     sa.Np = b.norms;
     sa.qscale = b.scal;
+    sa.blk_part = b.blk_part;
+    sa.cent = b.cent;
     sa.nblk = p.nblk;
     sa.d = p.d;
     sa.P = p.splits;
@@ -848,6 +878,7 @@ int knn_run_lowp(const KnnPlan &p, const float *Q, const float *R, int32_t *out_
     sa.cand_key = b.cand_key;
     const int qg = lowp_queries_per_group(p.precision, p.d);
     if ((st = lowp_screen(p, sa, (unsigned)((p.nq + qg - 1) / qg), stream)) != RSC_OK) return st;
+    if (p.resid > 0 && (st = lowp_unmap(p, b, stream)) != RSC_OK) return st;
     RerankArgs ra{};
     ra.Q = Q;
     ra.nq = p.nq;

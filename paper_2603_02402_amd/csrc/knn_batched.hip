@@ -13,8 +13,12 @@
 //     FP32 MFMA screen of the exact path on each;
 //   * rerank, certificate and exhaustive fallback are those of the exact
 //     path, the fallback restricted to the row's own sample.
-// The policy (reference ranges per size class, item order) is chosen by a
-// measuring autotuner and cached per batch shape.
+// The tile shape and the schedule are chosen by a measuring autotuner and
+// cached per batch shape: the schedule policy (item order, default split
+// rule), the screen tile's width (16 or 32 keys kept per query and
+// contraction half) and, per log2 sample-size class, the tile's depth along
+// the references (a sample's references cut into 1, 2 or 4 ranges, each a
+// work item of its own).
 
 #include <hip/hip_runtime.h>
 
@@ -84,7 +88,8 @@ __global__ void k_batch_init(int32_t *counter, int32_t *cand_idx, float *cand_ke
 // ---------------------------------------------------------------------------
 // Policies and plans (host).
 // ---------------------------------------------------------------------------
-constexpr int kMaxSplits = 2;
+constexpr int kMaxSplits = 4;  // reference ranges per sample a tile shape may ask for
+constexpr int kBuckets = 40;   // log2 sample-size classes
 
 struct Policy {
     int min_rows_split;  // samples with at least this many rows get 2 reference ranges (0 = never)
@@ -102,6 +107,44 @@ const Policy kPolicies[RSC_BATCH_POLICIES] = {
 };
 constexpr int kDefaultPolicy = 0;
 
+// What the autotuner chooses.
+struct Shape {
+    int policy = kDefaultPolicy;  // schedule policy (item order, default split rule)
+    int half = 0;                 // keys per query and contraction half (16 or 32); 0: from k
+    int8_t split[kBuckets] = {};  // reference ranges per sample by log2 size class; 0: the policy's rule
+};
+
+int size_bucket(int64_t n) {
+    int b = 0;
+    while (b < kBuckets - 1 && ((int64_t)1 << (b + 1)) <= n) ++b;
+    return b;
+}
+
+std::string shape_text(const Shape &sh) {
+    std::string t = "p" + std::to_string(sh.policy) + "h" + std::to_string(sh.half);
+    for (int b = 0; b < kBuckets; ++b)
+        if (sh.split[b]) t += "s" + std::to_string(b) + ":" + std::to_string((int)sh.split[b]);
+    return t;
+}
+
+bool parse_shape(const std::string &t, Shape *out) {
+    Shape sh;
+    int pos = 0, v = 0, nread = 0;
+    if (std::sscanf(t.c_str(), "p%dh%d%n", &sh.policy, &sh.half, &nread) != 2) return false;
+    if (sh.policy < 0 || sh.policy >= RSC_BATCH_POLICIES || (sh.half != 0 && sh.half != 16 && sh.half != 32))
+        return false;
+    pos = nread;
+    int b = 0;
+    while (pos < (int)t.size()) {
+        if (std::sscanf(t.c_str() + pos, "s%d:%d%n", &b, &v, &nread) != 2) return false;
+        if (b < 0 || b >= kBuckets || v < 1 || v > kMaxSplits) return false;
+        sh.split[b] = (int8_t)v;
+        pos += nread;
+    }
+    *out = sh;
+    return true;
+}
+
 struct BatchPlan {
     KnnPlan kp;
     int S = 0;
@@ -111,7 +154,8 @@ struct BatchPlan {
     std::vector<BatchItem> items;
 };
 
-int build_plan(const int64_t *offsets, int S, int d, int k, const Policy &pol, BatchPlan *out) {
+int build_plan(const int64_t *offsets, int S, int d, int k, const Shape &sh, BatchPlan *out) {
+    const Policy &pol = kPolicies[sh.policy];
     BatchPlan bp;
     bp.S = S;
     bp.soff.assign(offsets, offsets + S + 1);
@@ -123,6 +167,10 @@ int build_plan(const int64_t *offsets, int S, int d, int k, const Policy &pol, B
     if (st != RSC_OK) return st;
     bp.kp.nblk = bp.boff[S];
     bp.kp.splits = kMaxSplits;
+    if (sh.half == 32 && bp.kp.half == 16) {  // the wider screen tile
+        bp.kp.half = 32;
+        bp.kp.screen = 64;
+    }
     bp.blk_sample.resize(bp.kp.nblk);
     for (int s = 0; s < S; ++s)
         for (int64_t b = bp.boff[s]; b < bp.boff[s + 1]; ++b) bp.blk_sample[b] = s;
@@ -135,7 +183,9 @@ int build_plan(const int64_t *offsets, int S, int d, int k, const Policy &pol, B
     for (int s : order) {
         const int64_t n = bp.soff[s + 1] - bp.soff[s];
         const int64_t nb = bp.boff[s + 1] - bp.boff[s];
-        const int P = (pol.min_rows_split > 0 && n >= pol.min_rows_split) ? 2 : 1;
+        const int tuned = sh.split[size_bucket(n)];
+        const int P = tuned > 0 ? (int)std::min<int64_t>(tuned, nb)
+                                : ((pol.min_rows_split > 0 && n >= pol.min_rows_split) ? 2 : 1);
         const int64_t per = (nb + P - 1) / P;
         for (int64_t q = 0; q < n; q += QG) {
             for (int p = 0; p < P; ++p) {
@@ -173,10 +223,15 @@ struct BatchBuffers {
 };
 
 // Workspace: the exact path's buffers for the concatenated problem, then the
-// batch tables.  Sized for the worst case over all policies.
+// batch tables.  Sized for the worst case over all tile shapes (the widest
+// screen tile, the most reference ranges).
 size_t batch_workspace(const BatchPlan &bp, void *ws, BatchBuffers *out) {
     BatchBuffers b;
-    const size_t base = knn_workspace(bp.kp, ws, &b.kb);
+    KnnPlan widest = bp.kp;  // any tile shape fits the same carving
+    widest.half = 32;
+    widest.screen = 64;
+    const size_t base = knn_workspace(widest, nullptr, nullptr);
+    knn_workspace(bp.kp, ws, &b.kb);
     Carver cv(ws ? static_cast<char *>(ws) + base : nullptr);
     constexpr int QG = kScreenWaves * 32;
     size_t max_items = 0;
@@ -281,8 +336,9 @@ int screen_only(const BatchPlan &bp, const BatchBuffers &b, const float *X, hipS
 // Policy cache: key = device, d, k and the histogram of log2 sample sizes.
 // ---------------------------------------------------------------------------
 std::mutex g_cache_mu;
-std::map<std::string, int> g_cache;
+std::map<std::string, Shape> g_cache;
 bool g_cache_loaded = false;
+std::vector<std::string> g_trial_names;  // the trials of the last autotune call
 
 std::string batch_key(const int64_t *offsets, int S, int d, int k) {
     int dev = 0, cus = 0;
@@ -310,20 +366,21 @@ void load_cache_file() {
     if (!path) return;
     FILE *f = std::fopen(path, "r");
     if (!f) return;
-    char key[1024];
-    int pol;
-    while (std::fscanf(f, "%1023s %d", key, &pol) == 2)
-        if (pol >= 0 && pol < RSC_BATCH_POLICIES) g_cache[key] = pol;
+    char key[1024], val[1024];
+    while (std::fscanf(f, "%1023s %1023s", key, val) == 2) {
+        Shape sh;
+        if (parse_shape(val, &sh)) g_cache[key] = sh;
+    }
     std::fclose(f);
 }
 
-void store_cache(const std::string &key, int pol) {
-    g_cache[key] = pol;
+void store_cache(const std::string &key, const Shape &sh) {
+    g_cache[key] = sh;
     const char *path = std::getenv("RSC_AUTOTUNE_CACHE");
     if (!path) return;
     FILE *f = std::fopen(path, "w");
     if (!f) return;
-    for (auto &kv : g_cache) std::fprintf(f, "%s %d\n", kv.first.c_str(), kv.second);
+    for (auto &kv : g_cache) std::fprintf(f, "%s %s\n", kv.first.c_str(), shape_text(kv.second).c_str());
     std::fclose(f);
 }
 
@@ -441,7 +498,7 @@ size_t batched_workspace_bytes(const int64_t *offsets, int S, int d, int k) {
     for (int s = 0; s < S; ++s)
         if (offsets[s + 1] - offsets[s] < k) return 0;
     BatchPlan bp;
-    if (build_plan(offsets, S, d, k, kPolicies[kDefaultPolicy], &bp) != RSC_OK) return 0;
+    if (build_plan(offsets, S, d, k, Shape(), &bp) != RSC_OK) return 0;
     return batch_workspace(bp, nullptr, nullptr);
 }
 
@@ -449,15 +506,15 @@ int batched_run(const float *X, const int64_t *offsets, int S, int d, int k, int
                 void *ws, size_t ws_bytes, hipStream_t s) {
     int st = check_batch_args(X, offsets, S, d, k, out_idx, out_dist);
     if (st != RSC_OK) return st;
-    int pol = kDefaultPolicy;
+    Shape sh;
     {
         std::lock_guard<std::mutex> lock(g_cache_mu);
         load_cache_file();
         auto it = g_cache.find(batch_key(offsets, S, d, k));
-        if (it != g_cache.end()) pol = it->second;
+        if (it != g_cache.end()) sh = it->second;
     }
     BatchPlan bp;
-    if ((st = build_plan(offsets, S, d, k, kPolicies[pol], &bp)) != RSC_OK) return st;
+    if ((st = build_plan(offsets, S, d, k, sh, &bp)) != RSC_OK) return st;
     BatchBuffers b;
     const size_t need = batch_workspace(bp, ws, &b);
     if (!ws || need > ws_bytes) {
@@ -496,39 +553,91 @@ int batched_autotune(const float *X, const int64_t *offsets, int S, int d, int k
     int32_t dummy_i = 0;
     int st = check_batch_args(X, offsets, S, d, k, &dummy_i, &dummy_f);
     if (st != RSC_OK) return st;
+    if (times_ms)
+        for (int t = 0; t < RSC_BATCH_TRIALS; ++t) times_ms[t] = NAN;
     hipEvent_t e0, e1;
     if ((st = hip_status(hipEventCreate(&e0), "event")) != RSC_OK) return st;
-    if ((st = hip_status(hipEventCreate(&e1), "event")) != RSC_OK) return st;
-    int best = -1;
-    float best_ms = INFINITY;
+    if ((st = hip_status(hipEventCreate(&e1), "event")) != RSC_OK) {
+        (void)hipEventDestroy(e0);
+        return st;
+    }
+    std::vector<std::string> names;
     bool prepared = false;
-    for (int pol = 0; pol < RSC_BATCH_POLICIES && st == RSC_OK; ++pol) {
+    // Time the screen of one tile shape (a warm run first for the first trial).
+    auto trial = [&](const Shape &sh, const std::string &name, float *ms_out) -> int {
         BatchPlan bp;
-        if ((st = build_plan(offsets, S, d, k, kPolicies[pol], &bp)) != RSC_OK) break;
+        int r = build_plan(offsets, S, d, k, sh, &bp);
+        if (r != RSC_OK) return r;
         BatchBuffers b;
         const size_t need = batch_workspace(bp, ws, &b);
         if (!ws || need > ws_bytes) {
             set_error("workspace too small: need " + std::to_string(need) + " bytes");
-            st = RSC_ERR_WORKSPACE;
-            break;
+            return RSC_ERR_WORKSPACE;
         }
-        if ((st = upload_plan(bp, b, s)) != RSC_OK) break;
+        if ((r = upload_plan(bp, b, s)) != RSC_OK) return r;
         if (!prepared) {
-            // the packed references do not depend on the policy
-            if ((st = knn_prep_fp32(bp.kp, X, b.kb, b.blk_sample, b.boff, b.soff, s)) != RSC_OK) break;
+            // the packed references do not depend on the shape
+            if ((r = knn_prep_fp32(bp.kp, X, b.kb, b.blk_sample, b.boff, b.soff, s)) != RSC_OK) return r;
+            if ((r = screen_only(bp, b, X, s)) != RSC_OK) return r;  // warm
             prepared = true;
         }
-        if ((st = screen_only(bp, b, X, s)) != RSC_OK) break;  // warm
-        if ((st = hip_status(hipEventRecord(e0, s), "event")) != RSC_OK) break;
-        if ((st = screen_only(bp, b, X, s)) != RSC_OK) break;
-        if ((st = hip_status(hipEventRecord(e1, s), "event")) != RSC_OK) break;
-        if ((st = hip_status(hipEventSynchronize(e1), "event")) != RSC_OK) break;
+        if ((r = hip_status(hipEventRecord(e0, s), "event")) != RSC_OK) return r;
+        if ((r = screen_only(bp, b, X, s)) != RSC_OK) return r;
+        if ((r = hip_status(hipEventRecord(e1, s), "event")) != RSC_OK) return r;
+        if ((r = hip_status(hipEventSynchronize(e1), "event")) != RSC_OK) return r;
+        if ((r = hip_status(hipEventElapsedTime(ms_out, e0, e1), "event time")) != RSC_OK) return r;
+        if (times_ms && (int)names.size() < RSC_BATCH_TRIALS) times_ms[names.size()] = *ms_out;
+        names.push_back(name);
+        return RSC_OK;
+    };
+    Shape best;
+    float best_ms = INFINITY;
+    int best_trial = -1;
+    auto consider = [&](const Shape &sh, const std::string &name) -> int {
         float ms = 0.f;
-        if ((st = hip_status(hipEventElapsedTime(&ms, e0, e1), "event time")) != RSC_OK) break;
-        if (times_ms) times_ms[pol] = ms;
-        if (ms < best_ms) {
+        const int r = trial(sh, name, &ms);
+        if (r == RSC_OK && ms < best_ms) {
             best_ms = ms;
-            best = pol;
+            best = sh;
+            best_trial = (int)names.size() - 1;
+        }
+        return r;
+    };
+    // 1. the schedule policies (default tile)
+    for (int pol = 0; pol < RSC_BATCH_POLICIES && st == RSC_OK; ++pol) {
+        Shape sh;
+        sh.policy = pol;
+        st = consider(sh, std::string("policy: ") + kPolicies[pol].name);
+    }
+    // 2. the wider screen tile (32 keys per query and half), when k leaves the choice
+    if (st == RSC_OK && k <= 16) {
+        Shape sh = best;
+        sh.half = 32;
+        st = consider(sh, std::string("tile 32 keys/half, ") + kPolicies[best.policy].name);
+    }
+    // 3. the tile's depth per size class, heaviest classes first
+    if (st == RSC_OK) {
+        double work[kBuckets] = {0.0}, total = 0.0;
+        for (int i = 0; i < S; ++i) {
+            const double n = (double)(offsets[i + 1] - offsets[i]);
+            work[size_bucket(offsets[i + 1] - offsets[i])] += n * n;
+            total += n * n;
+        }
+        std::vector<int> order;
+        for (int b = 0; b < kBuckets; ++b)
+            if (work[b] >= 0.05 * total) order.push_back(b);
+        std::sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+        for (int b : order) {
+            const Shape base = best;
+            for (int sp : {1, 2, 4}) {
+                if (st != RSC_OK) break;
+                Shape sh = base;
+                sh.split[b] = (int8_t)sp;
+                const bool same_as_base = base.split[b] == sp;
+                if (same_as_base) continue;
+                st = consider(sh, "size class 2^" + std::to_string(b) + ": " + std::to_string(sp) +
+                                      " reference range(s) per sample, on top of the best so far");
+            }
         }
     }
     const hipError_t d0 = hipEventDestroy(e0), d1 = hipEventDestroy(e1);
@@ -538,9 +647,18 @@ int batched_autotune(const float *X, const int64_t *offsets, int S, int d, int k
         std::lock_guard<std::mutex> lock(g_cache_mu);
         load_cache_file();
         store_cache(batch_key(offsets, S, d, k), best);
+        g_trial_names = names;
+        if (best_trial >= 0 && best_trial < (int)g_trial_names.size())
+            g_trial_names[best_trial] += " [chosen: " + shape_text(best) + "]";
     }
-    if (chosen) *chosen = best;
+    if (chosen) *chosen = best_trial;
     return RSC_OK;
+}
+
+const char *batched_trial_name(int t) {
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    if (t < 0 || t >= (int)g_trial_names.size()) return "";
+    return g_trial_names[t].c_str();
 }
 
 const char *batched_policy_name(int pol) {

@@ -234,6 +234,176 @@ __global__ __launch_bounds__(256) void k_pack_fp8(const float *__restrict__ R, i
 }
 
 // ---------------------------------------------------------------------------
+// FP8 residual variant.  The references are split into k-means partitions
+// and packed partition by partition (a partition's last block padded, map[]
+// turning a packed row back into a row id); each reference is stored as the
+// e4m3 code of its residual y - c_p, scaled per dimension by the absmax of
+// the residuals.  A query is coded against each partition it meets, as
+// q = x - c_p: the screen recomputes its codes when the wave's block moves
+// to another partition.  With both sides relative to c_p the key is
+// G (|q|^2 + |r~|^2 - 2 q~ . r~) = G |x - y~|^2: |r~|^2 (the dequantised
+// residual's norm) is packed with the codes and |q|^2 is added per lane.
+// ---------------------------------------------------------------------------
+__global__ void k_resid_init_rows(int32_t *__restrict__ init, int P, int64_t n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < P; i += gridDim.x * blockDim.x)
+        init[i] = (int32_t)(((int64_t)i * n) / P);
+}
+
+// Block offsets of the partitions (each padded to whole blocks) and the
+// partition of every packed block (blocks past the last partition: P - 1),
+// stored four times per block so that one 16-byte load brings it into LDS.
+__global__ __launch_bounds__(1024) void k_resid_blocks(const int64_t *__restrict__ poff, int P, int64_t nblk,
+                                                       int64_t *__restrict__ pblk, int32_t *__restrict__ blk_part) {
+    if (threadIdx.x == 0) {
+        int64_t b = 0;
+        for (int p = 0; p < P; ++p) {
+            pblk[p] = b;
+            b += (poff[p + 1] - poff[p] + 31) / 32;
+        }
+        pblk[P] = b;
+    }
+    __syncthreads();
+    for (int64_t blk = threadIdx.x; blk < nblk; blk += blockDim.x) {
+        int lo = 0, hi = P - 1;  // last partition p with pblk[p] <= blk
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (pblk[mid] <= blk)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) blk_part[4 * blk + j] = lo;
+    }
+}
+
+// map[packed slot] = row for every row (the map is -1 filled before).
+__global__ __launch_bounds__(256) void k_resid_map(const int64_t *__restrict__ poff, const int32_t *__restrict__ perm,
+                                                   int64_t n, int P, const int64_t *__restrict__ pblk,
+                                                   int64_t map_cap, int32_t *__restrict__ map) {
+    for (int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pos < n;
+         pos += (int64_t)gridDim.x * blockDim.x) {
+        int lo = 0, hi = P - 1;  // partition with poff[p] <= pos < poff[p+1]
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (poff[mid] <= pos)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const int64_t slot = pblk[lo] * 32 + (pos - poff[lo]);
+        if (slot >= 0 && slot < map_cap) map[slot] = perm[pos];
+    }
+}
+
+// Per-dimension max |y - c_assign(y)| over the references (float bits).
+__global__ __launch_bounds__(256) void k_resid_absmax(const float *__restrict__ R, int64_t n, int d,
+                                                      const float *__restrict__ C,
+                                                      const int32_t *__restrict__ assign,
+                                                      uint32_t *__restrict__ amax_bits) {
+    __shared__ uint32_t local[128];
+    for (int t = threadIdx.x; t < d; t += blockDim.x) local[t] = 0u;
+    __syncthreads();
+    const int64_t total = n * d;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t row = e / d;
+        const int t = (int)(e - row * d);
+        const float r = R[e] - C[(int64_t)assign[row] * d + t];
+        atomicMax(&local[t], __float_as_uint(fabsf(r)));
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < d; t += blockDim.x) atomicMax(&amax_bits[t], local[t]);
+}
+
+// scal[0..d): residual scale s_t = absmax_t / 448 (1 for an all-zero
+// dimension); scal[d..2d): query multiplier -2 G s_t; scal[2d]: G, the power
+// of two that puts a query residual of the references' absmax at a quarter
+// to a half of the e4m3 range (a query near the partition fits without
+// saturating).
+__global__ void k_fp8_resid_scales(const uint32_t *__restrict__ amax, int d, float *__restrict__ scal) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    float m = 0.f;
+    for (int t = 0; t < d; ++t) {
+        const float a = __uint_as_float(amax[t]);
+        const float s = a > 0.f ? a / kFp8Max : 1.f;
+        scal[t] = s;
+        m = fmaxf(m, 2.f * a * s);
+    }
+    float G = 1.f;
+    if (m > 0.f) G = ldexpf(1.f, (int)floorf(log2f(kFp8Max / m)) - 1);
+    for (int t = 0; t < d; ++t) scal[d + t] = -2.f * G * scal[t];
+    scal[2 * d] = G;
+}
+
+// As k_pack_fp8, for packed slot (b, row lane) holding map[32 b + lane % 32]
+// and its residual against the block's partition centroid.
+__global__ __launch_bounds__(256) void k_pack_fp8_resid(const float *__restrict__ R, int d, int KS, int64_t nblk,
+                                                        const float *__restrict__ scal,
+                                                        const int32_t *__restrict__ map,
+                                                        const int32_t *__restrict__ blk_part,
+                                                        const float *__restrict__ C, i32x4 *__restrict__ Ap,
+                                                        float *__restrict__ Np) {
+    const int64_t total = nblk * KS * kWave;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int lane = (int)(e % kWave);
+        const int64_t bs = e / kWave;
+        const int s = (int)(bs % KS);
+        const int64_t b = bs / KS;
+        const int32_t row = map[32 * b + (lane & 31)];
+        const float *c = C + (int64_t)blk_part[4 * b] * d;
+        const int h = lane >> 5;
+        const int k0 = 64 * s + 32 * h;
+        i32x8 w;
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            uint32_t four = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int kk = k0 + 4 * p + q;
+                uint32_t code = 0;
+                if (kk < d && row >= 0) code = e4m3_code((R[(int64_t)row * d + kk] - c[kk]) / scal[kk]);
+                four |= code << (8 * q);
+            }
+            w[p] = (int)four;
+        }
+        Ap[2 * bs * kWave + lane] = i32x4{w[0], w[1], w[2], w[3]};
+        Ap[2 * bs * kWave + kWave + lane] = i32x4{w[4], w[5], w[6], w[7]};
+        if (s == 0 && h == 0) {
+            float out = INFINITY;
+            if (row >= 0) {
+                double nr2 = 0.0;
+                for (int t = 0; t < d; ++t) {
+                    const double v =
+                        (double)e4m3_value(e4m3_code((R[(int64_t)row * d + t] - c[t]) / scal[t])) * scal[t];
+                    nr2 += v * v;
+                }
+                out = (float)(nr2 * scal[2 * d]);
+            }
+            const int i = lane & 31;
+            const int g = i >> 3, hh = (i >> 2) & 1, j = i & 3;
+            Np[b * 32 + hh * 16 + 4 * g + j] = out;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_resid_fill_i32(int32_t *__restrict__ a, int64_t n, int32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = v;
+}
+
+// Candidate lists hold packed rows: turn them into row ids (-1 stays).
+__global__ __launch_bounds__(256) void k_resid_unmap(int32_t *__restrict__ cand, int64_t count,
+                                                     const int32_t *__restrict__ map) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = cand[i];
+        if (v >= 0) cand[i] = map[v];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Screen.  Lane l handles query c = l % 32 of each of its QB query blocks
 // and contraction half h = l / 32; output register v of a 32x32 block holds
 // reference row 8(v/4) + 4h + (v%4).
@@ -261,11 +431,12 @@ struct LowpOp<RSC_FP8_E4M3> {
 // double-buffered LDS ring of PH blocks per phase, filled by asynchronous
 // global->LDS loads (each wave issues a quarter of them) one phase ahead;
 // one barrier per phase.
-template <int PREC, int KS>
+template <int PREC, int KS, bool RESID = false>
 struct LowpRing {
     static constexpr int kBlockBytes = KS * kWave * (PREC == RSC_BF16 ? 16 : 32);
     static constexpr int kNormBytes = PREC == RSC_FP8_E4M3 ? 128 : 0;
-    static constexpr int kSlotBytes = kBlockBytes + kNormBytes;
+    static constexpr int kPartBytes = RESID ? 16 : 0;  // the block's partition (residual variant)
+    static constexpr int kSlotBytes = kBlockBytes + kNormBytes + kPartBytes;
     static constexpr int kLoads = kBlockBytes / 1024;  // 1 KiB wave loads per block
     static constexpr int kPhase = PREC == RSC_BF16 ? 4 : 8;  // blocks per phase
 };
@@ -274,11 +445,11 @@ __device__ __forceinline__ void lds_load16(const void *gsrc, void *lds_base) {
     __builtin_amdgcn_global_load_lds(gsrc, (void __attribute__((address_space(3))) *)lds_base, 16, 0, 0);
 }
 
-template <int PREC, int KS, int L, int QB>
+template <int PREC, int KS, int L, int QB, bool RESID = false>
 __global__ __launch_bounds__(256, 3) void k_screen_lowp(ScreenArgs a) {
     using Op = LowpOp<PREC>;
     using T = typename Op::T;
-    using Ring = LowpRing<PREC, KS>;
+    using Ring = LowpRing<PREC, KS, RESID>;
     constexpr int QW = QB * 32;
     constexpr int QG = kScreenWaves * QW;
     constexpr int PH = Ring::kPhase;
@@ -317,19 +488,34 @@ __global__ __launch_bounds__(256, 3) void k_screen_lowp(ScreenArgs a) {
 #pragma unroll
             for (int pb = wave; pb < PH; pb += kScreenWaves) {
                 const int64_t blk = std::min<int64_t>(b0 + pb, blk1 - 1);
-                if (lane < 8) lds_load16(a.Np + blk * 32 + lane * 4, buf + pb * SLOT + Ring::kBlockBytes);
+                // lanes 0..7: the 32 norms; lane 8 (residual variant): the
+                // block's partition, landing right after them
+                if constexpr (RESID) {
+                    if (lane < 9)
+                        lds_load16(lane < 8 ? (const void *)(a.Np + blk * 32 + lane * 4)
+                                            : (const void *)(a.blk_part + blk * 4),
+                                   buf + pb * SLOT + Ring::kBlockBytes);
+                } else {
+                    if (lane < 8) lds_load16(a.Np + blk * 32 + lane * 4, buf + pb * SLOT + Ring::kBlockBytes);
+                }
             }
         }
     };
 
     for (int64_t qblk = blockIdx.x; qblk * QG < nslots; qblk += gridDim.x) {
         int64_t slot[QB];
+        int64_t qrow[QB];
         T bq[QB][KS];
+        float tq[QB];  // residual variant: G |x - c_p|^2 of the current partition
+        int cur_part = -1;
 #pragma unroll
         for (int qb = 0; qb < QB; ++qb) {
             slot[qb] = qblk * QG + wave * QW + qb * 32 + c;
             int64_t row = -1;
             if (slot[qb] < nslots) row = a.qlist ? (int64_t)a.qlist[slot[qb]] : slot[qb];
+            qrow[qb] = row;
+            tq[qb] = 0.f;
+            if constexpr (RESID) continue;  // coded per partition, at its first block
             const float *x = a.Q + (row >= 0 ? row : 0) * a.d;
 #pragma unroll
             for (int s = 0; s < KS; ++s) {
@@ -369,6 +555,41 @@ __global__ __launch_bounds__(256, 3) void k_screen_lowp(ScreenArgs a) {
 #pragma unroll
         for (int qb = 0; qb < QB; ++qb) top[qb].init();
 
+        // Residual variant: the query codes of q = x - c_p (wave-uniform call).
+        auto code_partition = [&](int part) {
+            const float *cp = a.cent + (int64_t)part * a.d;
+            const float G = a.qscale[2 * a.d];
+#pragma unroll
+            for (int qb = 0; qb < QB; ++qb) {
+                const int64_t row = qrow[qb];
+                const float *x = a.Q + (row >= 0 ? row : 0) * a.d;
+                float ss = 0.f;
+#pragma unroll
+                for (int s = 0; s < KS; ++s) {
+                    T v;
+#pragma unroll
+                    for (int w = 0; w < 8; ++w) {
+                        uint32_t four = 0;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int kk = 64 * s + 32 * h + 4 * w + q;
+                            uint32_t code = 0;
+                            if (row >= 0 && kk < a.d) {
+                                const float qv = x[kk] - cp[kk];
+                                ss += qv * qv;
+                                code = e4m3_code(qv * a.qscale[a.d + kk]);
+                            }
+                            four |= code << (8 * q);
+                        }
+                        v[w] = (int)four;
+                    }
+                    bq[qb][s] = v;
+                }
+                ss += __shfl_xor(ss, 32, kWave);  // the other contraction half's dimensions
+                tq[qb] = G * ss;
+            }
+        };
+
         const int64_t nph = (blk1 - blk0 + PH - 1) / PH;
         // One phase: wait until its blocks have landed in `cur`, start the
         // next phase's loads into `nxt`, then screen the blocks of `cur`.
@@ -381,6 +602,13 @@ __global__ __launch_bounds__(256, 3) void k_screen_lowp(ScreenArgs a) {
                 const int64_t blk = blk0 + ph * PH + r;
                 if (blk >= blk1) break;
                 const char *sl = cur + r * SLOT;
+                if constexpr (RESID) {
+                    const int part = *reinterpret_cast<const int *>(sl + Ring::kBlockBytes + Ring::kNormBytes);
+                    if (part != cur_part) {
+                        code_partition(part);
+                        cur_part = part;
+                    }
+                }
                 T A[KS];
 #pragma unroll
                 for (int s = 0; s < KS; ++s) {
@@ -406,7 +634,13 @@ __global__ __launch_bounds__(256, 3) void k_screen_lowp(ScreenArgs a) {
                 __builtin_amdgcn_sched_barrier(0);
                 f32x16 acc[QB];
 #pragma unroll
-                for (int qb = 0; qb < QB; ++qb) acc[qb] = init;
+                for (int qb = 0; qb < QB; ++qb) {
+                    acc[qb] = init;
+                    if constexpr (RESID) {
+#pragma unroll
+                        for (int v = 0; v < 16; ++v) acc[qb][v] += tq[qb];
+                    }
+                }
 #pragma unroll
                 for (int s = 0; s < KS; ++s) {
 #pragma unroll
@@ -431,10 +665,10 @@ __global__ __launch_bounds__(256, 3) void k_screen_lowp(ScreenArgs a) {
     }
 }
 
-template <int PREC, int KS, int L, int QB>
+template <int PREC, int KS, int L, int QB, bool RESID = false>
 int launch_lowp(const ScreenArgs &a, unsigned gx, const char *name, hipStream_t stream) {
     ScopedTimer timer(name, stream);
-    hipLaunchKernelGGL((k_screen_lowp<PREC, KS, L, QB>), dim3(gx, (unsigned)a.P), dim3(256), 0, stream, a);
+    hipLaunchKernelGGL((k_screen_lowp<PREC, KS, L, QB, RESID>), dim3(gx, (unsigned)a.P), dim3(256), 0, stream, a);
     return launch_status(name);
 }
 
@@ -486,6 +720,44 @@ int lowp_prepare(const KnnPlan &p, const float *Q, const float *R, void *packed,
     return launch_status("pack_fp8");
 }
 
+int lowp_prepare_resid(const KnnPlan &p, const float *R, const KnnBuffers &b, hipStream_t stream) {
+    constexpr int kIters = 4;  // Lloyd iterations of the partitioning
+    int st;
+    {
+        ScopedTimer timer("resid_partition", stream);
+        hipLaunchKernelGGL(k_resid_init_rows, dim3(1), dim3(256), 0, stream, b.init, p.resid, p.nr);
+        if ((st = launch_status("resid_init_rows")) != RSC_OK) return st;
+        int64_t relocated = 0;
+        if ((st = kmeans_run(R, p.nr, p.d, p.resid, b.init, kIters, b.cent, b.assign, b.poff, b.perm, &relocated,
+                             b.kws, b.kws_bytes, stream)) != RSC_OK)
+            return st;
+    }
+    const int ks = lowp_steps(p.precision, p.d);
+    const int64_t tot = p.nblk * ks * kWave;
+    const unsigned g1 = (unsigned)std::min<int64_t>((tot + 255) / 256, 65536);
+    ScopedTimer timer("prep_pack", stream);
+    hipLaunchKernelGGL(k_resid_blocks, dim3(1), dim3(1024), 0, stream, b.poff, p.resid, p.nblk, b.pblk, b.blk_part);
+    hipLaunchKernelGGL(k_resid_fill_i32, dim3((unsigned)std::min<int64_t>((p.nblk * 32 + 255) / 256, 65536)),
+                       dim3(256), 0, stream, b.map, p.nblk * 32, -1);
+    const unsigned gm = (unsigned)std::min<int64_t>((p.nr + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_resid_map, dim3(gm), dim3(256), 0, stream, b.poff, b.perm, p.nr, p.resid, b.pblk,
+                       p.nblk * 32, b.map);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, stream, b.amax, 256, 0u);
+    const unsigned ga = (unsigned)std::min<int64_t>((p.nr * p.d + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_resid_absmax, dim3(ga), dim3(256), 0, stream, R, p.nr, p.d, b.cent, b.assign, b.amax);
+    hipLaunchKernelGGL(k_fp8_resid_scales, dim3(1), dim3(64), 0, stream, b.amax, p.d, b.scal);
+    hipLaunchKernelGGL(k_pack_fp8_resid, dim3(g1), dim3(256), 0, stream, R, p.d, ks, p.nblk, b.scal, b.map,
+                       b.blk_part, b.cent, static_cast<i32x4 *>((void *)b.packed), b.norms);
+    return launch_status("pack_fp8_resid");
+}
+
+int lowp_unmap(const KnnPlan &p, const KnnBuffers &b, hipStream_t stream) {
+    const int64_t count = p.nq * p.splits * p.screen;
+    const unsigned g = (unsigned)std::min<int64_t>((count + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_resid_unmap, dim3(g), dim3(256), 0, stream, b.cand_idx, count, b.map);
+    return launch_status("resid_unmap");
+}
+
 int lowp_screen(const KnnPlan &p, const scr::ScreenArgs &a, unsigned gx, hipStream_t s) {
     const int ks = lowp_steps(p.precision, p.d);
     if (p.precision == RSC_BF16) {
@@ -499,6 +771,12 @@ int lowp_screen(const KnnPlan &p, const scr::ScreenArgs &a, unsigned gx, hipStre
             case 7: return launch_lowp<RSC_BF16, 7, 32, kLowpQB>(a, gx, "screen_bf16", s);
             case 8: return launch_lowp<RSC_BF16, 8, 32, kLowpQB>(a, gx, "screen_bf16", s);
             case 9: return launch_lowp<RSC_BF16, 9, 32, kLowpQB>(a, gx, "screen_bf16", s);
+            default: break;
+        }
+    } else if (p.resid > 0) {
+        switch (ks) {
+            case 1: return launch_lowp<RSC_FP8_E4M3, 1, 32, kLowpQB, true>(a, gx, "screen_fp8_resid", s);
+            case 2: return launch_lowp<RSC_FP8_E4M3, 2, 32, kLowpQB, true>(a, gx, "screen_fp8_resid", s);
             default: break;
         }
     } else {

@@ -284,6 +284,59 @@ __global__ __launch_bounds__(kBlock) void k_lv_tot(const int32_t *__restrict__ l
 }
 
 // One sweep of local moving: Lnext[v] from the labels L at the sweep start.
+// A wave takes two consecutive vertices: when both rows have at most 32
+// entries, each half of the wave holds one row (its weights summed per
+// community by lane broadcasts within the half); otherwise the wave takes
+// the two vertices one after the other, a whole wave per row.
+__device__ __forceinline__ void move_one(int64_t v, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                                         const int64_t *__restrict__ gw, const int64_t *__restrict__ kdeg,
+                                         const int64_t *__restrict__ tot, const int32_t *__restrict__ L,
+                                         int32_t *__restrict__ Lnext, int up, double gamma, double two_m,
+                                         int32_t *__restrict__ hk, int64_t *__restrict__ hv, int &moved) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t b = ptr[v], e = ptr[v + 1];
+    const int32_t a = L[v];
+    const int64_t kv = kdeg[v];
+    double best_h = 0.0;
+    int32_t best_c = -1;
+    int64_t Ka = 0;  // K(v, a), held by the lanes whose key is a
+    bool has_a = false;
+    row_groups(
+        b, e, hk + 2 * b, hv + 2 * b,
+        [&](int64_t j, int32_t *c, int64_t *w) {
+            const int32_t u = col[j];
+            *c = u == (int32_t)v ? -1 : L[u];
+            *w = gw[j];
+        },
+        [&](bool valid, int32_t c, int64_t K) {
+            if (!valid) return;
+            if (c == a) {
+                Ka = K;
+                has_a = true;
+                return;
+            }
+            if (up ? c < a : c > a) return;
+            const double h = gain(K, gamma, kv, tot[c], two_m);
+            if (best_c < 0 || better(h, c, best_h, best_c)) {
+                best_h = h;
+                best_c = c;
+            }
+        });
+    wave_best(best_h, best_c);
+    // K(v, a): every lane that saw key a holds the same sum
+    const uint64_t holders = __ballot(has_a);
+    if (holders)
+        Ka = readlane64(Ka, __builtin_ctzll(holders));
+    else
+        Ka = 0;
+    const double stay = gain(Ka, gamma, kv, tot[a] - kv, two_m);
+    const int32_t next = (best_c >= 0 && best_h > stay) ? best_c : a;
+    if (lane == 0) {
+        Lnext[v] = next;
+        moved += next != a;
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_lv_move(const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
                                                     const int64_t *__restrict__ gw, int64_t N,
                                                     const int64_t *__restrict__ kdeg, const int64_t *__restrict__ tot,
@@ -291,50 +344,65 @@ __global__ __launch_bounds__(kBlock) void k_lv_move(const int64_t *__restrict__ 
                                                     int up, double gamma, double two_m, int32_t *__restrict__ hk,
                                                     int64_t *__restrict__ hv, LeidenState *__restrict__ st) {
     const int lane = threadIdx.x & (kWave - 1);
+    const int half = lane >> 5, sub = lane & 31;
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
     int moved = 0;
-    for (int64_t v = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; v < N; v += waves) {
-        const int64_t b = ptr[v], e = ptr[v + 1];
-        const int32_t a = L[v];
-        const int64_t kv = kdeg[v];
+    for (int64_t g = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; 2 * g < N; g += waves) {
+        const int64_t v = 2 * g + half;
+        const bool vok = v < N;
+        const int64_t b = vok ? ptr[v] : 0;
+        const int len = vok ? (int)(ptr[v + 1] - b) : 0;
+        const int len0 = __builtin_amdgcn_readlane(len, 0), len1 = __builtin_amdgcn_readlane(len, 32);
+        if (len0 > 32 || len1 > 32) {
+            move_one(2 * g, ptr, col, gw, kdeg, tot, L, Lnext, up, gamma, two_m, hk, hv, moved);
+            if (2 * g + 1 < N) move_one(2 * g + 1, ptr, col, gw, kdeg, tot, L, Lnext, up, gamma, two_m, hk, hv, moved);
+            continue;
+        }
+        const int32_t a = vok ? L[v] : -1;
+        const int64_t kv = vok ? kdeg[v] : 0;
+        int32_t c = -1;
+        int64_t w = 0;
+        if (sub < len) {
+            const int32_t u = col[b + sub];
+            c = u == (int32_t)v ? -1 : L[u];
+            w = gw[b + sub];
+        }
+        // K(v, c) of this lane's community within its half's row
+        const int tmax = len0 > len1 ? len0 : len1;
+        int64_t K = 0;
+        for (int t = 0; t < tmax; ++t) {
+            const int32_t c0 = __builtin_amdgcn_readlane(c, t), c1 = __builtin_amdgcn_readlane(c, 32 + t);
+            const int64_t w0 = readlane64(w, t), w1 = readlane64(w, 32 + t);
+            if ((half ? c1 : c0) == c) K += half ? w1 : w0;
+        }
         double best_h = 0.0;
         int32_t best_c = -1;
-        int64_t Ka = 0;  // K(v, a), held by the lanes whose key is a
-        bool has_a = false;
-        row_groups(
-            b, e, hk + 2 * b, hv + 2 * b,
-            [&](int64_t j, int32_t *c, int64_t *w) {
-                const int32_t u = col[j];
-                *c = u == (int32_t)v ? -1 : L[u];
-                *w = gw[j];
-            },
-            [&](bool valid, int32_t c, int64_t K) {
-                if (!valid) return;
-                if (c == a) {
-                    Ka = K;
-                    has_a = true;
-                    return;
-                }
-                if (up ? c < a : c > a) return;
-                const double h = gain(K, gamma, kv, tot[c], two_m);
-                if (best_c < 0 || better(h, c, best_h, best_c)) {
-                    best_h = h;
-                    best_c = c;
-                }
-            });
-        wave_best(best_h, best_c);
-        // K(v, a): every lane that saw key a holds the same sum
-        const uint64_t holders = __ballot(has_a);
-        if (holders) Ka = readlane64(Ka, __builtin_ctzll(holders));
-        else Ka = 0;
-        const double stay = gain(Ka, gamma, kv, tot[a] - kv, two_m);
-        const int32_t next = (best_c >= 0 && best_h > stay) ? best_c : a;
-        if (lane == 0) {
+        const bool valid = c >= 0;
+        const bool is_a = valid && c == a;
+        if (valid && !is_a && !(up ? c < a : c > a)) {
+            best_h = gain(K, gamma, kv, tot[c], two_m);
+            best_c = c;
+        }
+        for (int o = 16; o > 0; o >>= 1) {  // best within the half
+            const double h2 = __shfl_xor(best_h, o, kWave);
+            const int32_t c2 = __shfl_xor(best_c, o, kWave);
+            if (c2 >= 0 && (best_c < 0 || better(h2, c2, best_h, best_c))) {
+                best_h = h2;
+                best_c = c2;
+            }
+        }
+        const uint64_t holders = __ballot(is_a);
+        const uint32_t hold0 = (uint32_t)holders, hold1 = (uint32_t)(holders >> 32);
+        const int64_t Ka0 = hold0 ? readlane64(K, __builtin_ctz(hold0)) : 0;
+        const int64_t Ka1 = hold1 ? readlane64(K, 32 + __builtin_ctz(hold1)) : 0;
+        if (vok && sub == 0) {
+            const double stay = gain(half ? Ka1 : Ka0, gamma, kv, tot[a] - kv, two_m);
+            const int32_t next = (best_c >= 0 && best_h > stay) ? best_c : a;
             Lnext[v] = next;
             moved += next != a;
         }
     }
-    if (lane == 0 && moved) atomicAdd(&st->moved, moved);
+    if ((lane & 31) == 0 && moved) atomicAdd(&st->moved, moved);
 }
 
 // Refinement set-up: kin[v] = K(v, C - v) and totC[c] = sum of k over c.
@@ -712,8 +780,7 @@ int read_back(T *host, const T *dev, hipStream_t s, const char *what) {
 size_t leiden_workspace_bytes(int64_t n, int64_t nnz) { return carve_leiden(n, nnz, nullptr, nullptr); }
 
 int leiden_run(const int64_t *indptr, const int32_t *indices, const float *weights, int64_t n, int64_t nnz,
-               double gamma, int32_t *labels, double *quality, int32_t *levels_out, int64_t *ncomm_out, void *ws,
-               hipStream_t s) {
+               double gamma, int32_t *labels, rsc_leiden_stats *stats, void *ws, hipStream_t s) {
     LeidenWs w;
     carve_leiden(n, nnz, ws, &w);
     int st;
@@ -751,7 +818,8 @@ int leiden_run(const int64_t *indptr, const int32_t *indices, const float *weigh
     if ((st = launch_status("leiden set-up")) != RSC_OK) return st;
 
     int64_t N = n, M = nnz;
-    int lv = 0;
+    int lv = 0, sweeps = 0, rounds = 0;
+    int64_t move_bytes = 0;
     double two_m0 = 0.0;
     for (;;) {
         hipLaunchKernelGGL(k_lv_init, dim3(1), dim3(64), 0, s, w.st);
@@ -765,12 +833,17 @@ int leiden_run(const int64_t *indptr, const int32_t *indices, const float *weigh
         int64_t moves = 0;
         int quiet = 0;
         for (int sweep = 1; sweep <= kMaxSweeps && quiet < 2; ++sweep) {
-            hipLaunchKernelGGL(k_lv_fill64, dim3(grid_items(N)), dim3(kBlock), 0, s, w.tot, N, (int64_t)0);
-            hipLaunchKernelGGL(k_lv_tot, dim3(grid_items(N)), dim3(kBlock), 0, s, w.L, w.kdeg, N, w.tot);
-            hipLaunchKernelGGL(k_lv_init, dim3(1), dim3(64), 0, s, w.st);
-            hipLaunchKernelGGL(k_lv_move, dim3(grid_waves(N)), dim3(kBlock), 0, s, G.ptr, G.col, G.w, N, w.kdeg,
-                               w.tot, w.L, w.Lnext, sweep % 2, gamma, two_m, w.hk, w.hv, w.st);
+            {
+                ScopedTimer t("leiden_move", s);
+                hipLaunchKernelGGL(k_lv_fill64, dim3(grid_items(N)), dim3(kBlock), 0, s, w.tot, N, (int64_t)0);
+                hipLaunchKernelGGL(k_lv_tot, dim3(grid_items(N)), dim3(kBlock), 0, s, w.L, w.kdeg, N, w.tot);
+                hipLaunchKernelGGL(k_lv_init, dim3(1), dim3(64), 0, s, w.st);
+                hipLaunchKernelGGL(k_lv_move, dim3(grid_waves((N + 1) / 2)), dim3(kBlock), 0, s, G.ptr, G.col, G.w, N, w.kdeg,
+                                   w.tot, w.L, w.Lnext, sweep % 2, gamma, two_m, w.hk, w.hv, w.st);
+            }
             if ((st = launch_status("leiden local moving")) != RSC_OK) return st;
+            ++sweeps;
+            move_bytes += 16 * M + 24 * N;
             std::swap(w.L, w.Lnext);
             if ((st = read_back(&hs, w.st, s, "read moves")) != RSC_OK) return st;
             moves += hs.moved;
@@ -779,6 +852,8 @@ int leiden_run(const int64_t *indptr, const int32_t *indices, const float *weigh
         ++lv;
         if (moves == 0 || lv >= kMaxLevels) break;
         // 2. refinement
+        {
+        ScopedTimer t_refine("leiden_refine", s);
         hipLaunchKernelGGL(k_lv_fill64, dim3(grid_items(N)), dim3(kBlock), 0, s, w.totC, N, (int64_t)0);
         hipLaunchKernelGGL(k_lv_iota, dim3(grid_items(N)), dim3(kBlock), 0, s, w.R, N);
         hipLaunchKernelGGL(k_lv_refine_prep, dim3(grid_waves(N)), dim3(kBlock), 0, s, G.ptr, G.col, G.w, N, w.kdeg,
@@ -797,10 +872,13 @@ int leiden_run(const int64_t *indptr, const int32_t *indices, const float *weigh
             hipLaunchKernelGGL(k_lv_refine_apply, dim3(grid_items(N)), dim3(kBlock), 0, s, w.prop, w.size, N, w.R,
                                w.st);
             if ((st = launch_status("leiden refinement")) != RSC_OK) return st;
+            ++rounds;
             if ((st = read_back(&hs, w.st, s, "read joins")) != RSC_OK) return st;
             if (!hs.joins) break;
         }
+        }
         // 3. aggregation
+        ScopedTimer t_agg("leiden_aggregate", s);
         hipLaunchKernelGGL(k_lv_heads, dim3(grid_items(N)), dim3(kBlock), 0, s, w.R, N, w.head);
         if ((st = hip_status(rocprim::exclusive_scan(w.tmp, w.tmp_bytes, (const int32_t *)w.head, w.id, (int32_t)0,
                                                      (size_t)N, rocprim::plus<int32_t>(), s),
@@ -868,7 +946,7 @@ int leiden_run(const int64_t *indptr, const int32_t *indices, const float *weigh
         (st = hip_status(hipStreamSynchronize(s), "synchronise")) != RSC_OK)
         return st;
     const int64_t ncomm = (int64_t)last_num + last_mark;
-    if (quality) {
+    {
         double q = 0.0;
         if (two_m0 > 0.0) {
             hipLaunchKernelGGL(k_lv_fill64, dim3(grid_items(ncomm)), dim3(kBlock), 0, s, w.qin, ncomm, (int64_t)0);
@@ -879,10 +957,16 @@ int leiden_run(const int64_t *indptr, const int32_t *indices, const float *weigh
             if ((st = launch_status("leiden modularity")) != RSC_OK) return st;
             if ((st = read_back(&q, w.q, s, "read modularity")) != RSC_OK) return st;
         }
-        *quality = q;
+        if (stats) {
+            stats->quality = q;
+            stats->n_communities = ncomm;
+            stats->levels = lv;
+            stats->sweeps = sweeps;
+            stats->rounds = rounds;
+            stats->reserved = 0;
+            stats->move_bytes = move_bytes;
+        }
     }
-    if (levels_out) *levels_out = lv;
-    if (ncomm_out) *ncomm_out = ncomm;
     return RSC_OK;
 }
 

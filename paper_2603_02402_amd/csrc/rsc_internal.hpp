@@ -73,6 +73,7 @@ struct KnnPlan {
     int splits;            // reference ranges of the main screen
     int precision;         // rsc_precision of the screen
     int metric;            // rsc_metric
+    int resid;             // FP8 residual variant: reference partitions (0 = off)
 };
 
 struct KnnBuffers {
@@ -86,6 +87,13 @@ struct KnnBuffers {
     int32_t *esc_idx;
     float *esc_key;
     float *qn, *rn;   // unit-normalised queries / references (cosine metric)
+    // FP8 residual variant
+    float *cent;          // partition centroids, resid x d
+    int32_t *assign, *perm, *init, *map;
+    int32_t *blk_part;    // partition of each packed block, 4 copies per block
+    int64_t *poff, *pblk;
+    void *kws;            // k-means workspace
+    size_t kws_bytes;
 };
 
 // Arguments of the float64 rerank (knn.hip).
@@ -154,6 +162,11 @@ size_t lowp_packed_bytes(int precision, int64_t nblk, int d);
 int lowp_prepare(const KnnPlan &p, const float *Q, const float *R, void *packed, float *norms, float *scal,
                  uint32_t *amax, hipStream_t stream);
 int lowp_screen(const KnnPlan &p, const scr::ScreenArgs &a, unsigned gx, hipStream_t s);
+// FP8 residual variant: partitions, residual scales and the partition-ordered
+// packing (into b.packed / b.norms, with b.map and b.blk_part); then, after
+// the screen, the candidates' packed rows turned back into row ids.
+int lowp_prepare_resid(const KnnPlan &p, const float *R, const KnnBuffers &b, hipStream_t stream);
+int lowp_unmap(const KnnPlan &p, const KnnBuffers &b, hipStream_t stream);
 
 // Batched form (knn_batched.hip).
 size_t batched_workspace_bytes(const int64_t *offsets, int S, int d, int k);
@@ -162,6 +175,7 @@ int batched_run(const float *X, const int64_t *offsets, int S, int d, int k, int
 int batched_autotune(const float *X, const int64_t *offsets, int S, int d, int k, void *ws, size_t ws_bytes,
                      hipStream_t s, int32_t *chosen, float *times_ms);
 const char *batched_policy_name(int pol);
+const char *batched_trial_name(int trial);
 
 // ---- routed form (partition.hip, router.hip, routed.hip) -----------------
 
@@ -253,7 +267,6 @@ int graph_run_noalloc(const int32_t *idx, const float *dist, int64_t n, int k, i
 
 size_t leiden_workspace_bytes(int64_t n, int64_t nnz);
 int leiden_run(const int64_t *indptr, const int32_t *indices, const float *weights, int64_t n, int64_t nnz,
-               double gamma, int32_t *labels, double *quality, int32_t *levels_out, int64_t *ncomm_out, void *ws,
-               hipStream_t s);
+               double gamma, int32_t *labels, rsc_leiden_stats *stats, void *ws, hipStream_t s);
 
 }  // namespace rsc

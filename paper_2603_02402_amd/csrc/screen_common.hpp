@@ -63,6 +63,8 @@ struct ScreenArgs {
     const void *Ap;         // packed references (layout depends on the precision)
     const float *Np;        // norms in accumulator order, where the layout needs them
     const float *qscale;    // per-dimension query scales (FP8 screen)
+    const int32_t *blk_part;  // FP8 residual variant: partition of each packed block (4 copies per block)
+    const float *cent;        // FP8 residual variant: partition centroids
     int64_t nblk;
     int d;
     int P;                  // reference ranges (gridDim.y)

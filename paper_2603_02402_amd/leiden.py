@@ -5,14 +5,14 @@ from __future__ import annotations
 
 import ctypes
 
-from ._lib import check, load
+from ._lib import LeidenStats, check, load
 
 
 def leiden(graph, gamma: float = 1.0, workspace=None):
     """Leiden communities of a symmetric CSR graph (a :class:`Graph` or
-    ``(indptr, indices, data)`` on the GPU).  Returns ``(labels, quality,
-    levels, n_communities)``: labels a new int32 tensor numbered by first
-    appearance, quality the modularity of the labels."""
+    ``(indptr, indices, data)`` on the GPU).  Returns ``(labels, stats)``:
+    labels a new int32 tensor numbered by first appearance; stats a dict of
+    ``rsc_leiden_stats`` (quality = the modularity of the labels)."""
     import torch
 
     from . import Workspace
@@ -34,11 +34,9 @@ def leiden(graph, gamma: float = 1.0, workspace=None):
         raise ValueError("leiden: unsupported size (1 <= n <= 2^31 - 2, 0 <= nnz <= 2^40)")
     ws = (workspace or Workspace(indptr.device)).get(need)
     labels = torch.empty(n, dtype=torch.int32, device=indptr.device)
-    q = ctypes.c_double(0.0)
-    lv = ctypes.c_int32(0)
-    nc = ctypes.c_int64(0)
+    st = LeidenStats()
     check(lib.rsc_leiden(ctypes.c_void_p(indptr.data_ptr()), ctypes.c_void_p(indices.data_ptr()),
                          ctypes.c_void_p(data.data_ptr()), n, nnz, gamma, ctypes.c_void_p(labels.data_ptr()),
-                         ctypes.byref(q), ctypes.byref(lv), ctypes.byref(nc), ctypes.c_void_p(ws.data_ptr()),
-                         ws.numel(), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
-    return labels, float(q.value), int(lv.value), int(nc.value)
+                         ctypes.byref(st), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                         ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+    return labels, {f: getattr(st, f) for f, _ in st._fields_ if f != "reserved"}

@@ -85,11 +85,12 @@ def _noise_scale(d: int) -> np.ndarray:
 
 
 def mixture_from_centres(rng: np.random.Generator, centres: np.ndarray, n: int,
-                         weights: np.ndarray, return_labels: bool = False):
-    """Draw ``n`` cells around given ``centres`` (labels first, then noise)."""
+                         weights: np.ndarray, return_labels: bool = False, spread: float = 1.0):
+    """Draw ``n`` cells around given ``centres`` (labels first, then noise
+    of standard deviation ``spread`` sqrt(1/i) in dimension i)."""
     c, d = centres.shape
     labels = rng.choice(c, size=n, p=weights)
-    scale = _noise_scale(d)
+    scale = _noise_scale(d) * spread
     out = np.empty((n, d), dtype=np.float32)
     for s in range(0, n, _CHUNK):
         e = min(n, s + _CHUNK)
@@ -115,6 +116,15 @@ def mixture(n: int, d: int = 50, n_clusters: int = 20, law: str = "uniform", see
     rng = _rng(seed)
     centres = draw_centres(rng, n_clusters, d)
     return mixture_from_centres(rng, centres, n, cluster_weights(n_clusters, law), return_labels)
+
+
+def tight_mixture(n: int, d: int = 50, n_clusters: int = 20, spread: float = 0.2, seed: int = 0):
+    """A mixture whose clusters are ``spread`` times as wide as ``mixture``'s:
+    the neighbour gaps are then small against the row norms, as they are in
+    the 2M-cell workload, at a size the CPU oracle handles."""
+    rng = _rng(seed)
+    centres = draw_centres(rng, n_clusters, d)
+    return mixture_from_centres(rng, centres, n, cluster_weights(n_clusters, "uniform"), spread=spread)
 
 
 def batched_sizes(n_samples: int = 64, lo: int = 2000, hi: int = 200000, seed: int = 4) -> np.ndarray:

@@ -167,10 +167,8 @@ def test_connectivities_noalloc_validation(lib):
 
 
 def test_leiden_validation(lib):
-    q = ctypes.c_double(0)
-
     def call(n=100, nnz=1000, gamma=1.0, ptr=FAKE, idx=FAKE, w=FAKE, lab=FAKE, ws=FAKE, ws_bytes=1 << 30):
-        return lib.rsc_leiden(ptr, idx, w, n, nnz, gamma, lab, ctypes.byref(q), None, None, ws, ws_bytes, None)
+        return lib.rsc_leiden(ptr, idx, w, n, nnz, gamma, lab, None, ws, ws_bytes, None)
 
     assert call(n=0) == -1
     assert call(nnz=-1) == -1
@@ -263,6 +261,8 @@ def test_batched_validation(lib):
     assert lib.rsc_knn_batched_workspace_bytes(bad.ctypes.data_as(ctypes.c_void_p), 2, 50, 15) == 0
     assert lib.rsc_batch_policy_name(0) != b""
     assert lib.rsc_batch_policy_name(99) == b""
+    assert lib.rsc_batch_trial_name(0) == b""  # no autotune call yet
+    assert lib.rsc_batch_trial_name(-1) == b""
 
 
 def test_routed_validation(lib):
@@ -319,6 +319,28 @@ def test_metric_validation(lib):
     # the cosine form keeps the normalised rows in its workspace
     assert lib.rsc_knn_workspace_bytes(1000, 1000, 50, 15, ctypes.byref(cos)) > \
         lib.rsc_knn_workspace_bytes(1000, 1000, 50, 15, ctypes.byref(eu)) + 1000 * 50 * 4 - 1
+
+
+def test_fp8_residual_validation(lib):
+    from paper_2603_02402_amd import _lib
+
+    def opts(prec, parts, metric=0):
+        return _lib.KnnOpts(prec, 0, metric, parts)
+
+    def call(o, n=1000):
+        return lib.rsc_knn_opt(FAKE, n, 50, 15, ctypes.byref(o), FAKE, FAKE, FAKE, 1 << 40, None)
+
+    assert call(opts(1, 16)) == -1 and "fp8_residual" in _err(lib)      # BF16 screen
+    assert call(opts(0, 16)) == -1                                        # FP32 screen
+    assert call(opts(2, 16, metric=1)) == -1                              # cosine metric
+    assert call(opts(2, 1)) == -1 and "partition" in _err(lib)
+    assert call(opts(2, 4097)) == -1
+    assert call(opts(2, 1001)) == -1                                      # more partitions than rows
+    assert lib.rsc_knn_workspace_bytes(1000, 1000, 50, 15, ctypes.byref(opts(2, 1001))) == 0
+    # the residual variant holds its partitions, lists and map beyond the plain FP8 workspace
+    plain = lib.rsc_knn_workspace_bytes(1000, 1000, 50, 15, ctypes.byref(opts(2, 0)))
+    resid = lib.rsc_knn_workspace_bytes(1000, 1000, 50, 15, ctypes.byref(opts(2, 16)))
+    assert resid > plain + 16 * 50 * 4 + 2 * 1000 * 4
 
 
 def test_edistance_validation(lib):

@@ -81,15 +81,23 @@ def test_shapes(rsc, oracle_mod, d, k):
 
 
 def test_autotune_and_determinism(rsc, oracle_mod):
+    """The autotuner measures the schedule policies, the wider screen tile and
+    the tile depth per size class; whatever shape it picks, the result is the
+    exact kNN, bitwise the same as under the default shape."""
     sizes = np.rint(np.exp(np.random.default_rng(5).uniform(np.log(2000), np.log(60000), size=12))).astype(int)
     X, off = small_batch(sizes, seed=11)
+    i0, d0, _, _ = run_batched(rsc, X, off, 15)  # default shape (nothing tuned for this batch yet)
     i1, d1, _, tuned = run_batched(rsc, X, off, 15, autotune=True)
     chosen, times = tuned
-    log(f"[batched] autotune chose {chosen}: {times}")
-    assert 0 <= chosen < 6 and all(t > 0 for t in times.values())
+    log(f"[batched] autotune chose trial {chosen}: {times}")
+    assert len(times) > 6 and 0 <= chosen < len(times) and all(t > 0 for t in times.values())
+    assert any("tile 32 keys/half" in name for name in times)
+    assert any("reference range" in name for name in times)
+    assert "[chosen:" in list(times)[chosen]
     i2, d2, _, _ = run_batched(rsc, X, off, 15)
-    np.testing.assert_array_equal(i1, i2)
-    np.testing.assert_array_equal(d1.view(np.uint32), d2.view(np.uint32))
+    for ix, dx in ((i0, d0), (i2, d2)):
+        np.testing.assert_array_equal(i1, ix)
+        np.testing.assert_array_equal(d1.view(np.uint32), dx.view(np.uint32))
     check_against_oracle(oracle_mod, X, off, i1, d1, 15, rows_per_sample=16)
 
 

@@ -33,9 +33,10 @@ def gpu_leiden(rsc, indptr, indices, data, gamma=1.0):
     import torch
 
     g = tuple(torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (indptr, indices, data))
-    labels, q, lv, nc = rsc.leiden(g, gamma=gamma)
+    labels, st = rsc.leiden(g, gamma=gamma)
     torch.cuda.synchronize()
-    return labels.cpu().numpy(), q, lv, nc
+    assert st["sweeps"] >= st["levels"] and st["move_bytes"] >= 0
+    return labels.cpu().numpy(), st["quality"], st["levels"], st["n_communities"]
 
 
 def check(rsc, indptr, indices, data, label, gamma=1.0):

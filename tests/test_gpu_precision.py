@@ -2,7 +2,8 @@
 
 Judged by recall@15 and distance error against the FP64 oracle (the
 spec bar for this form is recall@15 >= 0.99 for BF16; the FP8 form
-with per-dimension absmax scaling is reported, not held to that bar).
+with per-dimension absmax scaling is held to its measured recall less a
+margin: 1.0 on the 10k workload, 0.50 on the 2M one).
 """
 
 import sys
@@ -62,7 +63,7 @@ def check_structure(X, idx, dist, k, oracle_mod, self_mode=True):
         np.testing.assert_array_equal(dist[rows, first:].ravel(), d_exact)
 
 
-@pytest.mark.parametrize("precision,floor", [("bf16", 0.99), ("fp8", 0.3)])
+@pytest.mark.parametrize("precision,floor", [("bf16", 0.99), ("fp8", 0.99)])
 def test_10k_recall(rsc, oracle_mod, precision, floor):
     prec = rsc.RSC_BF16 if precision == "bf16" else rsc.RSC_FP8_E4M3
     X = synth.workload("plain_10k")
@@ -110,7 +111,8 @@ def test_precision_2m_sampled(rsc, oracle_mod):
     rows = synth.sample_rows(X.shape[0], 64, seed=321)
     log("[precision] 2M oracle on 64 sampled rows")
     _, _, dist_o = oracle_mod.knn_rows(X, rows, 15)
-    for name, prec, floor in (("bf16", rsc.RSC_BF16, 0.99), ("fp8", rsc.RSC_FP8_E4M3, 0.2)):
+    # measured: FP8 0.503 on these 64 rows (0.513 over all 2M rows)
+    for name, prec, floor in (("bf16", rsc.RSC_BF16, 0.99), ("fp8", rsc.RSC_FP8_E4M3, 0.45)):
         idx, dist = run(rsc, X, 15, prec)
         rec = tie_aware_recall(dist[rows], dist_o, 15)
         log(f"[precision] {name} 2M sampled recall@15 = {rec:.5f}")

@@ -396,10 +396,23 @@ def test_router_rejects_bad_arguments(rsc, tmp_path):
 # ---------------------------------------------------------------------------
 
 def test_routed_end_to_end_and_ablation(rsc, oracle_mod):
-    """What the trained router gains over probing the nearest centroids: at
-    the same number of probes, the routed form (router + exact fallback for
-    low-mass rows) must reach recall@15 >= 0.99 and beat nearest-centroid
-    probing, which has no way to tell a hard row from an easy one."""
+    """What the trained router gains over probing the nearest centroids,
+    measured like against like at the same number of probes:
+      * the network alone (no fallback) against the nearest centroids (no
+        fallback): the network ranks the partitions no better than the
+        centroid distances do (measured: 0.969 against 0.971), and is held
+        within one point of them;
+      * the routed form (router + exact search for its low-mass rows) must
+        reach recall@15 >= 0.99, and is compared with the nearest centroids
+        given the same exact-search budget: exact search for the same number
+        of rows, chosen by the centroids' own signal of doubt, the smallest
+        gap between the squared distances to the (probes+1)-th and the
+        probes-th (or the first) nearest centroid.  The network's softmax
+        mass beats the first gap (0.994 against 0.987) and only matches the
+        second (0.9936 against 0.9938): held within 0.3 points of the best.
+    So the trained network's gain over the method without it is its
+    confidence signal, not its ranking, and a plain geometric signal does as
+    well; the benchmark reports the same comparison at 5M cells."""
     from oracle import partition
 
     k, P, probes = 15, 128, 6
@@ -426,12 +439,25 @@ def test_routed_end_to_end_and_ablation(rsc, oracle_mod):
     nc_parts, _ = rsc.knn(C, probes, Q=Xb)             # nearest centroids, in order
     nc_idx, _, _, st_nc = rsc.knn_probed(Xb, k, off, perm, nc_parts)
     rec_nc = recall(nc_idx)
-    log(f"  recall@15: routed+fallback {rec_routed:.4f} (exact rows {st['low_mass_rows']}, "
+    import torch
+
+    nc_d = rsc.knn(C, probes + 1, Q=Xb)[1].double() ** 2
+    low = int(st["low_mass_rows"])
+    rec_gap = {}
+    for name, (a, b) in {"next": (probes, probes - 1), "first": (probes, 0)}.items():
+        mask = torch.zeros(n, dtype=torch.uint8, device="cuda")
+        mask[torch.argsort(nc_d[:, a] - nc_d[:, b])[:low]] = 1
+        g_idx, _, _, _ = rsc.knn_probed(Xb, k, off, perm, nc_parts[:, :probes].contiguous(), exact_rows=mask)
+        rec_gap[name] = recall(g_idx)
+    log(f"  recall@15: routed+fallback {rec_routed:.4f} (exact rows {low}, "
         f"uncertified {st['uncertified_rows']}, mean candidates {st['mean_probed_rows']:.0f}); "
         f"router only {rec_router_only:.4f}; nearest centroids {rec_nc:.4f} "
-        f"(mean candidates {st_nc['mean_probed_rows']:.0f})")
+        f"(mean candidates {st_nc['mean_probed_rows']:.0f}); nearest centroids + exact search for the same "
+        f"{low} rows by gap to the next centroid {rec_gap['next']:.4f}, to the first {rec_gap['first']:.4f}")
     assert rec_routed >= 0.99
-    assert rec_routed > rec_nc
+    assert rec_routed > rec_gap["next"]
+    assert rec_routed >= max(rec_gap.values()) - 0.003
+    assert rec_router_only >= rec_nc - 0.01
     # the routed answer itself: exact within the probed partitions for routed
     # rows (the oracle on the router's own probe lists), exact over every cell
     # for rows sent to exact search
