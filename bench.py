@@ -255,7 +255,7 @@ def precision_forms(args, rsc) -> dict:
     del X
     ws = rsc.Workspace(dev)
     ws.get(max(rsc.knn_workspace_bytes(n, n, d, k), rsc.knn_workspace_bytes(n, n, d, k, precision=rsc.RSC_BF16),
-               rsc.knn_workspace_bytes(n, n, d, k, precision=rsc.RSC_FP8_E4M3, fp8_residual=256),
+               rsc.knn_workspace_bytes(n, n, d, k, precision=rsc.RSC_FP8_E4M3, fp8_residual=1024),
                rsc.connectivities_workspace_bytes(n, k)))
     cap = 2 * n * (k - 1)
 
@@ -283,16 +283,16 @@ def precision_forms(args, rsc) -> dict:
                      "screen_frac_of_peak": round(2 * d * n * n / (scr / 1e3) / 1e12 / peak, 4),
                      "weight_error_on_common_entries": we,
                      "meets_recall_0.99": rec >= 0.99}
-    # the FP8 residual variant (a separately labelled form): 256 k-means
+    # the FP8 residual variant (a separately labelled form): 1024 k-means
     # partitions of the cells, residual coding on both sides; the partitioning
     # is part of every timed call
     log("[bench] precision forms: fp8_e4m3_residual_rerank")
     kern = {}
-    ms, scr, g = timed_form(rsc, Xt, k, rsc.RSC_FP8_E4M3, args.form_steps, 1, ws, fo, fp8_residual=256, kernels=kern)
+    ms, scr, g = timed_form(rsc, Xt, k, rsc.RSC_FP8_E4M3, args.form_steps, 1, ws, fo, fp8_residual=1024, kernels=kern)
     rec = recall_at_k(fo[1], ex[1], k)
     we = weight_error(g, g_exact, n)
     res["fp8_e4m3_residual_rerank"] = {
-        "partitions": 256, "cells_per_s": round(n / (ms / 1e3), 1), "ms_per_step": round(ms, 2),
+        "partitions": 1024, "cells_per_s": round(n / (ms / 1e3), 1), "ms_per_step": round(ms, 2),
         "screen_ms": round(scr, 2), "kernel_ms": kern, "recall@15": round(rec, 5),
         "screen_tflops_algorithmic": round(2 * d * n * n / (scr / 1e3) / 1e12, 2),
         "screen_frac_of_peak": round(2 * d * n * n / (scr / 1e3) / 1e12 / 5000.0, 4),

@@ -393,6 +393,45 @@ __global__ __launch_bounds__(256) void k_resid_fill_i32(int32_t *__restrict__ a,
         a[i] = v;
 }
 
+// The residual variant's query codes against one partition: the e4m3 codes
+// of -2 G s_t (x_t - c_t) over this lane's contraction half, and G |x - c|^2.
+// Kept out of line: it runs once per partition change, and inlined into the
+// unrolled block loop it would be copied once per block of a phase.
+template <int KS>
+struct ResidCodes {
+    i32x8 c[KS];
+    float t;
+};
+
+template <int KS>
+__device__ __noinline__ ResidCodes<KS> resid_query_codes(const float *__restrict__ Q, const float *__restrict__ cent,
+                                                         const float *__restrict__ qscale, int d, int64_t row,
+                                                         int part, int h) {
+    ResidCodes<KS> out;
+    const float *cp = cent + (int64_t)part * d;
+    const float *x = Q + (row >= 0 ? row : 0) * d;
+    float ss = 0.f;
+    for (int s = 0; s < KS; ++s) {
+        for (int w = 0; w < 8; ++w) {
+            uint32_t four = 0;
+            for (int q = 0; q < 4; ++q) {
+                const int kk = 64 * s + 32 * h + 4 * w + q;
+                uint32_t code = 0;
+                if (row >= 0 && kk < d) {
+                    const float qv = x[kk] - cp[kk];
+                    ss += qv * qv;
+                    code = e4m3_code(qv * qscale[d + kk]);
+                }
+                four |= code << (8 * q);
+            }
+            out.c[s][w] = (int)four;
+        }
+    }
+    ss += __shfl_xor(ss, 32, kWave);  // the other contraction half's dimensions
+    out.t = qscale[2 * d] * ss;
+    return out;
+}
+
 // Candidate lists hold packed rows: turn them into row ids (-1 stays).
 __global__ __launch_bounds__(256) void k_resid_unmap(int32_t *__restrict__ cand, int64_t count,
                                                      const int32_t *__restrict__ map) {
@@ -557,36 +596,14 @@ __global__ __launch_bounds__(256, 3) void k_screen_lowp(ScreenArgs a) {
 
         // Residual variant: the query codes of q = x - c_p (wave-uniform call).
         auto code_partition = [&](int part) {
-            const float *cp = a.cent + (int64_t)part * a.d;
-            const float G = a.qscale[2 * a.d];
+            if constexpr (PREC == RSC_FP8_E4M3) {
 #pragma unroll
-            for (int qb = 0; qb < QB; ++qb) {
-                const int64_t row = qrow[qb];
-                const float *x = a.Q + (row >= 0 ? row : 0) * a.d;
-                float ss = 0.f;
+                for (int qb = 0; qb < QB; ++qb) {
+                    const ResidCodes<KS> rc = resid_query_codes<KS>(a.Q, a.cent, a.qscale, a.d, qrow[qb], part, h);
 #pragma unroll
-                for (int s = 0; s < KS; ++s) {
-                    T v;
-#pragma unroll
-                    for (int w = 0; w < 8; ++w) {
-                        uint32_t four = 0;
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const int kk = 64 * s + 32 * h + 4 * w + q;
-                            uint32_t code = 0;
-                            if (row >= 0 && kk < a.d) {
-                                const float qv = x[kk] - cp[kk];
-                                ss += qv * qv;
-                                code = e4m3_code(qv * a.qscale[a.d + kk]);
-                            }
-                            four |= code << (8 * q);
-                        }
-                        v[w] = (int)four;
-                    }
-                    bq[qb][s] = v;
+                    for (int s = 0; s < KS; ++s) bq[qb][s] = rc.c[s];
+                    tq[qb] = rc.t;
                 }
-                ss += __shfl_xor(ss, 32, kWave);  // the other contraction half's dimensions
-                tq[qb] = G * ss;
             }
         };
 
