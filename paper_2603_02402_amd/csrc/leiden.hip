@@ -405,6 +405,23 @@ __global__ __launch_bounds__(kBlock) void k_lv_move(const int64_t *__restrict__ 
     if ((lane & 31) == 0 && moved) atomicAdd(&st->moved, moved);
 }
 
+// After a sweep: the community totals follow the vertices that moved (integer
+// sums, so tot stays exactly the sum of k over each label).
+__global__ __launch_bounds__(kBlock) void k_lv_tot_delta(const int32_t *__restrict__ L,
+                                                         const int32_t *__restrict__ Lnext,
+                                                         const int64_t *__restrict__ kdeg, int64_t N,
+                                                         int64_t *__restrict__ tot) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < N; v += stride) {
+        const int32_t a = L[v], b = Lnext[v];
+        const int64_t kv = kdeg[v];
+        if (a != b && kv) {
+            atomicAdd(reinterpret_cast<unsigned long long *>(&tot[b]), (unsigned long long)kv);
+            atomicAdd(reinterpret_cast<unsigned long long *>(&tot[a]), (unsigned long long)(-kv));
+        }
+    }
+}
+
 // Refinement set-up: kin[v] = K(v, C - v) and totC[c] = sum of k over c.
 __global__ __launch_bounds__(kBlock) void k_lv_refine_prep(const int64_t *__restrict__ ptr,
                                                            const int32_t *__restrict__ col,
@@ -832,14 +849,18 @@ int leiden_run(const int64_t *indptr, const int32_t *indices, const float *weigh
         // 1. local moving
         int64_t moves = 0;
         int quiet = 0;
+        // community totals of the level's starting labels; each sweep then
+        // moves them along with the vertices that change label
+        hipLaunchKernelGGL(k_lv_fill64, dim3(grid_items(N)), dim3(kBlock), 0, s, w.tot, N, (int64_t)0);
+        hipLaunchKernelGGL(k_lv_tot, dim3(grid_items(N)), dim3(kBlock), 0, s, w.L, w.kdeg, N, w.tot);
         for (int sweep = 1; sweep <= kMaxSweeps && quiet < 2; ++sweep) {
             {
                 ScopedTimer t("leiden_move", s);
-                hipLaunchKernelGGL(k_lv_fill64, dim3(grid_items(N)), dim3(kBlock), 0, s, w.tot, N, (int64_t)0);
-                hipLaunchKernelGGL(k_lv_tot, dim3(grid_items(N)), dim3(kBlock), 0, s, w.L, w.kdeg, N, w.tot);
                 hipLaunchKernelGGL(k_lv_init, dim3(1), dim3(64), 0, s, w.st);
                 hipLaunchKernelGGL(k_lv_move, dim3(grid_waves((N + 1) / 2)), dim3(kBlock), 0, s, G.ptr, G.col, G.w, N, w.kdeg,
                                    w.tot, w.L, w.Lnext, sweep % 2, gamma, two_m, w.hk, w.hv, w.st);
+                hipLaunchKernelGGL(k_lv_tot_delta, dim3(grid_items(N)), dim3(kBlock), 0, s, w.L, w.Lnext, w.kdeg, N,
+                                   w.tot);
             }
             if ((st = launch_status("leiden local moving")) != RSC_OK) return st;
             ++sweeps;
