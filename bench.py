@@ -88,9 +88,11 @@ def graph_gbs(kernels: dict, n: int, k: int, nnz: int) -> dict:
     one_way = max(nnz - E, 0)
     mutual = max(2 * E - nnz, 0)
     nk = n * k
+    P = (m + 15) // 16 * 16  # padded list length of the mutual-edge lookup
     design = {
         "smooth_knn": 4 * nk + 8 * E + 16 * n,                                    # dist in; a, rho, sigma out
-        "union_count": 4 * nk + 8 * E + 8 * mutual + 4 * E + 4 * E + 8 * n,       # idx, a (own + reverse) in; wf, rs, counts out
+        # idx, a (own + reverse) in; padded id copy out and back in; wf, rs, counts out
+        "union_count": 4 * nk + 8 * n * P + 8 * E + 8 * mutual + 4 * E + 4 * E + 8 * n,
         "csr_scan": 8 * n + 16 * n + 8 * (n + 1),                                 # counts in; indptr, reverse bases out
         "union_fill": 4 * E + 4 * E + 4 * nk + 8 * one_way + 8 * one_way,         # rs, wf, idx, bases in; reverse records out
         "row_sort": 20 * n + 4 * E + 4 * nk + 8 * one_way + 8 * nnz,              # bases, counts, indptr, wf, idx, records in; CSR out

@@ -226,12 +226,33 @@ __device__ __forceinline__ void sample_of(const int64_t *__restrict__ seg, int S
     *hi = seg[b];
 }
 
+// ids[i * P + t] = row i's neighbour t (slots 1..k-1 of idx), -1 in the
+// padding up to P (a multiple of 16): every row starts a 64-byte line, so the
+// mutual-edge lookup of a row reads whole lines.
+__global__ __launch_bounds__(256) void k_pad_ids(const int32_t *__restrict__ idx, int64_t n, int k, int P,
+                                                 int4 *__restrict__ ids) {
+    const int m = k - 1, q = P / 4;
+    const int64_t total = n * q;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = t / q;
+        const int c = 4 * (int)(t - i * q);
+        const int32_t *src = idx + i * k + 1;
+        int4 v;
+        v.x = c < m ? src[c] : -1;
+        v.y = c + 1 < m ? src[c + 1] : -1;
+        v.z = c + 2 < m ? src[c + 2] : -1;
+        v.w = c + 3 < m ? src[c + 3] : -1;
+        ids[t] = v;
+    }
+}
+
 // Union weight of every directed edge, the rows' kept counts and the slots
 // of the one-way edges among their targets' reverse entries.
 //   wf[e]   float32 union weight (0: dropped, or a rejected edge);
 //   rs[e]   slot among row j's reverse entries (kept one-way edge), -1 for a
 //           mutual edge, -2 for a dropped or rejected one.
 __global__ __launch_bounds__(kEdgeBlock) void k_union_probe(const int32_t *__restrict__ idx,
+                                                            const int32_t *__restrict__ ids, int P,
                                                             const double *__restrict__ a, int64_t n, int k,
                                                             const int64_t *__restrict__ seg, int S,
                                                             float *__restrict__ wf, int32_t *__restrict__ rs,
@@ -263,6 +284,7 @@ __global__ __launch_bounds__(kEdgeBlock) void k_union_probe(const int32_t *__res
             if (act) {
                 const int64_t e = i * m + s;
                 const int32_t j = idx[i * k + 1 + s];
+                const double x = a[e];  // loaded beside j, not after the lookup
                 bool ok = j >= 0 && j < n && j != i;
                 if (ok && seg) {
                     int64_t lo, hi;
@@ -273,18 +295,22 @@ __global__ __launch_bounds__(kEdgeBlock) void k_union_probe(const int32_t *__res
                 }
                 int32_t slot = -2;
                 if (ok) {
-                    // position of i in j's list, its m ids loaded in batches of 16
-                    const int32_t *lj = idx + (int64_t)j * k + 1;
+                    // position of i in j's list: its padded copy, 16 ids
+                    // (one 64-byte line) per load batch
+                    const int4 *lj = reinterpret_cast<const int4 *>(ids + (int64_t)j * P);
                     int sp = -1;
                     for (int t0 = 0; t0 < m && sp < 0; t0 += 16) {
-                        int32_t v[16];
+                        int4 v[4];
 #pragma unroll
-                        for (int u = 0; u < 16; ++u) v[u] = t0 + u < m ? lj[t0 + u] : -1;
+                        for (int u = 0; u < 4; ++u) v[u] = lj[t0 / 4 + u];
 #pragma unroll
-                        for (int u = 0; u < 16; ++u)
-                            if (sp < 0 && v[u] == (int32_t)i) sp = t0 + u;
+                        for (int u = 0; u < 4; ++u) {
+                            if (sp < 0 && v[u].x == (int32_t)i) sp = t0 + 4 * u;
+                            if (sp < 0 && v[u].y == (int32_t)i) sp = t0 + 4 * u + 1;
+                            if (sp < 0 && v[u].z == (int32_t)i) sp = t0 + 4 * u + 2;
+                            if (sp < 0 && v[u].w == (int32_t)i) sp = t0 + 4 * u + 3;
+                        }
                     }
-                    const double x = a[e];
                     double w = x;
                     if (sp >= 0) {
                         const double y = a[(int64_t)j * m + sp];
@@ -441,10 +467,12 @@ __global__ __launch_bounds__(kEdgeBlock) void k_rev_fill(const int32_t *__restri
             const int64_t i = i0 + r;
             if (!((mp.R > 1 ? r < mp.R : s < m) && i < n)) continue;
             const int64_t e = i * m + s;
+            // the edge's three loads are independent: issue them together
             const int32_t slot = rs[e];
-            if (slot < 0) continue;
             const int32_t j = idx[i * k + 1 + s];
-            rev[rbase[j] + slot] = make_int2((int32_t)i, __float_as_int(wf[e]));
+            const float f = wf[e];
+            if (slot < 0) continue;
+            rev[rbase[j] + slot] = make_int2((int32_t)i, __float_as_int(f));
         }
     }
 }
@@ -455,9 +483,11 @@ __device__ __forceinline__ void row_entry(const int32_t *__restrict__ idx, const
                                           const int2 *__restrict__ rev, int64_t i, int k, int m, int64_t rb,
                                           int64_t p, int32_t *col, float *val) {
     if (p < m) {
+        // both loads unconditional, so that they are in flight together
         const float f = wf[i * m + p];
+        const int32_t c = idx[i * k + 1 + p];
         *val = f;
-        *col = f != 0.f ? idx[i * k + 1 + p] : INT_MAX;
+        *col = f != 0.f ? c : INT_MAX;
     } else {
         const int2 t = rev[rb + (p - m)];
         *col = t.x;
@@ -465,8 +495,83 @@ __device__ __forceinline__ void row_entry(const int32_t *__restrict__ idx, const
     }
 }
 
-// One wave per row: rank every kept entry by column (lane broadcasts) and
-// write it to its sorted position.
+__device__ __forceinline__ int64_t lane_i64(int64_t x, int src) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(uint64_t)x, src);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)((uint64_t)x >> 32), src);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Ascending sort of (col, val) by col over segments of W lanes (W = 32: each
+// half of the wave sorts its own row; W = 64: the whole wave one row); x is
+// the lane's index within its segment.  A bitonic network: log2(W) merge
+// stages, each a compare-exchange with the lane x ^ j.
+template <int W>
+__device__ __forceinline__ void bitonic_sort(int32_t &col, float &val, int x) {
+#pragma unroll
+    for (int kk = 2; kk <= W; kk <<= 1) {
+#pragma unroll
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            const int32_t oc = __shfl_xor(col, j, kWave);
+            const float ov = __shfl_xor(val, j, kWave);
+            const bool ascending = (x & kk) == 0;
+            const bool lower = (x & j) == 0;
+            if (ascending == lower ? oc < col : oc > col) {
+                col = oc;
+                val = ov;
+            }
+        }
+    }
+}
+
+// Row i's entries sorted by column and written from out0 on; repeated
+// columns set dup.
+__device__ __forceinline__ void sort_row_wave(const int32_t *__restrict__ idx, const float *__restrict__ wf,
+                                              const int2 *__restrict__ rev, int64_t i, int k, int m, int64_t rb,
+                                              int64_t len, int64_t out0, int32_t *__restrict__ indices,
+                                              float *__restrict__ data, bool &dup) {
+    const int lane = threadIdx.x & (kWave - 1);
+    if (len <= kWave) {
+        int32_t col = INT_MAX;
+        float val = 0.f;
+        if (lane < len) row_entry(idx, wf, rev, i, k, m, rb, lane, &col, &val);
+        bitonic_sort<kWave>(col, val, lane);
+        const int32_t next = __shfl_down(col, 1, kWave);
+        if (col != INT_MAX) {
+            dup |= lane < kWave - 1 && next == col;
+            indices[out0 + lane] = col;
+            data[out0 + lane] = val;
+        }
+        return;
+    }
+    // longer rows: rank every entry by lane broadcasts of 64-entry chunks
+    for (int64_t e0 = 0; e0 < len; e0 += kWave) {
+        const int64_t e = e0 + lane;
+        int32_t col = INT_MAX;
+        float val = 0.f;
+        if (e < len) row_entry(idx, wf, rev, i, k, m, rb, e, &col, &val);
+        int64_t rank = 0;
+        for (int64_t c0 = 0; c0 < len; c0 += kWave) {
+            int32_t oc = INT_MAX;
+            float ov;
+            if (c0 + lane < len) row_entry(idx, wf, rev, i, k, m, rb, c0 + lane, &oc, &ov);
+            const int lim = (int)((len - c0) < kWave ? (len - c0) : kWave);
+            for (int t = 0; t < lim; ++t) {
+                const int32_t x = __builtin_amdgcn_readlane(oc, t);
+                rank += x < col;
+                dup |= x == col && c0 + t != e && col != INT_MAX;
+            }
+        }
+        if (col != INT_MAX) {
+            indices[out0 + rank] = col;
+            data[out0 + rank] = val;
+        }
+    }
+}
+
+// Rows in pairs, one pair per wave: when both rows have at most 32 entries
+// each half of the wave sorts one of them; otherwise the wave takes the two
+// rows one after the other.  Dropped own slots carry column INT_MAX and sort
+// behind the kept entries, which land at out0 + their sorted position.
 __global__ __launch_bounds__(256) void k_row_sort(const int32_t *__restrict__ idx, const float *__restrict__ wf,
                                                   const int2 *__restrict__ rev, const int32_t *__restrict__ rev_cnt,
                                                   const int64_t *__restrict__ rbase,
@@ -474,51 +579,44 @@ __global__ __launch_bounds__(256) void k_row_sort(const int32_t *__restrict__ id
                                                   int32_t *__restrict__ indices, float *__restrict__ data,
                                                   GraphResult *__restrict__ res) {
     const int lane = threadIdx.x & (kWave - 1);
+    const int half = lane >> 5, sub = lane & 31;
     const int m = k - 1;
     const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t waves = ((int64_t)gridDim.x * blockDim.x) / kWave;
     bool dup = false;
-    for (int64_t i = wave0; i < n; i += waves) {
-        const int64_t rb = rbase[i];
-        const int64_t len = (int64_t)m + rev_cnt[i];
-        const int64_t out0 = indptr[i];
-        if (len <= kWave) {
+    // the next pair's row figures are loaded one iteration ahead
+    int64_t len_n = 0, rb_n = 0, out_n = 0;
+    auto fetch = [&](int64_t g) {
+        const int64_t r = 2 * g + half;
+        const bool ok = 2 * g < n && r < n;
+        len_n = ok ? (int64_t)m + rev_cnt[r] : 0;
+        rb_n = ok ? rbase[r] : 0;
+        out_n = ok ? indptr[r] : 0;
+    };
+    fetch(wave0);
+    for (int64_t g = wave0; 2 * g < n; g += waves) {
+        const int64_t mine = 2 * g + half;
+        const int64_t len = len_n, rb = rb_n, out0 = out_n;
+        fetch(g + waves);
+        if (__ballot(len > 32) == 0ull) {
             int32_t col = INT_MAX;
             float val = 0.f;
-            if (lane < len) row_entry(idx, wf, rev, i, k, m, rb, lane, &col, &val);
-            int rank = 0;
-            for (int t = 0; t < (int)len; ++t) {
-                const int32_t x = __builtin_amdgcn_readlane(col, t);
-                rank += x < col;
-                dup |= x == col && t != lane && col != INT_MAX;
-            }
+            if (sub < len) row_entry(idx, wf, rev, mine, k, m, rb, sub, &col, &val);
+            bitonic_sort<32>(col, val, sub);
+            const int32_t next = __shfl_down(col, 1, 32);
             if (col != INT_MAX) {
-                indices[out0 + rank] = col;
-                data[out0 + rank] = val;
+                dup |= sub < 31 && next == col;
+                indices[out0 + sub] = col;
+                data[out0 + sub] = val;
             }
-        } else {
-            for (int64_t e0 = 0; e0 < len; e0 += kWave) {
-                const int64_t e = e0 + lane;
-                int32_t col = INT_MAX;
-                float val = 0.f;
-                if (e < len) row_entry(idx, wf, rev, i, k, m, rb, e, &col, &val);
-                int64_t rank = 0;
-                for (int64_t c0 = 0; c0 < len; c0 += kWave) {
-                    int32_t oc = INT_MAX;
-                    float ov;
-                    if (c0 + lane < len) row_entry(idx, wf, rev, i, k, m, rb, c0 + lane, &oc, &ov);
-                    const int lim = (int)((len - c0) < kWave ? (len - c0) : kWave);
-                    for (int t = 0; t < lim; ++t) {
-                        const int32_t x = __builtin_amdgcn_readlane(oc, t);
-                        rank += x < col;
-                        dup |= x == col && c0 + t != e && col != INT_MAX;
-                    }
-                }
-                if (col != INT_MAX) {
-                    indices[out0 + rank] = col;
-                    data[out0 + rank] = val;
-                }
-            }
+            continue;
+        }
+        for (int r = 0; r < 2; ++r) {
+            const int64_t i = 2 * g + r;
+            if (i >= n) break;
+            const int src = 32 * r;  // lane 0 holds row 2g's figures, lane 32 row 2g + 1's
+            const int64_t li = lane_i64(len, src), ri = lane_i64(rb, src), oi = lane_i64(out0, src);
+            sort_row_wave(idx, wf, rev, i, k, m, ri, li, oi, indices, data, dup);
         }
     }
     if (dup) atomicOr(&res->error, 2);
@@ -534,7 +632,10 @@ struct GraphWs {
     int64_t *tot;
     int64_t *seg;
     int2 *rev;
+    int32_t *ids;  // padded neighbour lists, n x pad_ids(k) (64-byte aligned)
 };
+
+int pad_ids(int k) { return ((k - 1 + 15) / 16) * 16; }
 
 size_t carve_graph(int64_t n, int k, int32_t S, void *base, GraphWs *w) {
     Carver cv(base);
@@ -551,6 +652,7 @@ size_t carve_graph(int64_t n, int k, int32_t S, void *base, GraphWs *w) {
     g.tot = cv.take<int64_t>(2 * nb);
     g.seg = S > 0 ? cv.take<int64_t>((size_t)S + 1) : nullptr;
     g.rev = cv.take<int2>(ne ? ne : 1);
+    g.ids = cv.take<int32_t>(ne ? (size_t)n * (size_t)pad_ids(k) : 1);
     if (w) *w = g;
     return cv.used;
 }
@@ -607,10 +709,13 @@ int graph_run_impl(const int32_t *idx, const float *dist, int64_t n, int k, cons
     const int64_t groups = (n + R - 1) / R;
     {
         ScopedTimer t("union_count", stream);
-        if (m > 0)
-            hipLaunchKernelGGL(k_union_probe, dim3(wave_grid(groups)), dim3(kEdgeBlock), 0, stream, idx, w.a, n, k,
-                               w.seg, S, w.wf, w.rs, w.own, w.rev_cnt, w.res);
-        else
+        if (m > 0) {
+            const int P = pad_ids(k);
+            hipLaunchKernelGGL(k_pad_ids, dim3((unsigned)std::min<int64_t>(grid_for(n * (P / 4), 256), 65536)),
+                               dim3(256), 0, stream, idx, n, k, P, reinterpret_cast<int4 *>(w.ids));
+            hipLaunchKernelGGL(k_union_probe, dim3(wave_grid(groups)), dim3(kEdgeBlock), 0, stream, idx, w.ids, P,
+                               w.a, n, k, w.seg, S, w.wf, w.rs, w.own, w.rev_cnt, w.res);
+        } else
             hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, 256)), dim3(256), 0, stream, w.own, n, 0);
         if ((st = launch_status("union_count")) != RSC_OK) return st;
     }
@@ -633,7 +738,7 @@ int graph_run_impl(const int32_t *idx, const float *dist, int64_t n, int k, cons
     }
     if (m > 0) {
         ScopedTimer t("row_sort", stream);
-        hipLaunchKernelGGL(k_row_sort, dim3(wave_grid(n)), dim3(256), 0, stream, idx, w.wf, w.rev, w.rev_cnt,
+        hipLaunchKernelGGL(k_row_sort, dim3(wave_grid((n + 1) / 2)), dim3(256), 0, stream, idx, w.wf, w.rev, w.rev_cnt,
                            w.rbase, indptr, n, k, indices, data, w.res);
         if ((st = launch_status("row_sort")) != RSC_OK) return st;
     }
