@@ -135,18 +135,74 @@ __device__ __forceinline__ void table_add(int32_t *hk, int64_t *hv, int64_t cap,
     }
 }
 
+// A wave's table of distinct keys in LDS (open addressing, kLdsSlots slots).
+// A row with more distinct keys than it can place within kLdsProbes probes
+// falls back to the global table.
+constexpr int kLdsSlots = 256;
+constexpr int kLdsProbes = 32;
+struct WaveTable {
+    int32_t key[kLdsSlots];
+    unsigned long long val[kLdsSlots];
+};
+
+// LDS writes of this wave are complete and visible to all of its lanes.
+__device__ __forceinline__ void lds_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Adds w under key c; false when no free slot was found within kLdsProbes.
+__device__ __forceinline__ bool lds_add(WaveTable *t, int32_t c, int64_t w) {
+    uint32_t s = ((uint32_t)c * 0x9E3779B1u) >> 24;  // top 8 bits: kLdsSlots = 256
+    for (int p = 0; p < kLdsProbes; ++p) {
+        const int32_t prev = atomicCAS(&t->key[s], -1, c);
+        if (prev == -1 || prev == c) {
+            atomicAdd(&t->val[s], (unsigned long long)w);
+            return true;
+        }
+        s = (s + 1) & (kLdsSlots - 1);
+    }
+    return false;
+}
+
 // The distinct keys of one wave's row and the summed weight of each.
 // key_of(e, &key, &w) gives an entry's key (< 0: skip the entry) and weight.
 // visit(valid, key, K) is called once per lane and chunk with the lane's
 // (key, K) pair; a key can reach several lanes (with the same K) but every
 // distinct key of the row reaches at least one.  b, e: the row's entry
-// range; hk, hv: the row's table of 2 (e - b) slots (used when the row is
-// longer than a wave).
+// range; lt: the wave's LDS table (or null), used for rows of more than 32
+// entries; hk, hv: the row's global table of 2 (e - b) slots, used for rows
+// longer than a wave when the LDS table is absent or too small.
 template <class KeyOf, class Visit>
-__device__ __forceinline__ void row_groups(int64_t b, int64_t e, int32_t *hk, int64_t *hv, KeyOf key_of,
-                                           Visit visit) {
+__device__ __forceinline__ void row_groups(int64_t b, int64_t e, WaveTable *lt, int32_t *hk, int64_t *hv,
+                                           KeyOf key_of, Visit visit) {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t len = e - b;
+    if (lt && len > 32) {
+        for (int j = lane; j < kLdsSlots; j += kWave) {
+            lt->key[j] = -1;
+            lt->val[j] = 0ull;
+        }
+        lds_wave_sync();
+        bool full = false;
+        for (int64_t j = b + lane; j < e; j += kWave) {
+            int32_t c;
+            int64_t w;
+            key_of(j, &c, &w);
+            if (c >= 0 && !lds_add(lt, c, w)) full = true;
+        }
+        lds_wave_sync();
+        const bool fits = __ballot(full) == 0ull;
+        if (fits) {
+            for (int s0 = 0; s0 < kLdsSlots; s0 += kWave) {
+                const int32_t c = lt->key[s0 + lane];
+                const int64_t K = c >= 0 ? (int64_t)lt->val[s0 + lane] : 0;
+                visit(c >= 0, c, K);
+            }
+        }
+        lds_wave_sync();  // read out before the wave's next row clears it
+        if (fits) return;
+    }
     if (len <= kWave) {
         int32_t c = -1;
         int64_t w = 0;
@@ -292,7 +348,8 @@ __device__ __forceinline__ void move_one(int64_t v, const int64_t *__restrict__ 
                                          const int64_t *__restrict__ gw, const int64_t *__restrict__ kdeg,
                                          const int64_t *__restrict__ tot, const int32_t *__restrict__ L,
                                          int32_t *__restrict__ Lnext, int up, double gamma, double two_m,
-                                         int32_t *__restrict__ hk, int64_t *__restrict__ hv, int &moved) {
+                                         WaveTable *lt, int32_t *__restrict__ hk, int64_t *__restrict__ hv,
+                                         int &moved) {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t b = ptr[v], e = ptr[v + 1];
     const int32_t a = L[v];
@@ -302,7 +359,7 @@ __device__ __forceinline__ void move_one(int64_t v, const int64_t *__restrict__ 
     int64_t Ka = 0;  // K(v, a), held by the lanes whose key is a
     bool has_a = false;
     row_groups(
-        b, e, hk + 2 * b, hv + 2 * b,
+        b, e, lt, hk + 2 * b, hv + 2 * b,
         [&](int64_t j, int32_t *c, int64_t *w) {
             const int32_t u = col[j];
             *c = u == (int32_t)v ? -1 : L[u];
@@ -343,6 +400,8 @@ __global__ __launch_bounds__(kBlock) void k_lv_move(const int64_t *__restrict__ 
                                                     const int32_t *__restrict__ L, int32_t *__restrict__ Lnext,
                                                     int up, double gamma, double two_m, int32_t *__restrict__ hk,
                                                     int64_t *__restrict__ hv, LeidenState *__restrict__ st) {
+    __shared__ WaveTable tabs[kBlock / kWave];
+    WaveTable *lt = &tabs[threadIdx.x / kWave];
     const int lane = threadIdx.x & (kWave - 1);
     const int half = lane >> 5, sub = lane & 31;
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
@@ -354,8 +413,9 @@ __global__ __launch_bounds__(kBlock) void k_lv_move(const int64_t *__restrict__ 
         const int len = vok ? (int)(ptr[v + 1] - b) : 0;
         const int len0 = __builtin_amdgcn_readlane(len, 0), len1 = __builtin_amdgcn_readlane(len, 32);
         if (len0 > 32 || len1 > 32) {
-            move_one(2 * g, ptr, col, gw, kdeg, tot, L, Lnext, up, gamma, two_m, hk, hv, moved);
-            if (2 * g + 1 < N) move_one(2 * g + 1, ptr, col, gw, kdeg, tot, L, Lnext, up, gamma, two_m, hk, hv, moved);
+            move_one(2 * g, ptr, col, gw, kdeg, tot, L, Lnext, up, gamma, two_m, lt, hk, hv, moved);
+            if (2 * g + 1 < N)
+                move_one(2 * g + 1, ptr, col, gw, kdeg, tot, L, Lnext, up, gamma, two_m, lt, hk, hv, moved);
             continue;
         }
         const int32_t a = vok ? L[v] : -1;
@@ -480,6 +540,8 @@ __global__ __launch_bounds__(kBlock) void k_lv_refine_propose(
     const int64_t *__restrict__ kin, const int64_t *__restrict__ totC, const int64_t *__restrict__ totR,
     const int32_t *__restrict__ size, const int64_t *__restrict__ extR, double gamma, double two_m,
     int32_t *__restrict__ prop, int32_t *__restrict__ hk, int64_t *__restrict__ hv) {
+    __shared__ WaveTable tabs[kBlock / kWave];
+    WaveTable *lt = &tabs[threadIdx.x / kWave];
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
     for (int64_t v = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; v < N; v += waves) {
@@ -496,7 +558,7 @@ __global__ __launch_bounds__(kBlock) void k_lv_refine_propose(
         int32_t best_r = -1;
         const int64_t b = ptr[v], e = ptr[v + 1];
         row_groups(
-            b, e, hk + 2 * b, hv + 2 * b,
+            b, e, lt, hk + 2 * b, hv + 2 * b,
             [&](int64_t j, int32_t *c, int64_t *w) {
                 const int32_t u = col[j];
                 *c = -1;
