@@ -58,6 +58,8 @@ struct GraphResult {
     int64_t nnz;
     int32_t error;  // bit 0: index out of range or self; bit 1: repeated neighbour; bit 2: edge leaves its sample
     int32_t degenerate;
+    int32_t long_rows;  // rows of more than 64 entries, listed for the second sort kernel
+    int32_t pad;
 };
 
 __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
@@ -75,6 +77,7 @@ __global__ void k_init_result(GraphResult *r) {
         r->nnz = 0;
         r->error = 0;
         r->degenerate = 0;
+        r->long_rows = 0;
     }
 }
 
@@ -525,6 +528,12 @@ __device__ __forceinline__ void bitonic_sort(int32_t &col, float &val, int x) {
 
 // Row i's entries sorted by column and written from out0 on; repeated
 // columns set dup.
+// Rows of up to kSortCap entries that do not fit a wave are sorted in LDS:
+// their (column, weight) pairs are staged, padded with column INT_MAX to a
+// power of two, and sorted by a bitonic network whose compare-exchanges the
+// wave's lanes share, stage by stage.
+constexpr int kSortCap = 1024;
+
 __device__ __forceinline__ void sort_row_wave(const int32_t *__restrict__ idx, const float *__restrict__ wf,
                                               const int2 *__restrict__ rev, int64_t i, int k, int m, int64_t rb,
                                               int64_t len, int64_t out0, int32_t *__restrict__ indices,
@@ -543,7 +552,7 @@ __device__ __forceinline__ void sort_row_wave(const int32_t *__restrict__ idx, c
         }
         return;
     }
-    // longer rows: rank every entry by lane broadcasts of 64-entry chunks
+    // rows longer than kSortCap: rank every entry by lane broadcasts of 64-entry chunks
     for (int64_t e0 = 0; e0 < len; e0 += kWave) {
         const int64_t e = e0 + lane;
         int32_t col = INT_MAX;
@@ -577,7 +586,7 @@ __global__ __launch_bounds__(256) void k_row_sort(const int32_t *__restrict__ id
                                                   const int64_t *__restrict__ rbase,
                                                   const int64_t *__restrict__ indptr, int64_t n, int k,
                                                   int32_t *__restrict__ indices, float *__restrict__ data,
-                                                  GraphResult *__restrict__ res) {
+                                                  int32_t *__restrict__ long_list, GraphResult *__restrict__ res) {
     const int lane = threadIdx.x & (kWave - 1);
     const int half = lane >> 5, sub = lane & 31;
     const int m = k - 1;
@@ -616,8 +625,82 @@ __global__ __launch_bounds__(256) void k_row_sort(const int32_t *__restrict__ id
             if (i >= n) break;
             const int src = 32 * r;  // lane 0 holds row 2g's figures, lane 32 row 2g + 1's
             const int64_t li = lane_i64(len, src), ri = lane_i64(rb, src), oi = lane_i64(out0, src);
+            if (li > kWave) {
+                if (lane == 0) long_list[atomicAdd(&res->long_rows, 1)] = (int32_t)i;
+                continue;
+            }
             sort_row_wave(idx, wf, rev, i, k, m, ri, li, oi, indices, data, dup);
         }
+    }
+    if (dup) atomicOr(&res->error, 2);
+}
+
+// The rows listed by k_row_sort (more than 64 entries), one wave each:
+// sorted in LDS when they hold at most kSortCap entries, else ranked by
+// lane broadcasts.
+__global__ __launch_bounds__(256) void k_row_sort_long(const int32_t *__restrict__ idx, const float *__restrict__ wf,
+                                                       const int2 *__restrict__ rev,
+                                                       const int32_t *__restrict__ rev_cnt,
+                                                       const int64_t *__restrict__ rbase,
+                                                       const int64_t *__restrict__ indptr, int k,
+                                                       const int32_t *__restrict__ long_list,
+                                                       int32_t *__restrict__ indices, float *__restrict__ data,
+                                                       GraphResult *__restrict__ res) {
+    __shared__ int32_t stage_col[256 / kWave][kSortCap];
+    __shared__ float stage_val[256 / kWave][kSortCap];
+    int32_t *lds_col = stage_col[threadIdx.x / kWave];
+    float *lds_val = stage_val[threadIdx.x / kWave];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int m = k - 1;
+    const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    const int64_t count = res->long_rows;
+    bool dup = false;
+    for (int64_t t0 = wave0; t0 < count; t0 += waves) {
+        const int64_t i = long_list[t0];
+        const int64_t len = (int64_t)m + rev_cnt[i], rb = rbase[i], out0 = indptr[i];
+        if (len <= kSortCap) {
+            const int n_ = (int)len;
+            int P2 = 2 * kWave;
+            while (P2 < n_) P2 <<= 1;
+            for (int e = lane; e < P2; e += kWave) {
+                int32_t c = INT_MAX;
+                float v = 0.f;
+                if (e < n_) row_entry(idx, wf, rev, i, k, m, rb, e, &c, &v);
+                lds_col[e] = c;
+                lds_val[e] = v;
+            }
+            for (int kk = 2; kk <= P2; kk <<= 1) {
+                for (int j = kk >> 1; j > 0; j >>= 1) {
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+                    __builtin_amdgcn_wave_barrier();
+                    for (int t = lane; t < P2 / 2; t += kWave) {
+                        const int i0 = ((t & ~(j - 1)) << 1) | (t & (j - 1)), i1 = i0 + j;
+                        const int32_t c0 = lds_col[i0], c1 = lds_col[i1];
+                        if ((i0 & kk) == 0 ? c0 > c1 : c0 < c1) {
+                            const float v0 = lds_val[i0], v1 = lds_val[i1];
+                            lds_col[i0] = c1;
+                            lds_col[i1] = c0;
+                            lds_val[i0] = v1;
+                            lds_val[i1] = v0;
+                        }
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            for (int e = lane; e < n_; e += kWave) {
+                const int32_t c = lds_col[e];
+                if (c == INT_MAX) continue;
+                dup |= e + 1 < n_ && lds_col[e + 1] == c;
+                indices[out0 + e] = c;
+                data[out0 + e] = lds_val[e];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // read out before the wave's next row
+            __builtin_amdgcn_wave_barrier();
+            continue;
+        }
+        sort_row_wave(idx, wf, rev, i, k, m, rb, len, out0, indices, data, dup);
     }
     if (dup) atomicOr(&res->error, 2);
 }
@@ -738,8 +821,11 @@ int graph_run_impl(const int32_t *idx, const float *dist, int64_t n, int k, cons
     }
     if (m > 0) {
         ScopedTimer t("row_sort", stream);
+        // own (the kept counts) is spent once the scan has run: it holds the long-row list
         hipLaunchKernelGGL(k_row_sort, dim3(wave_grid((n + 1) / 2)), dim3(256), 0, stream, idx, w.wf, w.rev, w.rev_cnt,
-                           w.rbase, indptr, n, k, indices, data, w.res);
+                           w.rbase, indptr, n, k, indices, data, w.own, w.res);
+        hipLaunchKernelGGL(k_row_sort_long, dim3((unsigned)std::min<int64_t>(1024, (n + 255) / 256)), dim3(256), 0,
+                           stream, idx, w.wf, w.rev, w.rev_cnt, w.rbase, indptr, k, w.own, indices, data, w.res);
         if ((st = launch_status("row_sort")) != RSC_OK) return st;
     }
     GraphResult host;

@@ -79,7 +79,8 @@ def test_on_oracle_knn_10k(rsc, oracle_mod):
 
 
 @pytest.mark.parametrize("n,k,hub", [(50, 2, 0.1), (333, 3, 0.05), (1000, 15, 0.01), (3000, 32, 0.02),
-                                      (700, 63, 0.05), (20, 1, 0.1)])
+                                      (700, 63, 0.05), (20, 1, 0.1),
+                                      (3000, 63, 0.003)])  # 9 rows of more than 512 entries, up to 1414
 def test_synthetic_lists(rsc, oracle_mod, n, k, hub):
     idx, dist = synth.random_knn_lists(n, k, seed=n + k, hub_fraction=hub)
     check_conn_on_lists(rsc, oracle_mod, idx, dist, f"synthetic lists hub={hub}")
