@@ -20,9 +20,11 @@ namespace {
 thread_local std::string g_error;
 
 struct ProfileEntry {
-    const char *name;
+    std::string name;
     hipEvent_t start, stop;
 };
+
+thread_local const char *g_timer_prefix = nullptr;
 
 struct Profiler {
     std::mutex mu;
@@ -74,7 +76,12 @@ int hip_status(hipError_t e, const char *what) {
 
 int launch_status(const char *what) { return hip_status(hipGetLastError(), what); }
 
-ScopedTimer::ScopedTimer(const char *name, hipStream_t stream) : name_(name), stream_(stream), start_(nullptr) {
+TimerPrefix::TimerPrefix(const char *prefix) : prev_(g_timer_prefix) { g_timer_prefix = prefix; }
+TimerPrefix::~TimerPrefix() { g_timer_prefix = prev_; }
+
+ScopedTimer::ScopedTimer(const char *name, hipStream_t stream)
+    : name_(g_timer_prefix ? std::string(g_timer_prefix) + name : std::string(name)), stream_(stream),
+      start_(nullptr) {
     Profiler &p = profiler();
     std::lock_guard<std::mutex> lock(p.mu);
     if (!p.enabled) return;

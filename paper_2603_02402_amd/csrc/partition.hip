@@ -302,6 +302,7 @@ int assign_pass(const float *X, int64_t n, int d, const float *C, int P, int32_t
     KnnPlan kp;
     int st = knn_plan(n, P, d, 1, nullptr, false, &kp);
     if (st != RSC_OK) return st;
+    TimerPrefix tp("kmeans/");  // the assignment's own screen and rerank
     return knn_run(kp, X, C, assign, b.dist, b.knn_ws, s);
 }
 

@@ -31,9 +31,24 @@ class ScopedTimer {
     ScopedTimer &operator=(const ScopedTimer &) = delete;
 
   private:
-    const char *name_;
+    std::string name_;
     hipStream_t stream_;
     void *start_;
+};
+
+// While a TimerPrefix lives, the timers this thread starts file their pairs
+// under prefix + name (a stage that runs a whole kNN call inside another
+// call, such as k-means' assignments, keeps its kernels apart from the
+// outer call's own).
+class TimerPrefix {
+  public:
+    explicit TimerPrefix(const char *prefix);
+    ~TimerPrefix();
+    TimerPrefix(const TimerPrefix &) = delete;
+    TimerPrefix &operator=(const TimerPrefix &) = delete;
+
+  private:
+    const char *prev_;
 };
 
 constexpr size_t kAlign = 256;
