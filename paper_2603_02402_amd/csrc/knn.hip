@@ -181,6 +181,10 @@ __global__ __launch_bounds__(256) void k_pack(const float *__restrict__ R, const
     }
 }
 
+__global__ void k_set_i32(int32_t *p, int32_t v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
 __global__ void k_init_counters(KnnCounters *c) {
     if (threadIdx.x == 0) {
         c->flagged = 0;
@@ -823,6 +827,7 @@ size_t knn_workspace(const KnnPlan &p, void *ws, KnnBuffers *out) {
         b.pblk = cv.take<int64_t>((size_t)p.resid + 1);
         b.blk_part = cv.take<int32_t>((size_t)p.nblk * 4);
         b.map = cv.take<int32_t>((size_t)p.nblk * 32);
+        b.qcount = cv.take<int32_t>(1);
         b.kws_bytes = kmeans_workspace_bytes(p.nr, p.d, p.resid);
         b.kws = cv.take<char>(b.kws_bytes ? b.kws_bytes : 1);
     }
@@ -863,9 +868,20 @@ int knn_run_lowp(const KnnPlan &p, const float *Q, const float *R, int32_t *out_
         st = lowp_prepare(p, Qs, Rs, b.packed, b.norms, b.scal, b.amax, stream);
     if (st != RSC_OK) return st;
     if (p.nq == 0) return RSC_OK;
+    // Residual variant on one matrix: the queries are screened in partition
+    // order, so the 32 queries of a wave meet their own partition's blocks
+    // together and share the selection's queue flushes there.
+    const bool by_part = p.resid > 0 && p.self_mode;
+    if (by_part) {
+        hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(64), 0, stream, b.qcount, (int32_t)p.nq);
+        if ((st = launch_status("set query count")) != RSC_OK) return st;
+    }
     ScreenArgs sa{};
     sa.Q = Qs;
     sa.nq = p.nq;
+    sa.qlist = by_part ? b.perm : nullptr;
+    sa.qcount = by_part ? b.qcount : nullptr;
+    sa.qcap = (int)p.nq;
     sa.Ap = b.packed;
     sa.Np = b.norms;
     sa.qscale = b.scal;
@@ -882,6 +898,9 @@ int knn_run_lowp(const KnnPlan &p, const float *Q, const float *R, int32_t *out_
     RerankArgs ra{};
     ra.Q = Q;
     ra.nq = p.nq;
+    ra.qlist = sa.qlist;
+    ra.qcount = sa.qcount;
+    ra.qcap = sa.qcap;
     ra.R = R;
     ra.d = p.d;
     ra.k = p.k;

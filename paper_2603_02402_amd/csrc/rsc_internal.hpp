@@ -105,6 +105,7 @@ struct KnnBuffers {
     // FP8 residual variant
     float *cent;          // partition centroids, resid x d
     int32_t *assign, *perm, *init, *map;
+    int32_t *qcount;  // residual variant: the number of queries screened in partition order (device)
     int32_t *blk_part;    // partition of each packed block, 4 copies per block
     int64_t *poff, *pblk;
     void *kws;            // k-means workspace
