@@ -818,6 +818,12 @@ size_t knn_workspace(const KnnPlan &p, void *ws, KnnBuffers *out) {
         b.rn = cv.take<float>((size_t)p.nr * p.d);
         b.qn = p.self_mode ? b.rn : cv.take<float>((size_t)std::max<int64_t>(p.nq, 1) * p.d);
     }
+    if (!fp32 && p.resid == 0 && p.nq > 0) {
+        // spatial order of the queries (perm) and its sort
+        b.perm = cv.take<int32_t>((size_t)p.nq);
+        b.qcount = cv.take<int32_t>(1);
+        b.order_ws = cv.take<char>(query_order_workspace(p.nq));
+    }
     if (p.resid > 0) {
         b.cent = cv.take<float>((size_t)p.resid * p.d);
         b.assign = cv.take<int32_t>((size_t)p.nr);
@@ -868,19 +874,27 @@ int knn_run_lowp(const KnnPlan &p, const float *Q, const float *R, int32_t *out_
         st = lowp_prepare(p, Qs, Rs, b.packed, b.norms, b.scal, b.amax, stream);
     if (st != RSC_OK) return st;
     if (p.nq == 0) return RSC_OK;
-    // Residual variant on one matrix: the queries are screened in partition
-    // order, so the 32 queries of a wave meet their own partition's blocks
-    // together and share the selection's queue flushes there.
-    const bool by_part = p.resid > 0 && p.self_mode;
-    if (by_part) {
+    // The queries are screened in an order that keeps neighbours together,
+    // so that the 32 queries of a wave tend to take keys from the same
+    // blocks and share the selection's queue flushes: the residual variant
+    // on one matrix uses its partition order, the other forms a Morton order
+    // of the first coordinates (query_order.hip).
+    bool ordered = false;
+    if (p.resid > 0) {
+        ordered = p.self_mode;
+    } else if (b.order_ws) {
+        if ((st = query_order_run(Qs, p.nq, p.d, b.order_ws, b.perm, stream)) != RSC_OK) return st;
+        ordered = true;
+    }
+    if (ordered) {
         hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(64), 0, stream, b.qcount, (int32_t)p.nq);
         if ((st = launch_status("set query count")) != RSC_OK) return st;
     }
     ScreenArgs sa{};
     sa.Q = Qs;
     sa.nq = p.nq;
-    sa.qlist = by_part ? b.perm : nullptr;
-    sa.qcount = by_part ? b.qcount : nullptr;
+    sa.qlist = ordered ? b.perm : nullptr;
+    sa.qcount = ordered ? b.qcount : nullptr;
     sa.qcap = (int)p.nq;
     sa.Ap = b.packed;
     sa.Np = b.norms;

@@ -105,7 +105,8 @@ struct KnnBuffers {
     // FP8 residual variant
     float *cent;          // partition centroids, resid x d
     int32_t *assign, *perm, *init, *map;
-    int32_t *qcount;  // residual variant: the number of queries screened in partition order (device)
+    int32_t *qcount;  // the number of queries screened through perm (device)
+    void *order_ws;   // reduced-precision screens: workspace of the spatial query order
     int32_t *blk_part;    // partition of each packed block, 4 copies per block
     int64_t *poff, *pblk;
     void *kws;            // k-means workspace
@@ -183,6 +184,11 @@ int lowp_screen(const KnnPlan &p, const scr::ScreenArgs &a, unsigned gx, hipStre
 // the screen, the candidates' packed rows turned back into row ids.
 int lowp_prepare_resid(const KnnPlan &p, const float *R, const KnnBuffers &b, hipStream_t stream);
 int lowp_unmap(const KnnPlan &p, const KnnBuffers &b, hipStream_t stream);
+
+// Spatial order of query rows (query_order.hip): perm = the rows sorted by a
+// Morton code of their first three coordinates.
+size_t query_order_workspace(int64_t nq);
+int query_order_run(const float *Q, int64_t nq, int d, void *ws, int32_t *perm, hipStream_t s);
 
 // Batched form (knn_batched.hip).
 size_t batched_workspace_bytes(const int64_t *offsets, int S, int d, int k);
