@@ -90,6 +90,51 @@ __global__ __launch_bounds__(256) void k_row_d2(const float *__restrict__ X, int
         d2[r] = exact_d2(X + r * d, C + (int64_t)assign[r] * d, d);
 }
 
+// Exact nearest centroid of every row by brute force, for d <= 64: the row
+// sits in registers as float64 (zero-padded to DMAX dimensions, which adds
+// exact zeros to every sum), the centroids pass through LDS in tiles of
+// kAssignTile rows, and every distance is exact_d2's (differences, squares
+// and sums rounded as written, in dimension order); ties go to the lowest
+// centroid index.  So the assignment is the exact k = 1 search's, at
+// 3 DMAX P float64 operations per row.
+constexpr int kAssignTile = 64;
+
+template <int DMAX>
+__global__ __launch_bounds__(256) void k_assign_exact(const float *__restrict__ X, int64_t n, int d,
+                                                      const float *__restrict__ C, int P,
+                                                      int32_t *__restrict__ assign) {
+    __shared__ double ct[kAssignTile * DMAX];
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double x[DMAX];
+#pragma unroll
+    for (int t = 0; t < DMAX; ++t) x[t] = (r < n && t < d) ? (double)X[r * d + t] : 0.0;
+    double best = INFINITY;
+    int32_t bj = 0;
+    for (int j0 = 0; j0 < P; j0 += kAssignTile) {
+        const int nt = P - j0 < kAssignTile ? P - j0 : kAssignTile;
+        __syncthreads();  // the previous tile is no longer read
+        for (int e = threadIdx.x; e < kAssignTile * DMAX; e += blockDim.x) {
+            const int jj = e / DMAX, t = e - jj * DMAX;
+            ct[e] = (jj < nt && t < d) ? (double)C[(int64_t)(j0 + jj) * d + t] : 0.0;
+        }
+        __syncthreads();
+        for (int jj = 0; jj < nt; ++jj) {
+            const double *c = ct + jj * DMAX;  // the same address on every lane: broadcast reads
+            double s = 0.0;
+#pragma unroll
+            for (int t = 0; t < DMAX; ++t) {
+                const double diff = __dsub_rn(x[t], c[t]);
+                s = __dadd_rn(s, __dmul_rn(diff, diff));
+            }
+            if (s < best) {
+                best = s;
+                bj = j0 + jj;
+            }
+        }
+    }
+    if (r < n) assign[r] = bj;
+}
+
 // (d2 desc, index asc): whether (da, ia) comes first.
 __device__ __forceinline__ bool farther(double da, int64_t ia, double db, int64_t ib) {
     return da > db || (da == db && ia < ib);
@@ -299,6 +344,21 @@ size_t carve_kmeans(int64_t n, int d, int P, void *ws, KmeansBuffers *out) {
 
 int assign_pass(const float *X, int64_t n, int d, const float *C, int P, int32_t *assign, const KmeansBuffers &b,
                 hipStream_t s) {
+    if (d <= 64) {
+        ScopedTimer t("kmeans_assign", s);
+        const unsigned g = (unsigned)((n + 255) / 256);
+        switch ((d + 7) / 8) {
+            case 1: hipLaunchKernelGGL(k_assign_exact<8>, dim3(g), dim3(256), 0, s, X, n, d, C, P, assign); break;
+            case 2: hipLaunchKernelGGL(k_assign_exact<16>, dim3(g), dim3(256), 0, s, X, n, d, C, P, assign); break;
+            case 3: hipLaunchKernelGGL(k_assign_exact<24>, dim3(g), dim3(256), 0, s, X, n, d, C, P, assign); break;
+            case 4: hipLaunchKernelGGL(k_assign_exact<32>, dim3(g), dim3(256), 0, s, X, n, d, C, P, assign); break;
+            case 5: hipLaunchKernelGGL(k_assign_exact<40>, dim3(g), dim3(256), 0, s, X, n, d, C, P, assign); break;
+            case 6: hipLaunchKernelGGL(k_assign_exact<48>, dim3(g), dim3(256), 0, s, X, n, d, C, P, assign); break;
+            case 7: hipLaunchKernelGGL(k_assign_exact<56>, dim3(g), dim3(256), 0, s, X, n, d, C, P, assign); break;
+            default: hipLaunchKernelGGL(k_assign_exact<64>, dim3(g), dim3(256), 0, s, X, n, d, C, P, assign); break;
+        }
+        return launch_status("kmeans assignment");
+    }
     KnnPlan kp;
     int st = knn_plan(n, P, d, 1, nullptr, false, &kp);
     if (st != RSC_OK) return st;
