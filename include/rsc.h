@@ -736,8 +736,8 @@ int rsc_profile_reset(void);
 /* Total milliseconds and launch count recorded for the kernel `name`
  * (host string, e.g. "screen_fp32").  The k-means assignments that run
  * inside a call (rsc_partition_kmeans, the routed index, the FP8 residual
- * form's partitioning) are filed as "kmeans_assign" (d <= 64: brute force)
- * or, for wider rows, under "kmeans/" + the kNN stage's name
+ * form's partitioning) are filed as "kmeans_assign" (brute force, for
+ * d <= 64 and at most 2048 parts) or else under "kmeans/" + the kNN stage's name
  * ("kmeans/screen_fp32", "kmeans/rerank").  Waits for the recorded
  * events. */
 int rsc_profile_get(const char *name, double *total_ms, int64_t *launches);

@@ -48,11 +48,14 @@ def host(t):
 # Partitions
 # ---------------------------------------------------------------------------
 
-def test_kmeans_matches_oracle(rsc, oracle_mod):
+@pytest.mark.parametrize("n,d,P", [(20000, 50, 64),    # brute-force assignment (d <= 64, P <= 2048)
+                                   (4000, 80, 16),      # the exact k = 1 search (d > 64)
+                                   (12000, 20, 2100)])  # the exact k = 1 search (P > 2048)
+def test_kmeans_matches_oracle(rsc, oracle_mod, n, d, P):
     from oracle import partition
 
-    X = synth.mixture(20000, n_clusters=30, law="zipf", seed=21)
-    P, iters = 64, 6
+    X = synth.mixture(n, d=d, n_clusters=30, law="zipf", seed=21)
+    iters = 6
     init = synth.init_rows(X.shape[0], P, seed=22)
     log(f"[kmeans] n={X.shape[0]} P={P} iters={iters}")
     C_g, a_g, off_g, perm_g, rel_g = rsc.partition_kmeans(dev(X), P, dev(init), iters)
