@@ -93,6 +93,16 @@ def test_random_lists_with_hubs(rsc, oracle_mod):
     check(rsc, p, x, d, "random kNN lists with hubs")
 
 
+def test_hub_rows_beyond_the_lds_table(rsc, oracle_mod):
+    """Hub rows of up to 830 entries: at the first level every neighbour is
+    its own community, more distinct communities than a wave's LDS table
+    holds (256 slots), so those rows take the global table."""
+    idx, dist = synth.random_knn_lists(4000, 15, seed=64, hub_fraction=0.004)
+    p, x, d, _, _ = oracle_mod.connectivities(idx, dist)
+    assert (np.diff(p) > 256).sum() >= 10
+    check(rsc, p, x, d, "hub rows beyond the LDS table")
+
+
 def test_cliques_and_edge_cases(rsc, oracle_mod):
     # two 8-cliques joined by one edge
     n = 16
