@@ -868,24 +868,31 @@ int knn_run_lowp(const KnnPlan &p, const float *Q, const float *R, int32_t *out_
     const bool cosine = p.metric == RSC_COSINE;
     if (cosine && (st = normalize_inputs(p, Q, R, b, stream)) != RSC_OK) return st;
     const float *Qs = cosine ? b.qn : Q, *Rs = cosine ? b.rn : R;  // what the screen sees
-    if (p.resid > 0)
-        st = lowp_prepare_resid(p, R, b, stream);
-    else
-        st = lowp_prepare(p, Qs, Rs, b.packed, b.norms, b.scal, b.amax, stream);
-    if (st != RSC_OK) return st;
-    if (p.nq == 0) return RSC_OK;
     // The queries are screened in an order that keeps neighbours together,
     // so that the 32 queries of a wave tend to take keys from the same
     // blocks and share the selection's queue flushes: the residual variant
     // on one matrix uses its partition order, the other forms a Morton order
-    // of the first coordinates (query_order.hip).
-    bool ordered = false;
-    if (p.resid > 0) {
-        ordered = p.self_mode;
-    } else if (b.order_ws) {
+    // of the first coordinates (query_order.hip).  On one matrix screened as
+    // a single reference range the latter also packs the references in that
+    // order, and every query group starts its scan at its own rows: the
+    // nearest references come first and tighten the thresholds before the
+    // rest streams past.  (With several ranges, references packed in that
+    // order would put a query's near rows into one range, whose 64
+    // candidates are then all it keeps of them: fewer true neighbours
+    // survive the noisier FP8 keys.)
+    bool ordered = false, rotate = false;
+    if (p.resid == 0 && b.order_ws && p.nq > 0) {
         if ((st = query_order_run(Qs, p.nq, p.d, b.order_ws, b.perm, stream)) != RSC_OK) return st;
         ordered = true;
+        rotate = p.self_mode && p.splits == 1;
     }
+    if (p.resid > 0)
+        st = lowp_prepare_resid(p, R, b, stream);
+    else
+        st = lowp_prepare(p, Qs, Rs, b.packed, b.norms, b.scal, b.amax, rotate ? b.perm : nullptr, stream);
+    if (st != RSC_OK) return st;
+    if (p.nq == 0) return RSC_OK;
+    if (p.resid > 0) ordered = p.self_mode;
     if (ordered) {
         hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(64), 0, stream, b.qcount, (int32_t)p.nq);
         if ((st = launch_status("set query count")) != RSC_OK) return st;
@@ -904,11 +911,13 @@ int knn_run_lowp(const KnnPlan &p, const float *Q, const float *R, int32_t *out_
     sa.nblk = p.nblk;
     sa.d = p.d;
     sa.P = p.splits;
+    sa.rotate = rotate ? 1 : 0;
     sa.cand_idx = b.cand_idx;
     sa.cand_key = b.cand_key;
     const int qg = lowp_queries_per_group(p.precision, p.d);
     if ((st = lowp_screen(p, sa, (unsigned)((p.nq + qg - 1) / qg), stream)) != RSC_OK) return st;
     if (p.resid > 0 && (st = lowp_unmap(p, b, stream)) != RSC_OK) return st;
+    if (rotate && (st = lowp_unmap_rows(p, b, b.perm, stream)) != RSC_OK) return st;
     RerankArgs ra{};
     ra.Q = Q;
     ra.nq = p.nq;

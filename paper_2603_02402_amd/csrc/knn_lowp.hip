@@ -92,7 +92,8 @@ __device__ inline float e4m3_value(uint32_t code) {
 // row: 0, and +inf as the norm's high part.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_pack_bf16(const float *__restrict__ R, int64_t nr, int d, int KS,
-                                                   int64_t nblk, i32x4 *__restrict__ Ap) {
+                                                   int64_t nblk, const int32_t *__restrict__ rmap,
+                                                   i32x4 *__restrict__ Ap) {
     const int64_t total = nblk * KS * kWave;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
@@ -100,12 +101,13 @@ __global__ __launch_bounds__(256) void k_pack_bf16(const float *__restrict__ R, 
         const int64_t bs = e / kWave;
         const int s = (int)(bs % KS);
         const int64_t b = bs / KS;
-        const int64_t row = 32 * b + (lane & 31);
+        const int64_t slot = 32 * b + (lane & 31);
+        const int64_t row = slot < nr && rmap ? (int64_t)rmap[slot] : slot;  // packed slot -> row
         const int h = lane >> 5;
         const int k0 = 16 * s + 8 * h;
         float nhi = 0.f, nlo = 0.f;
         if (k0 <= d + 1 && k0 + 8 > d) {  // this group holds a norm slot
-            if (row < nr) {
+            if (slot < nr) {
                 double n = 0.0;
                 for (int t = 0; t < d; ++t) {
                     const double v = bf16_value(bf16_bits(R[row * d + t]));
@@ -127,7 +129,7 @@ __global__ __launch_bounds__(256) void k_pack_bf16(const float *__restrict__ R, 
                 const int kk = k0 + 2 * p + q;
                 float v = 0.f;
                 if (kk < d) {
-                    if (row < nr) v = R[row * d + kk];
+                    if (slot < nr) v = R[row * d + kk];
                 } else if (kk == d) {
                     v = nhi;
                 } else if (kk == d + 1) {
@@ -189,7 +191,8 @@ __global__ void k_fp8_scales(const uint32_t *__restrict__ amax_r, const uint32_t
 // G ||s . q(y/s)||^2 in accumulator order (+inf past the last row).
 __global__ __launch_bounds__(256) void k_pack_fp8(const float *__restrict__ R, int64_t nr, int d, int KS,
                                                   int64_t nblk, const float *__restrict__ scal,
-                                                  i32x4 *__restrict__ Ap, float *__restrict__ Np) {
+                                                  const int32_t *__restrict__ rmap, i32x4 *__restrict__ Ap,
+                                                  float *__restrict__ Np) {
     const int64_t total = nblk * KS * kWave;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
@@ -197,7 +200,8 @@ __global__ __launch_bounds__(256) void k_pack_fp8(const float *__restrict__ R, i
         const int64_t bs = e / kWave;
         const int s = (int)(bs % KS);
         const int64_t b = bs / KS;
-        const int64_t row = 32 * b + (lane & 31);
+        const int64_t slot = 32 * b + (lane & 31);
+        const int64_t row = slot < nr && rmap ? (int64_t)rmap[slot] : slot;  // packed slot -> row
         const int h = lane >> 5;
         const int k0 = 64 * s + 32 * h;
         i32x8 w;
@@ -208,7 +212,7 @@ __global__ __launch_bounds__(256) void k_pack_fp8(const float *__restrict__ R, i
             for (int q = 0; q < 4; ++q) {
                 const int kk = k0 + 4 * p + q;
                 uint32_t code = 0;
-                if (kk < d && row < nr) code = e4m3_code(R[row * d + kk] / scal[kk]);
+                if (kk < d && slot < nr) code = e4m3_code(R[row * d + kk] / scal[kk]);
                 four |= code << (8 * q);
             }
             w[p] = (int)four;
@@ -218,7 +222,7 @@ __global__ __launch_bounds__(256) void k_pack_fp8(const float *__restrict__ R, i
         Ap[2 * bs * kWave + kWave + lane] = i32x4{w[4], w[5], w[6], w[7]};
         if (s == 0 && h == 0) {
             float out = INFINITY;
-            if (row < nr) {
+            if (slot < nr) {
                 double n = 0.0;
                 for (int t = 0; t < d; ++t) {
                     const double v = (double)e4m3_value(e4m3_code(R[row * d + t] / scal[t])) * scal[t];
@@ -432,6 +436,17 @@ __device__ __noinline__ ResidCodes<KS> resid_query_codes(const float *__restrict
     return out;
 }
 
+// Candidate lists hold packed slots: turn them into row ids through the
+// packing's row map (slots past the rows, never entered, and -1 stay).
+__global__ __launch_bounds__(256) void k_rows_unmap(int32_t *__restrict__ cand, int64_t count,
+                                                    const int32_t *__restrict__ rmap, int64_t nr) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = cand[i];
+        if (v >= 0 && v < nr) cand[i] = rmap[v];
+    }
+}
+
 // Candidate lists hold packed rows: turn them into row ids (-1 stays).
 __global__ __launch_bounds__(256) void k_resid_unmap(int32_t *__restrict__ cand, int64_t count,
                                                      const int32_t *__restrict__ map) {
@@ -512,21 +527,31 @@ __global__ __launch_bounds__(256, 3) void k_screen_lowp(ScreenArgs a) {
     const int64_t blk1 = std::min<int64_t>(a.nblk, blk0 + blk_per);
     const int64_t nslots = screen_slots(a);
     const char *Ab = static_cast<const char *>(a.Ap);
+    const int64_t span = blk1 - blk0;  // blocks of this range
+    int64_t rot = 0;                   // the query group's first block, relative to blk0
+
+    // Block of logical position j (0 <= j < span) of this range's scan:
+    // blk0 + (rot + j) mod span.
+    auto phys = [&](int64_t j) -> int64_t {
+        int64_t q = rot + j;
+        if (q >= span) q -= span;
+        return blk0 + q;
+    };
 
     // Issue this wave's share of the loads of phase `ph` into ring buffer `buf`.
     auto issue = [&](int64_t ph, char *buf) {
-        const int64_t b0 = blk0 + ph * PH;
+        const int64_t b0 = ph * PH;
         constexpr int NA = PH * Ring::kLoads;
 #pragma unroll
         for (int j = wave; j < NA; j += kScreenWaves) {
             const int pb = j / Ring::kLoads, q = j % Ring::kLoads;
-            const int64_t blk = std::min<int64_t>(b0 + pb, blk1 - 1);  // clamp: always in bounds
+            const int64_t blk = phys(std::min<int64_t>(b0 + pb, span - 1));  // clamp: always in bounds
             lds_load16(Ab + blk * Ring::kBlockBytes + q * 1024 + lane * 16, buf + pb * SLOT + q * 1024);
         }
         if constexpr (kNormInAcc) {
 #pragma unroll
             for (int pb = wave; pb < PH; pb += kScreenWaves) {
-                const int64_t blk = std::min<int64_t>(b0 + pb, blk1 - 1);
+                const int64_t blk = phys(std::min<int64_t>(b0 + pb, span - 1));
                 // lanes 0..7: the 32 norms; lane 8 (residual variant): the
                 // block's partition, landing right after them
                 if constexpr (RESID) {
@@ -542,6 +567,13 @@ __global__ __launch_bounds__(256, 3) void k_screen_lowp(ScreenArgs a) {
     };
 
     for (int64_t qblk = blockIdx.x; qblk * QG < nslots; qblk += gridDim.x) {
+        if (a.rotate && span > 0) {
+            // references packed in the queries' order: the group's own rows
+            // sit at packed slots qblk QG ..; start there (near references
+            // first fill the lists and tighten the thresholds early)
+            const int64_t own = qblk * QG / 32;
+            rot = own < blk0 ? 0 : (own >= blk1 ? span - 1 : own - blk0);
+        }
         int64_t slot[QB];
         int64_t qrow[QB];
         T bq[QB][KS];
@@ -607,7 +639,7 @@ __global__ __launch_bounds__(256, 3) void k_screen_lowp(ScreenArgs a) {
             }
         };
 
-        const int64_t nph = (blk1 - blk0 + PH - 1) / PH;
+        const int64_t nph = (span + PH - 1) / PH;
         // One phase: wait until its blocks have landed in `cur`, start the
         // next phase's loads into `nxt`, then screen the blocks of `cur`.
         auto phase = [&](int64_t ph, const char *cur, char *nxt) {
@@ -616,8 +648,8 @@ __global__ __launch_bounds__(256, 3) void k_screen_lowp(ScreenArgs a) {
             if (ph + 1 < nph) issue(ph + 1, nxt);
 #pragma unroll
             for (int r = 0; r < PH; ++r) {
-                const int64_t blk = blk0 + ph * PH + r;
-                if (blk >= blk1) break;
+                if (ph * PH + r >= span) break;
+                const int64_t blk = phys(ph * PH + r);
                 const char *sl = cur + r * SLOT;
                 if constexpr (RESID) {
                     const int part = *reinterpret_cast<const int *>(sl + Ring::kBlockBytes + Ring::kNormBytes);
@@ -710,13 +742,13 @@ size_t lowp_packed_bytes(int precision, int64_t nblk, int d) {
 }
 
 int lowp_prepare(const KnnPlan &p, const float *Q, const float *R, void *packed, float *norms, float *scal,
-                 uint32_t *amax, hipStream_t stream) {
+                 uint32_t *amax, const int32_t *rmap, hipStream_t stream) {
     const int ks = lowp_steps(p.precision, p.d);
     const int64_t tot = p.nblk * ks * kWave;
     const unsigned g1 = (unsigned)std::min<int64_t>((tot + 255) / 256, 65536);
     ScopedTimer timer("prep_pack", stream);
     if (p.precision == RSC_BF16) {
-        hipLaunchKernelGGL(k_pack_bf16, dim3(g1), dim3(256), 0, stream, R, p.nr, p.d, ks, p.nblk,
+        hipLaunchKernelGGL(k_pack_bf16, dim3(g1), dim3(256), 0, stream, R, p.nr, p.d, ks, p.nblk, rmap,
                            static_cast<i32x4 *>(packed));
         return launch_status("pack_bf16");
     }
@@ -732,7 +764,7 @@ int lowp_prepare(const KnnPlan &p, const float *Q, const float *R, void *packed,
         amax_q = amax_r;
     }
     hipLaunchKernelGGL(k_fp8_scales, dim3(1), dim3(64), 0, stream, amax_r, amax_q, p.d, scal);
-    hipLaunchKernelGGL(k_pack_fp8, dim3(g1), dim3(256), 0, stream, R, p.nr, p.d, ks, p.nblk, scal,
+    hipLaunchKernelGGL(k_pack_fp8, dim3(g1), dim3(256), 0, stream, R, p.nr, p.d, ks, p.nblk, scal, rmap,
                        static_cast<i32x4 *>(packed), norms);
     return launch_status("pack_fp8");
 }
@@ -766,6 +798,13 @@ int lowp_prepare_resid(const KnnPlan &p, const float *R, const KnnBuffers &b, hi
     hipLaunchKernelGGL(k_pack_fp8_resid, dim3(g1), dim3(256), 0, stream, R, p.d, ks, p.nblk, b.scal, b.map,
                        b.blk_part, b.cent, static_cast<i32x4 *>((void *)b.packed), b.norms);
     return launch_status("pack_fp8_resid");
+}
+
+int lowp_unmap_rows(const KnnPlan &p, const KnnBuffers &b, const int32_t *rmap, hipStream_t stream) {
+    const int64_t count = p.nq * p.splits * p.screen;
+    const unsigned g = (unsigned)std::min<int64_t>((count + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_rows_unmap, dim3(g), dim3(256), 0, stream, b.cand_idx, count, rmap, p.nr);
+    return launch_status("rows_unmap");
 }
 
 int lowp_unmap(const KnnPlan &p, const KnnBuffers &b, hipStream_t stream) {

@@ -176,14 +176,17 @@ int lowp_steps(int precision, int d);
 int lowp_qb(int precision, int d);
 int lowp_queries_per_group(int precision, int d);
 size_t lowp_packed_bytes(int precision, int64_t nblk, int d);
+// Packs the references (rmap: packed slot -> row, or null for row order).
 int lowp_prepare(const KnnPlan &p, const float *Q, const float *R, void *packed, float *norms, float *scal,
-                 uint32_t *amax, hipStream_t stream);
+                 uint32_t *amax, const int32_t *rmap, hipStream_t stream);
 int lowp_screen(const KnnPlan &p, const scr::ScreenArgs &a, unsigned gx, hipStream_t s);
 // FP8 residual variant: partitions, residual scales and the partition-ordered
 // packing (into b.packed / b.norms, with b.map and b.blk_part); then, after
 // the screen, the candidates' packed rows turned back into row ids.
 int lowp_prepare_resid(const KnnPlan &p, const float *R, const KnnBuffers &b, hipStream_t stream);
 int lowp_unmap(const KnnPlan &p, const KnnBuffers &b, hipStream_t stream);
+// Candidates from packed slots to rows through the packing's row map.
+int lowp_unmap_rows(const KnnPlan &p, const KnnBuffers &b, const int32_t *rmap, hipStream_t stream);
 
 // Spatial order of query rows (query_order.hip): perm = the rows sorted by a
 // Morton code of their first three coordinates.

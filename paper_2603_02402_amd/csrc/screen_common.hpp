@@ -68,6 +68,8 @@ struct ScreenArgs {
     int64_t nblk;
     int d;
     int P;                  // reference ranges (gridDim.y)
+    int rotate;             // reduced-precision screens on one matrix whose references are packed in the
+                            // queries' order: each query group starts its scan at its own block
     int32_t *cand_idx;
     float *cand_key;
 };
