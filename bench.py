@@ -242,7 +242,7 @@ def timed_form(rsc, Xt, k, precision, steps, warmup, ws, out, fp8_residual=0, ke
 
 
 def precision_forms(args, rsc) -> dict:
-    """The precision workload (n = 2M): plain exact FP32 (the judge of recall),
+    """The precision workload (n = 2M): plain exact FP32 (what recall is measured against),
     BF16 + rerank and FP8-e4m3 + rerank, each timed as a whole graph step."""
     import torch
 
@@ -843,8 +843,8 @@ def routed_form(args, rsc) -> dict:
             kern[name] = round(tot / args.form_steps, 3)
 
     routed_idx = idx.clone()
-    # the judge: plain exact FP32 kNN + connectivities of all n cells, timed once
-    log("[bench] routed form: exact search of every cell (the judge of recall)")
+    # the reference for recall: plain exact FP32 kNN + connectivities of all n cells, timed once
+    log("[bench] routed form: exact search of every cell (the reference for recall)")
     ews = rsc.Workspace(dev)
     ews.get(rsc.knn_workspace_bytes(n, n, d, k))
     torch.cuda.synchronize()
