@@ -763,7 +763,7 @@ def routed_form(args, rsc) -> dict:
 
     The index (partitions, labels, training) is built once and timed on its
     own; a timed step is the routed kNN of every base cell plus the
-    connectivities.  Recall@15 is judged against the exact path on sampled
+    connectivities.  Recall@15 is measured against the exact path on sampled
     rows, and nearest-centroid probing with the same probe count is measured
     beside it (the method without the router)."""
     import torch
@@ -917,7 +917,7 @@ def routed_form(args, rsc) -> dict:
     return {"workload": f"base n={n}, d=50, k=15, 500-cluster Zipf(1.1) mixture (centres seed 5, base seed 50), "
                         f"router trained on {args.routed_train} held-out cells (seed 51)",
             "cells_per_s": round(n / (ms / 1e3), 1), "ms_per_step": round(ms, 2), "kernel_ms_per_step": kern,
-            "recall@15": round(rec, 5), "meets_recall_0.99": rec >= 0.99, "recall_judged_on": f"all {n} cells",
+            "recall@15": round(rec, 5), "meets_recall_0.99": rec >= 0.99, "recall_measured_on": f"all {n} cells",
             "plain_exact_same_workload": {"cells_per_s": round(n / (ms_exact / 1e3), 1),
                                           "ms_per_step": round(ms_exact, 1), "nnz": int(g_exact.nnz),
                                           "escalated_rows": exact_stats["escalated_rows"],

@@ -92,7 +92,7 @@ typedef enum { RSC_EUCLIDEAN = 0, RSC_COSINE = 1 } rsc_metric;
  *                            scaling (s_t = max|y_t| / 448), FP32 accumulation.
  *              The reduced-precision forms keep the `screen` (default 64)
  *              smallest screened keys per query and re-rank them with float64
- *              distances; they are approximate (no certificate): judge them
+ *              distances; they are approximate (no certificate): measure them
  *              by recall@k.
  *   screen     candidates kept per query and reference range: 32 or 64 for
  *              RSC_FP32 (must exceed k when k < 64; 64 for larger k, where

@@ -7,7 +7,7 @@
 // per contraction half), which are then re-ranked with float64 distances of
 // the original float32 data by the same rerank kernel as the exact path.
 // No certificate is attempted: the result is approximate by design and is
-// judged by recall@k and distance error against exact search.
+// measured by recall@k and distance error against exact search.
 //
 // Keys are ||y~||^2 - 2 x~ . y~ where y~, x~ are the rounded vectors, so the
 // screen ranks by the exact distance between the rounded points:

@@ -1,7 +1,7 @@
 """FP8 residual variant of the precision form (rsc_knn_opts.fp8_residual):
 the references are coded as residuals against k-means partition centroids
 and each query against every partition it meets.  Approximate by design:
-judged by recall@15 against the float64 oracle, with the returned distances
+measured by recall@15 against the float64 oracle, with the returned distances
 the exact float64 ones of the returned pairs; the plain FP8 coding of the
 same rows is measured beside it."""
 

@@ -1,6 +1,6 @@
 """Precision form: BF16 / FP8-e4m3 screens with float64 rerank (approximate).
 
-Judged by recall@15 and distance error against the FP64 oracle (the
+Measured by recall@15 and distance error against the FP64 oracle (the
 bar for this form is recall@15 >= 0.99 for BF16; the FP8 form
 with per-dimension absmax scaling is held to its measured recall less a
 margin: 1.0 on the 10k workload, 0.50 on the 2M one).

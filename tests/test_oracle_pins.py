@@ -93,7 +93,7 @@ def test_knn_rectangular(oracle_mod):
 
 
 def test_pair_d2_matches_cdist(oracle_mod):
-    # the exact squared distances the precision tests judge with: scipy's
+    # the exact squared distances the precision tests measure with: scipy's
     # float64 cdist on random pairs, including i == j and repeated pairs
     rng = np.random.default_rng(31)
     for n, d in [(50, 1), (300, 7), (1000, 50), (64, 129)]:
