@@ -128,6 +128,33 @@ def test_end_to_end_10k(rsc, oracle_mod):
     log(f"[graph parity] end-to-end 10k: knn {res['exact_rows']} exact rows, weight rel max {rel:.2e}")
 
 
+@pytest.mark.parametrize("n", [1, 7, 300])
+def test_k1_lists_have_no_edges(rsc, oracle_mod, n):
+    """k = 1: every list holds only the row itself, so the graph is empty and rho = sigma = 0."""
+    idx = np.arange(n, dtype=np.int32).reshape(n, 1)
+    dist = np.zeros((n, 1), dtype=np.float32)
+    gp, _, _ = check_conn_on_lists(rsc, oracle_mod, idx, dist, "k=1 lists")
+    assert gp[-1] == 0
+
+
+@pytest.mark.parametrize("n,k", [(1, 1), (2, 2), (3, 2), (3, 3), (16, 15), (40, 33)])
+def test_end_to_end_few_cells(rsc, oracle_mod, n, k):
+    """kNN + connectivities of a handful of cells (k up to n) against the oracle's whole step."""
+    import torch
+
+    X = synth.mixture(n, d=50, n_clusters=2, seed=1000 + 10 * n + k)
+    log(f"[graph parity] end-to-end n={n} k={k}")
+    idx, dist, g = rsc.knn_graph(torch.from_numpy(X).cuda(), k)
+    torch.cuda.synchronize()
+    o = oracle_mod.knn_graph(X, k)
+    res = compare_knn(X, np.arange(n), idx.cpu().numpy(), dist.cpu().numpy(), o["idx"], o["dist"], oracle_mod, k)
+    rel = compare_csr((g.indptr.cpu().numpy(), g.indices.cpu().numpy(), g.data.cpu().numpy()),
+                      (o["indptr"], o["indices"], o["data"]), tie_rows=res["tie_row_ids"])
+    log(f"  knn {res['exact_rows']} exact rows, nnz {int(o['indptr'][-1])}, weight rel max {rel:.2e}")
+    if k == 1:
+        assert int(g.indptr.cpu().numpy()[-1]) == 0
+
+
 def test_synthetic_lists_1m(rsc, oracle_mod):
     """Graph stage at the 1M-cell scale on seeded kNN-shaped lists, full parity."""
     n, k = 1_000_000, 15
