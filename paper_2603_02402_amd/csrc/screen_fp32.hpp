@@ -19,6 +19,14 @@ __host__ __device__ constexpr int screen_min_waves(int DH, int L) {
     return (DH <= 25 && L == 16) ? 3 : DH <= 64 ? 2 : 1;
 }
 
+// Occupancy target of the grid-mapped screen (one tile per workgroup, no
+// persistent state): 4 waves per SIMD for the d <= 50 lists of 16, whose
+// block loop fits 128 registers (the few values the compiler spills are
+// addresses used before the loop).
+__host__ __device__ constexpr int plain_screen_waves(int DH, int L) {
+    return (DH <= 25 && L == 16) ? 4 : screen_min_waves(DH, L);
+}
+
 // Load float4 group s4 of a packed block (wave-uniform base wb).  A partial
 // last group (STEPS not a multiple of 4) is fetched with a narrower load so
 // that no dead register half is left pending under a load.
