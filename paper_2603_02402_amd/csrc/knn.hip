@@ -210,7 +210,7 @@ __global__ void k_init_counters(KnnCounters *c) {
 // of range p (index -1 / key +inf where fewer than L were seen).
 // ---------------------------------------------------------------------------
 template <int DH, int L>
-__global__ __launch_bounds__(256, plain_screen_waves(DH, L)) void k_screen_fp32(ScreenArgs a) {
+__global__ __launch_bounds__(256, tile_screen_waves(DH, L)) void k_screen_fp32(ScreenArgs a) {
     // Per-lane queue of keys that beat the lane's threshold (see LaneTopK).
     __shared__ float2 qbuf[kQueueCap * 256];
     constexpr int QG = kScreenWaves * 32;

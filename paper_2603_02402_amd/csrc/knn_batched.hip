@@ -58,7 +58,7 @@ struct BatchArgs {
 };
 
 template <int DH, int L>
-__global__ __launch_bounds__(256, screen_min_waves(DH, L)) void k_screen_batched(BatchArgs ba) {
+__global__ __launch_bounds__(256, tile_screen_waves(DH, L)) void k_screen_batched(BatchArgs ba) {
     __shared__ float2 qbuf[kQueueCap * 256];
     __shared__ int item_sh;
     const int tid = threadIdx.x;
@@ -258,7 +258,7 @@ int device_slots(int dh) {
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
             cus = 256;
     }
-    return cus * screen_min_waves(dh, 16);
+    return cus * tile_screen_waves(dh, 16);
 }
 
 template <int DH>

@@ -19,11 +19,11 @@ __host__ __device__ constexpr int screen_min_waves(int DH, int L) {
     return (DH <= 25 && L == 16) ? 3 : DH <= 64 ? 2 : 1;
 }
 
-// Occupancy target of the grid-mapped screen (one tile per workgroup, no
-// persistent state): 4 waves per SIMD for the d <= 50 lists of 16, whose
-// block loop fits 128 registers (the few values the compiler spills are
-// addresses used before the loop).
-__host__ __device__ constexpr int plain_screen_waves(int DH, int L) {
+// Occupancy target of the launches that run the tile code alone (the
+// grid-mapped screen and the persistent batched one): 4 waves per SIMD for
+// the d <= 50 lists of 16, whose block loop fits 128 registers (the few
+// values the compiler spills are addresses used outside the loop).
+__host__ __device__ constexpr int tile_screen_waves(int DH, int L) {
     return (DH <= 25 && L == 16) ? 4 : screen_min_waves(DH, L);
 }
 
