@@ -18,32 +18,14 @@
 #include <algorithm>
 #include <cstdint>
 
+#include "morton.hpp"
 #include "rsc_internal.hpp"
 
 namespace rsc {
 namespace {
 
 constexpr int kOrderDims = 3;
-constexpr int kOrderBits = 10;  // per coordinate: 30-bit keys
-
-// float bits mapped to unsigned integers of the same order
-__device__ __forceinline__ uint32_t ordered_bits(float x) {
-    const uint32_t b = __float_as_uint(x);
-    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
-}
-__device__ __forceinline__ float from_ordered(uint32_t u) {
-    return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
-}
-
-// 10 bits spread to every third bit position
-__device__ __forceinline__ uint32_t spread3(uint32_t v) {
-    v &= 0x3ffu;
-    v = (v | (v << 16)) & 0x030000ffu;
-    v = (v | (v << 8)) & 0x0300f00fu;
-    v = (v | (v << 4)) & 0x030c30c3u;
-    v = (v | (v << 2)) & 0x09249249u;
-    return v;
-}
+constexpr int kOrderBits = 10;  // per coordinate (quantise10): 30-bit keys
 
 __global__ void k_qo_init(uint32_t *bounds) {
     if (threadIdx.x < kOrderDims) {
@@ -90,8 +72,7 @@ __global__ __launch_bounds__(256) void k_qo_keys(const float *__restrict__ Q, in
         if (t < D) {
             const float a = from_ordered(bounds[2 * t]), b = from_ordered(bounds[2 * t + 1]);
             lo[t] = a;
-            const float span = b - a;
-            scale[t] = span > 0.f && isfinite(span) ? (float)((1 << kOrderBits) - 1) / span : 0.f;
+            scale[t] = scale10(a, b);
         }
     }
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nq; i += (int64_t)gridDim.x * blockDim.x) {
@@ -99,9 +80,7 @@ __global__ __launch_bounds__(256) void k_qo_keys(const float *__restrict__ Q, in
 #pragma unroll
         for (int t = 0; t < kOrderDims; ++t) {
             if (t < D) {
-                float q = (Q[i * d + t] - lo[t]) * scale[t];
-                q = fminf(fmaxf(q, 0.f), (float)((1 << kOrderBits) - 1));  // also maps NaN to 0
-                k |= spread3((uint32_t)q) << (kOrderDims - 1 - t);
+                k |= spread3(quantise10(Q[i * d + t], lo[t], scale[t])) << (kOrderDims - 1 - t);
             }
         }
         key[i] = k;

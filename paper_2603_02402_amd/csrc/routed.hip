@@ -25,6 +25,7 @@
 #include <cmath>
 #include <string>
 
+#include "morton.hpp"
 #include "rsc_internal.hpp"
 #include "screen_common.hpp"
 #include "screen_fp32.hpp"
@@ -312,30 +313,53 @@ __global__ __launch_bounds__(256) void k_fill_conf(int64_t n, const uint8_t *__r
     }
 }
 
-// Order the probed queries of each partition by their second and third
-// probes (then by row), so that the 32 queries of a tile probe nearly the
-// same partitions and their union stays small.  One workgroup per
-// partition, bitonic sort in LDS; a partition with more than kSegSort
-// probed queries keeps its fill order.
+// Order the probed queries of each partition along a Morton (Z-order)
+// curve of their first three coordinates, each quantised to 10 bits over the
+// bounding box of the partition's probed queries (then by row): the 32
+// queries of a tile then lie close together, probe nearly the same
+// partitions, and their union stays small.  One workgroup per partition,
+// bitonic sort in LDS; a partition with more than kSegSort probed queries
+// keeps its fill order.
 constexpr int kSegSort = 4096;
 
-__global__ __launch_bounds__(1024) void k_order_tiles(const int32_t *__restrict__ probe_parts, int np, int P,
+__global__ __launch_bounds__(1024) void k_order_tiles(const float *__restrict__ X, int d,
                                                       const int64_t *__restrict__ coff,
                                                       const int32_t *__restrict__ ccount,
                                                       int32_t *__restrict__ qperm) {
     __shared__ int2 e[kSegSort];  // (key, row)
+    __shared__ uint32_t lo[3], hi[3];  // the box, as ordered bits
     const int p = blockIdx.x;
     const int c = ccount[p];
     if (c <= kTileQ || c > kSegSort) return;
     const int64_t base = coff[p];
     int n2 = kTileQ;
     while (n2 < c) n2 <<= 1;
+    const int D = d < 3 ? d : 3;
+    if (threadIdx.x < 3) {
+        lo[threadIdx.x] = 0xffffffffu;
+        hi[threadIdx.x] = 0u;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < c; i += blockDim.x) {
+        const int64_t row = qperm[base + i];
+        for (int t = 0; t < D; ++t) {
+            const uint32_t u = ordered_bits(X[row * d + t]);
+            atomicMin(&lo[t], u);
+            atomicMax(&hi[t], u);
+        }
+    }
+    __syncthreads();
+    float x0[3], sc[3];
+    for (int t = 0; t < 3; ++t) {
+        x0[t] = t < D ? from_ordered(lo[t]) : 0.f;
+        sc[t] = t < D ? scale10(x0[t], from_ordered(hi[t])) : 0.f;
+    }
     for (int i = threadIdx.x; i < n2; i += blockDim.x) {
         if (i < c) {
             const int32_t row = qperm[base + i];
-            const int32_t *pr = probe_parts + (int64_t)row * np;
-            const int k1 = np > 1 ? pr[1] + 1 : 0, k2 = np > 2 ? pr[2] + 1 : 0;  // -1 entries -> 0
-            e[i] = make_int2(k1 * (P + 1) + k2, row);
+            uint32_t key = 0;
+            for (int t = 0; t < D; ++t) key |= spread3(quantise10(X[(int64_t)row * d + t], x0[t], sc[t])) << (2 - t);
+            e[i] = make_int2((int)key, row);
         } else {
             e[i] = make_int2(INT_MAX, INT_MAX);
         }
@@ -607,8 +631,7 @@ int probed_run(const float *X, int64_t n, int d, int k, const int64_t *offsets, 
                            &b.rc->ntiles, &b.rc->bad);
         hipLaunchKernelGGL(k_fill_conf, dim3(grid_for(n)), dim3(256), 0, s, n, b.route, b.own, b.coff, b.cursor,
                            b.qperm);
-        hipLaunchKernelGGL(k_order_tiles, dim3(P), dim3(1024), 0, s, probe_parts, probes, P, b.coff, b.ccount,
-                           b.qperm);
+        hipLaunchKernelGGL(k_order_tiles, dim3(P), dim3(1024), 0, s, X, d, b.coff, b.ccount, b.qperm);
         hipLaunchKernelGGL(k_fill_tiles, dim3(grid_for(P)), dim3(256), 0, s, P, b.ccount, b.coff, b.toff, b.tiles);
         if ((st = launch_status("probed lists")) != RSC_OK) return st;
     }
