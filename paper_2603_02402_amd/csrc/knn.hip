@@ -209,8 +209,8 @@ __global__ void k_init_counters(KnnCounters *c) {
 // Output: cand[(slot * 2P + 2p + h) * L + i], i-th smallest key of half h
 // of range p (index -1 / key +inf where fewer than L were seen).
 // ---------------------------------------------------------------------------
-template <int DH, int L>
-__global__ __launch_bounds__(256, tile_screen_waves(DH, L)) void k_screen_fp32(ScreenArgs a) {
+template <int DH, int L, int W>
+__global__ __launch_bounds__(256, W) void k_screen_fp32(ScreenArgs a) {
     // Per-lane queue of keys that beat the lane's threshold (see LaneTopK).
     __shared__ float2 qbuf[kQueueCap * 256];
     constexpr int QG = kScreenWaves * 32;
@@ -579,33 +579,39 @@ __global__ __launch_bounds__(64) void k_rescan(const float *__restrict__ Q, cons
 // Registers per lane of the running top-m list.
 int topm_regs(int m) { return m <= 64 ? 1 : m <= 128 ? 2 : 4; }
 
+// sparse: a grid with few active workgroups (the escalation)
 template <int DH, int L>
-int launch_screen(const ScreenArgs &a, unsigned gx, const char *name, hipStream_t stream) {
+int launch_screen(const ScreenArgs &a, unsigned gx, bool sparse, const char *name, hipStream_t stream) {
     ScopedTimer timer(name, stream);
-    hipLaunchKernelGGL((k_screen_fp32<DH, L>), dim3(gx, (unsigned)a.P), dim3(256), 0, stream, a);
+    constexpr int WF = tile_screen_waves(DH, L), WS = screen_min_waves(DH, L);
+    if (sparse && WS != WF)
+        hipLaunchKernelGGL((k_screen_fp32<DH, L, WS>), dim3(gx, (unsigned)a.P), dim3(256), 0, stream, a);
+    else
+        hipLaunchKernelGGL((k_screen_fp32<DH, L, WF>), dim3(gx, (unsigned)a.P), dim3(256), 0, stream, a);
     return launch_status(name);
 }
 
 template <int L>
-int dispatch_screen(int dh, const ScreenArgs &a, unsigned gx, const char *name, hipStream_t s) {
+int dispatch_screen(int dh, const ScreenArgs &a, unsigned gx, bool sparse, const char *name, hipStream_t s) {
     switch (dh) {
-        case 4: return launch_screen<4, L>(a, gx, name, s);
-        case 8: return launch_screen<8, L>(a, gx, name, s);
-        case 16: return launch_screen<16, L>(a, gx, name, s);
-        case 25: return launch_screen<25, L>(a, gx, name, s);
-        case 32: return launch_screen<32, L>(a, gx, name, s);
-        case 48: return launch_screen<48, L>(a, gx, name, s);
-        case 64: return launch_screen<64, L>(a, gx, name, s);
-        case 96: return launch_screen<96, L>(a, gx, name, s);
-        case 128: return launch_screen<128, L>(a, gx, name, s);
+        case 4: return launch_screen<4, L>(a, gx, sparse, name, s);
+        case 8: return launch_screen<8, L>(a, gx, sparse, name, s);
+        case 16: return launch_screen<16, L>(a, gx, sparse, name, s);
+        case 25: return launch_screen<25, L>(a, gx, sparse, name, s);
+        case 32: return launch_screen<32, L>(a, gx, sparse, name, s);
+        case 48: return launch_screen<48, L>(a, gx, sparse, name, s);
+        case 64: return launch_screen<64, L>(a, gx, sparse, name, s);
+        case 96: return launch_screen<96, L>(a, gx, sparse, name, s);
+        case 128: return launch_screen<128, L>(a, gx, sparse, name, s);
         default: set_error("internal: no screen kernel for this dimension"); return RSC_ERR_UNSUPPORTED;
     }
 }
 
-// One launch of the screen; `half_width` is the list length per contraction half.
-int screen(int dh, const ScreenArgs &a, unsigned gx, int half_width, const char *name, hipStream_t s) {
-    if (half_width == 16) return dispatch_screen<16>(dh, a, gx, name, s);
-    return dispatch_screen<32>(dh, a, gx, name, s);
+// One launch of the screen; `half_width` is the list length per contraction
+// half; `sparse` marks a grid with few active workgroups.
+int screen(int dh, const ScreenArgs &a, unsigned gx, int half_width, bool sparse, const char *name, hipStream_t s) {
+    if (half_width == 16) return dispatch_screen<16>(dh, a, gx, sparse, name, s);
+    return dispatch_screen<32>(dh, a, gx, sparse, name, s);
 }
 
 constexpr int kQueriesPerGroup = kScreenWaves * 32;
@@ -675,7 +681,7 @@ size_t knn_packed_floats(int dh, int64_t nblk) { return (size_t)nblk * packed_s4
 
 int knn_launch_screen(int dh, const scr::ScreenArgs &a, unsigned gx, int half_width, const char *name,
                       hipStream_t s) {
-    return screen(dh, a, gx, half_width, name, s);
+    return screen(dh, a, gx, half_width, false, name, s);
 }
 
 int knn_launch_rerank(const RerankArgs &ra, int64_t slots, const char *name, hipStream_t stream) {
@@ -980,7 +986,7 @@ int knn_run(const KnnPlan &p, const float *Q, const float *R, int32_t *out_idx, 
     sa.cand_idx = b.cand_idx;
     sa.cand_key = b.cand_key;
     const unsigned gq = (unsigned)((p.nq + kQueriesPerGroup - 1) / kQueriesPerGroup);
-    if ((st = screen(p.dh, sa, gq, p.half, "screen_fp32", stream)) != RSC_OK) return st;
+    if ((st = screen(p.dh, sa, gq, p.half, false, "screen_fp32", stream)) != RSC_OK) return st;
 
     // Each (range, half) list is one candidate group of width `half`.
     RerankArgs ra{};
@@ -1019,7 +1025,7 @@ int knn_run(const KnnPlan &p, const float *Q, const float *R, int32_t *out_idx, 
     se.cand_idx = b.esc_idx;
     se.cand_key = b.esc_key;
     const unsigned ge = (unsigned)((esc_cap + kQueriesPerGroup - 1) / kQueriesPerGroup);
-    if ((st = screen(p.dh, se, ge, kEscalateWidth / 2, "screen_escalate", stream)) != RSC_OK) return st;
+    if ((st = screen(p.dh, se, ge, kEscalateWidth / 2, true, "screen_escalate", stream)) != RSC_OK) return st;
     RerankArgs re = ra;
     re.qlist = b.flag1;
     re.qcount = &b.counters->flagged;

@@ -19,12 +19,15 @@ __host__ __device__ constexpr int screen_min_waves(int DH, int L) {
     return (DH <= 25 && L == 16) ? 3 : DH <= 64 ? 2 : 1;
 }
 
-// Occupancy target of the launches that run the tile code alone (the
-// grid-mapped screen and the persistent batched one): 4 waves per SIMD for
-// the d <= 50 lists of 16, whose block loop fits 128 registers (the few
-// values the compiler spills are addresses used outside the loop).
+// Occupancy target of the launches that run the tile code alone over a
+// full grid (the grid-mapped screen and the persistent batched one): for
+// d <= 50, 4 waves per SIMD with lists of 16, whose block loop fits 128
+// registers (the few values the compiler spills are addresses used outside
+// the loop), and 3 with lists of 32 (167 registers, no spills).  A sparse
+// grid (the escalation's few rows) keeps screen_min_waves: built for more
+// resident waves, the chain hides less latency when a wave runs alone.
 __host__ __device__ constexpr int tile_screen_waves(int DH, int L) {
-    return (DH <= 25 && L == 16) ? 4 : screen_min_waves(DH, L);
+    return DH <= 25 ? (L == 16 ? 4 : 3) : screen_min_waves(DH, L);
 }
 
 // Load float4 group s4 of a packed block (wave-uniform base wb).  A partial
